@@ -1,0 +1,169 @@
+"""Seeded synthetic inputs for the generalized MBE-FCI hot path.
+
+This module only *builds inputs*: molecular-orbital integrals h_pq and (pq|rs)
+plus the orbital partition (occupied set O, reference space R, expansion space
+X, maximum order).  It holds none of the method's arithmetic (no determinant,
+CASCI or many-body-expansion code), so both the CPU oracle and the HIP path
+can consume it without sharing any of the method.
+
+Workloads (all FP64, chemist-order integrals, 0-based orbital indices):
+
+* ``hubbard8``   -- 1D Hubbard, 8 sites, open, t=1, U=2, half filling, empty
+  reference, full expansion to order 8 (the paper's Type-3 "vacuum"
+  reference, Eq. 3).
+* ``hubbard16``  -- 1D Hubbard, 16 sites, open, t=1, U=4, half filling; the
+  reference space is the 6 MOs nearest the Fermi level, expansion over the
+  other 10 MOs to order 4 (the paper's general reference/expansion split,
+  Eq. 1).
+* ``synthetic40`` -- molecular-like synthetic Hamiltonian, M=40, 12 electrons,
+  (6e,6o) reference, order-3 expansion over 34 MOs.
+* ``hubbard12``  -- 1D Hubbard, 12 sites, open, t=1, U=3, half filling, empty
+  reference, order 6 (used for the gradient / backward path).
+* ``cas14``      -- 8 synthetic CAS(14e,14o) instances, M=14, seeds 1..8, the
+  whole space active (11,778,624 determinants each: the size of the paper's
+  largest Hubbard CASCI).
+
+Hubbard MOs are the eigenvectors of the open-chain hopping matrix in closed
+form, phi_k(j) = sqrt(2/(N+1)) sin(pi j k/(N+1)), ordered by orbital energy
+-2t cos(pi k/(N+1)); the on-site U tensor is transformed to that basis.  The
+synthetic generator draws, from ``numpy.random.default_rng(seed)``: sorted
+diagonal orbital energies ~ U(-2, 1); symmetric off-diagonal h_pq ~
+N(0, 0.05 exp(-|p-q|/6)); 120 symmetric Cholesky-like vectors L^P with the same
+decay; and (pq|rs) = sum_P L^P_pq L^P_rs, which is 8-fold symmetric.
+"""
+from __future__ import annotations
+
+import dataclasses
+import hashlib
+import math
+
+import numpy as np
+
+__all__ = [
+    "Problem",
+    "hubbard_site",
+    "hubbard_mo",
+    "synthetic",
+    "problem",
+    "WORKLOADS",
+    "checksum",
+]
+
+
+@dataclasses.dataclass
+class Problem:
+    """One MBE-FCI problem statement: integrals plus the orbital partition."""
+
+    name: str
+    h1: np.ndarray          # [M, M] symmetric
+    eri: np.ndarray         # [M, M, M, M] chemist order (pq|rs)
+    e_const: float
+    occ: list               # doubly occupied orbitals of the reference determinant
+    ref: list               # reference space R (possibly empty)
+    exp: list               # expansion space X (disjoint from R)
+    max_order: int
+
+    @property
+    def norb(self) -> int:
+        return int(self.h1.shape[0])
+
+    @property
+    def nelec(self) -> int:
+        return 2 * len(self.occ)
+
+
+def hubbard_site(nsite: int, t: float, u: float):
+    """Site-basis integrals of the open 1D Hubbard chain."""
+    h = np.zeros((nsite, nsite))
+    for j in range(nsite - 1):
+        h[j, j + 1] = h[j + 1, j] = -t
+    g = np.zeros((nsite,) * 4)
+    for j in range(nsite):
+        g[j, j, j, j] = u
+    return h, g
+
+
+def hubbard_orbitals(nsite: int):
+    """Closed-form hopping eigenvectors: column k-1 is phi_k, k = 1..N."""
+    j = np.arange(1, nsite + 1, dtype=np.float64)[:, None]
+    k = np.arange(1, nsite + 1, dtype=np.float64)[None, :]
+    return math.sqrt(2.0 / (nsite + 1)) * np.sin(np.pi * j * k / (nsite + 1))
+
+
+def hubbard_mo(nsite: int, t: float, u: float):
+    """Hubbard integrals in the hopping-eigenvector (MO) basis."""
+    h_site, _ = hubbard_site(nsite, t, u)
+    c = hubbard_orbitals(nsite)
+    h = c.T @ h_site @ c
+    h = 0.5 * (h + h.T)
+    # (pq|rs) = U sum_j C_jp C_jq C_jr C_js
+    pair = np.einsum("jp,jq->jpq", c, c).reshape(nsite, nsite * nsite)
+    g = (u * pair.T @ pair).reshape((nsite,) * 4)
+    return h, g
+
+
+def synthetic(norb: int, seed: int, nchol: int = 120):
+    """Molecular-like synthetic integrals (see module docstring)."""
+    rng = np.random.default_rng(seed)
+    h = np.zeros((norb, norb))
+    h[np.diag_indices(norb)] = np.sort(rng.uniform(-2.0, 1.0, norb))
+    iu = np.triu_indices(norb, 1)
+    sd = 0.05 * np.exp(-np.abs(iu[0] - iu[1]) / 6.0)
+    off = rng.standard_normal(len(sd)) * sd
+    h[iu] = off
+    h[(iu[1], iu[0])] = off
+    iu0 = np.triu_indices(norb, 0)
+    sd0 = 0.05 * np.exp(-np.abs(iu0[0] - iu0[1]) / 6.0)
+    lmat = np.zeros((nchol, norb, norb))
+    for p in range(nchol):
+        v = rng.standard_normal(len(sd0)) * sd0
+        lmat[p][iu0] = v
+        lmat[p][(iu0[1], iu0[0])] = v
+    flat = lmat.reshape(nchol, norb * norb)
+    g = (flat.T @ flat).reshape((norb,) * 4)
+    return h, g
+
+
+def _hubbard_problem(name, nsite, u, ref, max_order):
+    h, g = hubbard_mo(nsite, 1.0, u)
+    occ = list(range(nsite // 2))
+    exp = [p for p in range(nsite) if p not in ref]
+    return Problem(name, h, g, 0.0, occ, list(ref), exp, max_order)
+
+
+def problem(name: str, instance: int = 0) -> Problem:
+    """Build one named workload (``instance`` selects the cas14 seed 1..8)."""
+    if name == "hubbard8":
+        return _hubbard_problem(name, 8, 2.0, [], 8)
+    if name == "hubbard16":
+        # 1-based MOs k = 6..11 are the 3 occupied + 3 virtual nearest the Fermi level
+        return _hubbard_problem(name, 16, 4.0, list(range(5, 11)), 4)
+    if name == "hubbard12":
+        return _hubbard_problem(name, 12, 3.0, [], 6)
+    if name == "synthetic40":
+        h, g = synthetic(40, 0)
+        occ = list(range(6))
+        ref = list(range(3, 9))
+        exp = [p for p in range(40) if p not in ref]
+        return Problem(name, h, g, 0.0, occ, ref, exp, 3)
+    if name == "cas14":
+        if not 0 <= instance < 8:
+            raise ValueError("cas14 has instances 0..7 (seeds 1..8)")
+        h, g = synthetic(14, instance + 1)
+        occ = list(range(7))
+        return Problem(f"cas14[{instance}]", h, g, 0.0, occ, list(range(14)), [], 0)
+    if name.startswith("hubbard") and name[7:].isdigit():
+        n = int(name[7:])
+        return _hubbard_problem(name, n, 2.0, [], n)
+    raise KeyError(name)
+
+
+WORKLOADS = ("hubbard8", "hubbard16", "synthetic40", "hubbard12", "cas14")
+
+
+def checksum(*arrays) -> str:
+    """SHA-256 over the raw little-endian bytes of the given arrays."""
+    m = hashlib.sha256()
+    for a in arrays:
+        m.update(np.ascontiguousarray(a, dtype=np.float64).tobytes())
+    return m.hexdigest()
