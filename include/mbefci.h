@@ -1,0 +1,174 @@
+/*
+ * mbefci.h -- C ABI of the MI355X (gfx950) generalized MBE-FCI hot path.
+ *
+ * The method (Eriksen & Gauss, "Generalized Many-Body Expanded Full
+ * Configuration Interaction Theory", arXiv:1910.03527): the MOs are split into
+ * a reference space R and an expansion space X (orbitals of either occupancy).
+ * For every tuple T of 1..k expansion orbitals one CASCI is solved in the
+ * active space R u T; with eps_T = E_CASCI(R u T) - E_ref the increments obey
+ * the recursion of Eq. 2, the order sums E^(n) add the increments of order n,
+ * and E_FCI ~ E_ref + sum_n E^(n) (Eq. 1; Eq. 3 for an empty R).
+ *
+ * Conventions for every call:
+ *  - Energies in hartree, FP64.  Orbital indices 0-based.  Arrays row-major.
+ *    Two-electron integrals (pq|rs) in chemist order, [M][M][M][M], with the
+ *    8-fold permutational symmetry of real orbitals.
+ *  - "device" pointers are HIP device memory of the context's device (torch
+ *    tensors' data_ptr() work); "host" pointers are ordinary host memory.
+ *  - The caller owns every input and output buffer.  The library owns the
+ *    context, its cached string/link tables, plans, graphs and workspaces
+ *    (hipMalloc'd, grown on demand, freed by mbefci_destroy).
+ *  - hip_stream: the caller's stream (NULL = legacy default stream).  The
+ *    library orders its own stream after all work already queued on it and
+ *    makes it wait for the library's work before returning; calls that write
+ *    host outputs return only when those outputs are valid.
+ *  - Return value: MBEFCI_OK or a negative error code; on error no output is
+ *    written and mbefci_last_error(ctx) describes the failure.  No C++
+ *    exception crosses this boundary.
+ *  - A CASCI here means: the lowest eigenvalue in the S_z sector with the
+ *    given alpha/beta electron counts of the full-space Hamiltonian restricted
+ *    to determinants whose frozen orbitals (reference-determinant occupied
+ *    orbitals outside the active space) are doubly occupied and whose other
+ *    inactive orbitals are empty.
+ *  - Same inputs on the same device give bitwise identical outputs (fixed
+ *    reduction orders, no floating-point atomics).
+ */
+#ifndef MBEFCI_H
+#define MBEFCI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MBEFCI_OK = 0,
+  MBEFCI_EINVAL = -1,      /* invalid argument (sizes, indices, symmetry, NaN) */
+  MBEFCI_ENOMEM = -2,      /* device allocation failed or workspace cap exceeded */
+  MBEFCI_ENOTCONV = -3,    /* a Davidson solve hit max_iter; see stats */
+  MBEFCI_EDEVICE = -4,     /* HIP runtime error */
+  MBEFCI_EUNSUPPORTED = -5 /* shape outside the compiled kernels (active n > 14) */
+};
+
+enum { MBEFCI_BATCHED = 0, MBEFCI_PER_LAUNCH = 1 };
+
+typedef struct mbefci_ctx mbefci_ctx;
+
+typedef struct {
+  double conv_tol;       /* Davidson residual 2-norm tolerance (default 1e-6)       */
+  int32_t max_iter;      /* Davidson iterations per CASCI (default 200)              */
+  int32_t max_space;     /* subspace size before restart, 2..16 (default 16)        */
+  int32_t nguess;        /* lowest-diagonal unit guess vectors, 1..8 (default 4)    */
+  int32_t mode;          /* MBEFCI_BATCHED (default) or MBEFCI_PER_LAUNCH            */
+  int32_t use_graph;     /* batched mode: replay captured iterations (default 1)     */
+  int32_t tile;          /* sigma tile width 32/64/128, 0 = autotuned (default 0)    */
+  int32_t keep_ci;       /* keep converged CI vectors for the backward (default 1)   */
+  int32_t validate;      /* host checks of integral symmetry/finiteness (default 1)  */
+  int64_t max_workspace; /* workspace cap in bytes, 0 = no cap                       */
+  const char* tune_cache;/* autotuner cache file (read/written) or NULL              */
+} mbefci_opts;
+
+typedef struct {
+  int32_t norb;            /* M (1..64)                                              */
+  const double* h1;        /* device [M*M], symmetric                                */
+  const double* eri;       /* device [M^4], (pq|rs), 8-fold symmetric                */
+  double e_const;          /* constant energy shift                                  */
+  int32_t nocc;            /* number of doubly occupied orbitals of the reference    */
+  const int32_t* occ;      /* host [nocc]: those orbitals (the set O)                */
+  int32_t nref;            /* |R| (may be 0: the vacuum reference of Eq. 3)          */
+  const int32_t* ref;      /* host [nref]: reference space R                         */
+  int32_t nexp;            /* |X|                                                    */
+  const int32_t* exp;      /* host [nexp]: expansion space X, disjoint from R        */
+  int32_t max_order;       /* k, 0..nexp (0: only the reference CASCI)               */
+} mbefci_problem;
+
+typedef struct {
+  int64_t ntuples;           /* CASCIs solved, the reference CASCI included       */
+  int64_t nsingle;           /* of which single-determinant (no eigen-solve)      */
+  int64_t sigma_calls;       /* sigma = Hc evaluations summed over CASCIs         */
+  int64_t ndet_total;        /* sum of determinant counts                         */
+  int32_t max_iters;         /* largest Davidson iteration count                  */
+  int32_t first_failed;      /* first CASCI index that did not converge, or -1    */
+  int32_t nbuckets;          /* shape buckets                                     */
+  int32_t graph_launches;    /* replays of the captured iteration graph           */
+  double ms_total;           /* wall time of the call (host clock)                */
+  double ms_solve;           /* device time of the Davidson phase (HIP events)    */
+} mbefci_stats;
+
+/* ---- context ------------------------------------------------------------ */
+void mbefci_default_opts(mbefci_opts* opts);
+/* Create a context on HIP device `device`.  opts == NULL takes the defaults. */
+int mbefci_create(int device, const mbefci_opts* opts, mbefci_ctx** out);
+void mbefci_destroy(mbefci_ctx* ctx);
+/* Message of the last failure on ctx (valid until the next call on ctx). */
+const char* mbefci_last_error(const mbefci_ctx* ctx);
+int mbefci_set_opts(mbefci_ctx* ctx, const mbefci_opts* opts);
+
+/* ---- integer layer: strings and single-excitation link tables ------------
+ * A string of nelec electrons in norb active orbitals is a bitmask; strings
+ * are numbered in ascending integer order (address = sum_j C(o_j, j) over the
+ * occupied orbitals o_1 < o_2 < ..., the combinatorial number system).  The
+ * determinant with alpha string Ia and beta string Ib has address
+ * Ia * N_beta + Ib.  These tables are the integer backbone of every CASCI
+ * solve (the constituent CASCI calculations of Eq. 1). */
+int64_t mbefci_num_strings(int32_t norb, int32_t nelec);     /* C(norb, nelec) */
+int32_t mbefci_num_links(int32_t norb, int32_t nelec);       /* nelec*(norb-nelec+1) */
+/* out: device [nstr] uint64 bitmasks. */
+int mbefci_strings(mbefci_ctx* ctx, int32_t norb, int32_t nelec, uint64_t* out, void* hip_stream);
+/* out: device [nstr][nlink][4] int32 = (p, q, J, sign) with E_pq|I> = sign|J>,
+ * E_pq = a+_p a_q of one spin.  Per string: the diagonal entries (o,o,I,+1)
+ * for occupied o ascending, then for occupied q ascending and empty p
+ * ascending; sign = (-1)^(occupied orbitals strictly between p and q). */
+int mbefci_link_table(mbefci_ctx* ctx, int32_t norb, int32_t nelec, int32_t* out, void* hip_stream);
+/* Number of tuples of 1..max_order orbitals out of nexp: sum_n C(nexp, n). */
+int64_t mbefci_num_tuples(int32_t nexp, int32_t max_order);
+
+/* ---- one CASCI Hamiltonian in an active space ---------------------------
+ * h1 device [n*n], eri device [n^4] (active-space integrals), e_core the
+ * constant added to every diagonal element.  Determinant layout [Na][Nb]. */
+/* diag: device [Na*Nb], H_II including e_core. */
+int mbefci_hdiag(mbefci_ctx* ctx, int32_t norb, int32_t nalpha, int32_t nbeta, const double* h1,
+                 const double* eri, double e_core, double* diag, void* hip_stream);
+/* sigma = H c (e_core included): c, sigma device [Na*Nb]. */
+int mbefci_sigma(mbefci_ctx* ctx, int32_t norb, int32_t nalpha, int32_t nbeta, const double* h1,
+                 const double* eri, double e_core, const double* c, double* sigma,
+                 void* hip_stream);
+
+/* ---- batch of independent CASCIs of one shape ---------------------------
+ * nprob problems, each with its own integrals: h1s[i] device [n*n], eris[i]
+ * device [n^4] (host arrays of device pointers), e_core host [nprob].
+ * e_out host [nprob]: lowest eigenvalues.  ci_out: NULL or host array of
+ * nprob device pointers [Na*Nb] receiving the normalised eigenvectors. */
+int mbefci_casci(mbefci_ctx* ctx, int32_t nprob, int32_t norb, int32_t nalpha, int32_t nbeta,
+                 const double* const* h1s, const double* const* eris, const double* e_core,
+                 double* e_out, double* const* ci_out, mbefci_stats* stats, void* hip_stream);
+/* Spin-summed RDMs of the CI vectors kept by the last mbefci_casci on ctx:
+ * rdm1s[i] device [n*n] gamma_pq = <E_pq>, rdm2s[i] device [n^4]
+ * Gamma_pqrs = <E_pq E_rs> - delta_qr gamma_ps, symmetrised over the eight
+ * index permutations of (pq|rs) (the gradient convention: dE/dh = gamma,
+ * dE/d(pq|rs) = Gamma/2 for symmetric perturbations).  Either may be NULL. */
+int mbefci_casci_rdm(mbefci_ctx* ctx, double* const* rdm1s, double* const* rdm2s,
+                     void* hip_stream);
+
+/* ---- many-body expansion -------------------------------------------------
+ * Solves E_ref (CASCI of R) and the CASCI of R u T for every tuple T of
+ * 1..max_order expansion orbitals, then forms the increments of Eq. 2 and the
+ * order sums of Eq. 1.  Outputs (host): e_ref, e_order [max_order],
+ * e_total = e_ref + sum e_order, tuple_incr [num_tuples] or NULL (order by
+ * order, lexicographic tuples of the sorted X within an order).  Converged
+ * CI vectors are kept on ctx for mbefci_mbe_backward when keep_ci is set. */
+int mbefci_mbe_forward(mbefci_ctx* ctx, const mbefci_problem* prob, double* e_ref,
+                       double* e_order, double* e_total, double* tuple_incr, mbefci_stats* stats,
+                       void* hip_stream);
+/* Gradient of L = g[0] E_ref + sum_n g[n] E^(n) (g host [1+max_order]) of the
+ * last forward on ctx with respect to the MO integrals: d_h1 device [M*M]
+ * (symmetric) and d_eri device [M^4] (8-fold symmetrised); both overwritten. */
+int mbefci_mbe_backward(mbefci_ctx* ctx, const double* grad_out, double* d_h1, double* d_eri,
+                        void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MBEFCI_H */

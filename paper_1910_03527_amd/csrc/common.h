@@ -1,0 +1,103 @@
+// Shared internal definitions of the MBE-FCI HIP library (gfx950, FP64).
+//
+// Notation follows the paper (arXiv:1910.03527): M molecular orbitals, a
+// reference space R and an expansion space X; every tuple T of expansion
+// orbitals defines one CASCI in the active set A = R u T (Eq. 1, Eq. 2).
+// Inside one CASCI: n active orbitals, na/nb active alpha/beta electrons,
+// Na = C(n,na) alpha strings, Nb = C(n,nb) beta strings, determinant
+// address K = Ka*Nb + Kb, npair = n(n+1)/2 orbital pairs (a >= b).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mbefci {
+
+constexpr int kMaxActive = 16;          // active orbitals per CASCI
+constexpr int kMaxPair = kMaxActive * (kMaxActive + 1) / 2;
+constexpr int kMaxOrb = 64;             // orbitals of the whole problem
+constexpr int kMaxSpace = 16;           // Davidson subspace (+1 correction slot)
+constexpr int kBinom = 65;              // binomial table C(n,k), n,k < 65
+
+// packed single-excitation link: bits 0..21 string address J, bits 22..29
+// orbital-pair index pair(p,q) = max(p,q)*(max(p,q)+1)/2 + min(p,q),
+// bit 31 set when the sign is negative.
+__host__ __device__ inline uint32_t pack_link(int J, int pair, int sign) {
+  return (uint32_t)J | ((uint32_t)pair << 22) | (sign < 0 ? 0x80000000u : 0u);
+}
+__host__ __device__ inline int link_addr(uint32_t e) { return (int)(e & 0x3FFFFFu); }
+__host__ __device__ inline int link_pair(uint32_t e) { return (int)((e >> 22) & 0xFFu); }
+__host__ __device__ inline double link_sign(uint32_t e) { return (e & 0x80000000u) ? -1.0 : 1.0; }
+__host__ __device__ inline int pair_index(int p, int q) {
+  int a = p > q ? p : q, b = p > q ? q : p;
+  return a * (a + 1) / 2 + b;
+}
+
+// One CASCI problem inside a batch.
+struct Item {
+  int32_t n, na, nb, npair;
+  int32_t Na, Nb, La, Lb;
+  int64_t ndet;           // Na*Nb
+  int64_t off;            // offset of this item in every vector slot of the arenas
+  int64_t goff;           // offset of its G block [npair][ndet]
+  int64_t woff;           // offset of its W matrix [kpad][kpad] (row-major)
+  int32_t kpad;           // npair rounded up to a multiple of 16
+  int32_t ham;            // index of its ItemHam record
+  int32_t chunk0, nchunk; // partial-reduction chunks [chunk0, chunk0+nchunk)
+  int32_t shape;          // index of its string/link table set
+  int32_t pad_;
+  const uint32_t* linkA;  // [Na][La]
+  const uint32_t* linkB;  // [Nb][Lb]
+};
+
+// Active-space Hamiltonian of one CASCI after the frozen-core fold.
+struct ItemHam {
+  double ecore;                          // constant + frozen-core energy
+  double heff[kMaxActive * kMaxActive];  // h_eff_tu
+  double J[kMaxActive * kMaxActive];     // (tt|uu)
+  double K[kMaxActive * kMaxActive];     // (tu|ut)
+};
+
+// Per-item Davidson state (device resident).
+struct DavState {
+  int32_t m;          // current subspace size
+  int32_t conv;       // 1 once converged
+  int32_t iters;      // iterations taken
+  int32_t status;     // 0 ok, 1 not converged, 2 breakdown
+  int32_t nguess;     // number of guess vectors (slots 0..nguess-1)
+  int32_t pad_;
+  double theta;       // lowest Ritz value (active-space energy without ecore)
+  double rnorm;       // residual norm of the last Ritz vector
+  double tnorm2;      // squared norm of the correction vector
+  double y[kMaxSpace];
+  double coef[kMaxSpace + 1];
+  double Hs[kMaxSpace * kMaxSpace];
+};
+
+// One bucket of MBE tuples: every tuple of a given order with a given number
+// of occupied (reference-determinant) orbitals; all share one CASCI shape.
+struct BucketDev {
+  int32_t order, nocc;
+  int64_t item0, count;
+};
+
+// The orbital partition of an MBE problem for the device: the expansion space
+// split into its occupied part Xo and virtual part Xv (each sorted), the
+// reference space R and the occupied set O of the reference determinant.
+struct MbeSpaces {
+  int M, nocc_ref;  // nocc_ref = |O n R|
+  int nR, nXo, nXv, nO;
+  int R[kMaxOrb];
+  int Xo[kMaxOrb];
+  int Xv[kMaxOrb];
+  int O[kMaxOrb];
+};
+
+struct Work {     // one unit of a segmented launch: an item and a range
+  int32_t item;
+  int32_t begin;  // first tile / chunk
+  int32_t end;    // one past the last
+  int32_t pad_;
+};
+
+}  // namespace mbefci

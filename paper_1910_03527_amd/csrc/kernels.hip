@@ -1,0 +1,1182 @@
+// HIP kernels of the MBE-FCI hot path for gfx950 (CDNA4), all FP64.
+//
+// One translation unit holds every kernel so that the binomial table lives in
+// a single __constant__ object.  Launchers at the bottom are the only symbols
+// the host runtime calls (declared in launch.h).
+#include "common.h"
+#include "launch.h"
+
+namespace mbefci {
+
+// ----------------------------------------------------------------- binomials
+struct BinomTable {
+  int64_t v[kBinom][kBinom];
+};
+constexpr BinomTable make_binom() {
+  BinomTable t{};
+  for (int n = 0; n < kBinom; ++n) {
+    t.v[n][0] = 1;
+    for (int k = 1; k <= n; ++k) t.v[n][k] = t.v[n - 1][k - 1] + (k <= n - 1 ? t.v[n - 1][k] : 0);
+  }
+  return t;
+}
+__constant__ BinomTable c_binom = make_binom();
+
+__device__ inline int64_t binom(int n, int k) {
+  return (n < 0 || k < 0 || k > n) ? 0 : c_binom.v[n][k];
+}
+
+// Address of a string (bitmask, ascending-integer order of all strings with
+// the same popcount): combinatorial number system sum_j C(o_j, j), o_j the
+// j-th occupied orbital (1-based j) in ascending order.
+__device__ inline int64_t string_addr(uint64_t mask) {
+  int64_t a = 0;
+  int j = 1;
+  while (mask) {
+    int o = __builtin_ctzll(mask);
+    a += binom(o, j++);
+    mask &= mask - 1;
+  }
+  return a;
+}
+
+// Inverse of string_addr for strings of ne electrons.
+__device__ inline uint64_t string_unrank(int64_t r, int n, int ne) {
+  uint64_t mask = 0;
+  int o = n - 1;
+  for (int j = ne; j >= 1; --j) {
+    while (binom(o, j) > r) --o;
+    mask |= (uint64_t)1 << o;
+    r -= binom(o, j);
+    --o;
+  }
+  return mask;
+}
+
+// Lexicographic rank / unrank of a sorted k-combination of {0..N-1}.
+__device__ inline int64_t comb_lex_rank(const int* c, int k, int N) {
+  int64_t r = 0;
+  int prev = -1;
+  for (int i = 0; i < k; ++i) {
+    for (int j = prev + 1; j < c[i]; ++j) r += binom(N - 1 - j, k - 1 - i);
+    prev = c[i];
+  }
+  return r;
+}
+__device__ inline void comb_lex_unrank(int64_t r, int k, int N, int* c) {
+  int j = 0;
+  for (int i = 0; i < k; ++i) {
+    while (true) {
+      int64_t b = binom(N - 1 - j, k - 1 - i);
+      if (r < b) break;
+      r -= b;
+      ++j;
+    }
+    c[i] = j++;
+  }
+}
+
+// ------------------------------------------------- strings and link tables
+__global__ void k_strings(int n, int ne, int64_t N, uint64_t* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) out[i] = string_unrank(i, n, ne);
+}
+
+// One thread per string I: its single-excitation links E_pq|I> = s|J> in the
+// canonical order (diagonal entries first, then q in I ascending, p not in I
+// ascending).  The sign is (-1)^(number of occupied orbitals strictly between
+// p and q), the parity of a+_p a_q acting on the occupation-number vector.
+__global__ void k_links(int n, int ne, int64_t N, uint32_t* packed, int32_t* abi4) {
+  int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= N) return;
+  const int L = ne * (n - ne + 1);
+  uint64_t m = string_unrank(I, n, ne);
+  int idx = 0;
+  for (int o = 0; o < n; ++o)
+    if (m >> o & 1) {
+      if (packed) packed[I * L + idx] = pack_link((int)I, pair_index(o, o), 1);
+      if (abi4) {
+        int32_t* e = abi4 + (I * L + idx) * 4;
+        e[0] = o; e[1] = o; e[2] = (int32_t)I; e[3] = 1;
+      }
+      ++idx;
+    }
+  for (int q = 0; q < n; ++q) {
+    if (!(m >> q & 1)) continue;
+    for (int p = 0; p < n; ++p) {
+      if (m >> p & 1) continue;
+      uint64_t r = (m & ~((uint64_t)1 << q)) | ((uint64_t)1 << p);
+      int lo = p < q ? p : q, hi = p < q ? q : p;
+      uint64_t between = (((uint64_t)1 << hi) - 1) & ~((((uint64_t)1 << lo) << 1) - 1);
+      int sign = (__builtin_popcountll(m & between) & 1) ? -1 : 1;
+      int64_t J = string_addr(r);
+      if (packed) packed[I * L + idx] = pack_link((int)J, pair_index(p, q), sign);
+      if (abi4) {
+        int32_t* e = abi4 + (I * L + idx) * 4;
+        e[0] = p; e[1] = q; e[2] = (int32_t)J; e[3] = sign;
+      }
+      ++idx;
+    }
+  }
+}
+
+// ------------------------------------------------------- Hamiltonian set-up
+// Frozen-core fold of the full-space Hamiltonian onto the active set A of one
+// CASCI (frozen F = O \ A doubly occupied, all other orbitals deleted):
+//   E_core = e_const + sum_{i in F} 2 h_ii + sum_{i,j in F} [2(ii|jj) - (ij|ji)]
+//   h_eff_tu = h_tu + sum_{i in F} [2(tu|ii) - (ti|iu)]
+// and the pair-space contraction matrix used by sigma = H c:
+//   k_pq = h_eff_pq - 1/2 sum_{r in A} (pr|rq)
+//   W_{ab,cd} = 1/2 (ab|cd) + (k_ab d_cd + d_ab k_cd) / (2N),  a>=b, c>=d,
+// N = number of active electrons (the number operator acts as N on the CASCI
+// space, which folds the one-body term into the single contraction).
+struct ActiveSet {
+  int n, na;
+  int act[kMaxActive];
+  int nf;
+  int frz[kMaxOrb];
+};
+
+__device__ void build_item_hamiltonian(const ActiveSet& s, int M, const double* __restrict__ h1,
+                                       const double* __restrict__ eri, double e_const, int nel,
+                                       ItemHam* ham, double* W, int kpad) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int n = s.n;
+  __shared__ double s_red[256];
+  __shared__ double s_k[kMaxActive * kMaxActive];
+  auto G = [&](int p, int q, int r, int u) -> double {
+    return eri[(((size_t)p * M + q) * M + r) * M + u];
+  };
+  // frozen-core energy
+  double e = 0.0;
+  for (int x = t; x < s.nf * s.nf; x += nt) {
+    int i = s.frz[x / s.nf], j = s.frz[x % s.nf];
+    e += 2.0 * G(i, i, j, j) - G(i, j, j, i);
+  }
+  for (int x = t; x < s.nf; x += nt) e += 2.0 * h1[s.frz[x] * M + s.frz[x]];
+  s_red[t] = e;
+  __syncthreads();
+  for (int w = nt / 2; w > 0; w >>= 1) {
+    if (t < w) s_red[t] += s_red[t + w];
+    __syncthreads();
+  }
+  if (t == 0) ham->ecore = e_const + s_red[0];
+  // effective one-electron operator, Coulomb/exchange diagonals
+  for (int x = t; x < n * n; x += nt) {
+    int tt = x / n, uu = x % n;
+    int p = s.act[tt], q = s.act[uu];
+    double v = h1[p * M + q];
+    for (int f = 0; f < s.nf; ++f) {
+      int i = s.frz[f];
+      v += 2.0 * G(p, q, i, i) - G(p, i, i, q);
+    }
+    ham->heff[tt * kMaxActive + uu] = v;
+    ham->J[tt * kMaxActive + uu] = G(p, p, q, q);
+    ham->K[tt * kMaxActive + uu] = G(p, q, q, p);
+    double kv = v;
+    for (int r = 0; r < n; ++r) kv -= 0.5 * G(p, s.act[r], s.act[r], q);
+    s_k[tt * kMaxActive + uu] = kv;
+  }
+  __syncthreads();
+  if (W) {
+    const double inv2n = nel > 0 ? 0.5 / nel : 0.0;
+    const int npair = n * (n + 1) / 2;
+    for (int x = t; x < kpad * kpad; x += nt) {
+      int ab = x / kpad, cd = x % kpad;
+      double v = 0.0;
+      if (ab < npair && cd < npair) {
+        int a = 0;
+        while ((a + 1) * (a + 2) / 2 <= ab) ++a;
+        int b = ab - a * (a + 1) / 2;
+        int c = 0;
+        while ((c + 1) * (c + 2) / 2 <= cd) ++c;
+        int d = cd - c * (c + 1) / 2;
+        v = 0.5 * G(s.act[a], s.act[b], s.act[c], s.act[d]);
+        if (c == d) v += inv2n * s_k[a * kMaxActive + b];
+        if (a == b) v += inv2n * s_k[c * kMaxActive + d];
+      }
+      W[x] = v;
+    }
+  }
+}
+
+// One block per item: decode the tuple of bucket (order, nocc) from its index
+// (lexicographic ranks of its occupied and virtual parts), form A = R u T and
+// F = O \ A, and build the item's folded Hamiltonian and W.
+__global__ void k_mbe_setup(MbeSpaces sp, const BucketDev* __restrict__ buckets, int nbucket,
+                            const Item* __restrict__ items, const double* __restrict__ h1,
+                            const double* __restrict__ eri, double e_const, ItemHam* hams,
+                            double* warena, int32_t* tuple_pos, int max_order) {
+  const int it = blockIdx.x;
+  __shared__ ActiveSet s;
+  if (threadIdx.x == 0) {
+    int b = 0;
+    while (b + 1 < nbucket && buckets[b + 1].item0 <= it) ++b;
+    const BucketDev bk = buckets[b];
+    int64_t local = it - bk.item0;
+    int nv = bk.order - bk.nocc;
+    int64_t cv = binom(sp.nXv, nv);
+    int64_t ro = local / cv, rv = local % cv;
+    int co[kMaxActive], cvv[kMaxActive];
+    comb_lex_unrank(ro, bk.nocc, sp.nXo, co);
+    comb_lex_unrank(rv, nv, sp.nXv, cvv);
+    // active set: merge R, Xo[co], Xv[cvv] (all disjoint), sorted ascending
+    int tmp[kMaxActive];
+    int nt = 0;
+    for (int i = 0; i < sp.nR; ++i) tmp[nt++] = sp.R[i];
+    for (int i = 0; i < bk.nocc; ++i) tmp[nt++] = sp.Xo[co[i]];
+    for (int i = 0; i < nv; ++i) tmp[nt++] = sp.Xv[cvv[i]];
+    for (int i = 1; i < nt; ++i) {
+      int v = tmp[i], j = i - 1;
+      while (j >= 0 && tmp[j] > v) { tmp[j + 1] = tmp[j]; --j; }
+      tmp[j + 1] = v;
+    }
+    s.n = nt;
+    for (int i = 0; i < nt; ++i) s.act[i] = tmp[i];
+    s.nf = 0;
+    for (int i = 0; i < sp.nO; ++i) {
+      int o = sp.O[i];
+      bool in = false;
+      for (int j = 0; j < nt; ++j) in |= (tmp[j] == o);
+      if (!in) s.frz[s.nf++] = o;
+    }
+    s.na = sp.nocc_ref + bk.nocc;
+    if (tuple_pos) {
+      // positions: occupied part (indices into Xo), then virtual part (into Xv)
+      int32_t* tp = tuple_pos + (int64_t)it * (2 * max_order + 2);
+      tp[0] = bk.nocc;
+      tp[1] = nv;
+      for (int i = 0; i < bk.nocc; ++i) tp[2 + i] = co[i];
+      for (int i = 0; i < nv; ++i) tp[2 + bk.nocc + i] = cvv[i];
+    }
+  }
+  __syncthreads();
+  const Item& I = items[it];
+  build_item_hamiltonian(s, sp.M, h1, eri, e_const, I.na + I.nb, &hams[I.ham],
+                         I.ndet > 1 ? warena + I.woff : nullptr, I.kpad);
+}
+
+// Direct CASCI set-up: the whole given space is active (no frozen orbitals).
+__global__ void k_casci_setup(int n, const double* const* h1s, const double* const* eris,
+                              const double* ecores, const Item* __restrict__ items, ItemHam* hams,
+                              double* warena) {
+  const int it = blockIdx.x;
+  __shared__ ActiveSet s;
+  if (threadIdx.x == 0) {
+    s.n = n;
+    for (int i = 0; i < n; ++i) s.act[i] = i;
+    s.nf = 0;
+    s.na = items[it].na;
+  }
+  __syncthreads();
+  const Item& I = items[it];
+  build_item_hamiltonian(s, n, h1s[it], eris[it], ecores[it], I.na + I.nb, &hams[I.ham],
+                         I.ndet > 1 ? warena + I.woff : nullptr, I.kpad);
+}
+
+// --------------------------------------------------------------- diagonal
+// H_II - E_core = sum_{p in Ia u Ib} h_eff_pp + sum_{p<q in Ia} [(pp|qq)-(pq|qp)]
+//               + same for Ib + sum_{p in Ia, q in Ib} (pp|qq)
+__global__ void k_hdiag(const Item* __restrict__ items, const Work* __restrict__ work,
+                        const ItemHam* __restrict__ hams, double* diag) {
+  const Work wk = work[blockIdx.x];
+  const Item& I = items[wk.item];
+  const int64_t K = (int64_t)wk.begin * blockDim.x + threadIdx.x;
+  if (K >= I.ndet) return;
+  const ItemHam& H = hams[I.ham];
+  const int Ka = (int)(K / I.Nb), Kb = (int)(K % I.Nb);
+  uint64_t ma = string_unrank(Ka, I.n, I.na), mb = string_unrank(Kb, I.n, I.nb);
+  double e = 0.0;
+  for (uint64_t x = ma; x; x &= x - 1) {
+    int p = __builtin_ctzll(x);
+    e += H.heff[p * kMaxActive + p];
+    for (uint64_t y = x & (x - 1); y; y &= y - 1) {
+      int q = __builtin_ctzll(y);
+      e += H.J[p * kMaxActive + q] - H.K[p * kMaxActive + q];
+    }
+    for (uint64_t y = mb; y; y &= y - 1) e += H.J[p * kMaxActive + __builtin_ctzll(y)];
+  }
+  for (uint64_t x = mb; x; x &= x - 1) {
+    int p = __builtin_ctzll(x);
+    e += H.heff[p * kMaxActive + p];
+    for (uint64_t y = x & (x - 1); y; y &= y - 1) {
+      int q = __builtin_ctzll(y);
+      e += H.J[p * kMaxActive + q] - H.K[p * kMaxActive + q];
+    }
+  }
+  diag[I.off + K] = e;
+}
+
+// ------------------------------------------------------------------ sigma
+// sigma = (H - E_core) c by the Knowles-Handy / Olsen factorisation:
+//   D+_ab[K] = <K| E_ab + E_ba |c>   (a > b),   D+_aa[K] = <K|E_aa|c>
+//   G = W D+                          (the only dense step: FP64 MFMA)
+//   sigma_I = sum over links E_xy I = s K of s G_pair(x,y)[K]
+// Step 1+2 run fused in k_sigma_dgemm (D+ tile in LDS), step 3 in
+// k_sigma_gather.  Both read the vector slot given by `slot` (>= 0: fixed
+// slot, items with slot >= their guess count skip; -1: the item's newest).
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline int vec_slot(const DavState& st, int slot) {
+  return slot >= 0 ? slot : st.m - 1;
+}
+__device__ inline bool item_active(const DavState& st, int slot) {
+  if (st.conv) return false;
+  return slot < 0 || slot < st.nguess;
+}
+
+template <int NACT, int TN>
+__global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ items,
+                                                     const Work* __restrict__ work,
+                                                     const double* __restrict__ warena,
+                                                     const double* __restrict__ V, int64_t ntot,
+                                                     double* __restrict__ Garena,
+                                                     const DavState* __restrict__ st, int slot) {
+  constexpr int NP = NACT * (NACT + 1) / 2;
+  constexpr int KPAD = (NP + 15) / 16 * 16;
+  constexpr int KS = (NP + 3) / 4;       // MFMA k-steps (4 per step)
+  constexpr int NRB = KPAD / 16;         // 16-row blocks of G
+  constexpr int RBW = (NRB + 3) / 4;     // row blocks per wave
+  constexpr int NCB = TN / 16;           // 16-column blocks per tile
+  constexpr int NSUB = 256 / TN;
+  constexpr int LDT = TN + 1;            // padded LDS row (doubles)
+  __shared__ double Ds[KS * 4 * LDT];
+
+  const Work wk = work[blockIdx.x];
+  const Item& I = items[wk.item];
+  const DavState& S = st[wk.item];
+  if (!item_active(S, slot)) return;
+  const int vs = vec_slot(S, slot);
+  const double* __restrict__ c = V + (int64_t)vs * ntot + I.off;
+  double* __restrict__ G = Garena + I.goff;
+  const int Nb = I.Nb, La = I.La, Lb = I.Lb;
+  const int64_t ndet = I.ndet;
+
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int col = t % TN, sub = t / TN;
+
+  // W rows of this wave's row blocks, as MFMA A operands: lane l holds
+  // W[rb*16 + l%16][ks*4 + l/16] (B operand: lane l holds D+[ks*4 + l/16][l%16])
+  double wreg[RBW][KS];
+  const double* __restrict__ W = warena + I.woff;
+#pragma unroll
+  for (int r = 0; r < RBW; ++r) {
+    const int rb = wave + 4 * r;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+      wreg[r][ks] = (rb < NRB) ? W[(rb * 16 + (lane & 15)) * KPAD + ks * 4 + (lane >> 4)] : 0.0;
+  }
+
+  for (int tile = wk.begin; tile < wk.end; ++tile) {
+    const int64_t K0 = (int64_t)tile * TN;
+    for (int x = t; x < KS * 4 * LDT; x += 256) Ds[x] = 0.0;
+    __syncthreads();
+    const int64_t K = K0 + col;
+    const bool valid = K < ndet;
+    const int Ka = valid ? (int)(K / Nb) : 0, Kb = valid ? (int)(K % Nb) : 0;
+    if (valid) {
+      const uint32_t* la = I.linkA + (int64_t)Ka * La;
+      for (int l = sub; l < La; l += NSUB) {
+        uint32_t e = la[l];
+        Ds[link_pair(e) * LDT + col] += link_sign(e) * c[(int64_t)link_addr(e) * Nb + Kb];
+      }
+    }
+    __syncthreads();
+    if (valid) {
+      const uint32_t* lb = I.linkB + (int64_t)Kb * Lb;
+      const double* crow = c + (int64_t)Ka * Nb;
+      for (int l = sub; l < Lb; l += NSUB) {
+        uint32_t e = lb[l];
+        Ds[link_pair(e) * LDT + col] += link_sign(e) * crow[link_addr(e)];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RBW; ++r) {
+      const int rb = wave + 4 * r;
+      if (rb >= NRB) continue;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        double4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const double b = Ds[(ks * 4 + (lane >> 4)) * LDT + cb * 16 + (lane & 15)];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wreg[r][ks], b, acc, 0, 0, 0);
+        }
+        const int64_t Kc = K0 + cb * 16 + (lane & 15);
+        if (Kc < ndet) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            // gfx950 FP64 16x16x4 output layout: register v of lane l is
+            // row l/16 + 4v, column l%16 of the 16x16 block
+            const int row = rb * 16 + (lane >> 4) + 4 * v;
+            if (row < NP) G[(int64_t)row * ndet + Kc] = acc[v];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// sigma_I = sum_{links (x,y,J,s) of Ia} s G_xy[J, Ib] + sum_{links of Ib} s G_xy[Ia, J]
+__global__ void __launch_bounds__(256) k_sigma_gather(const Item* __restrict__ items,
+                                                      const Work* __restrict__ work,
+                                                      const double* __restrict__ Garena,
+                                                      double* __restrict__ Sarena, int64_t ntot,
+                                                      const DavState* __restrict__ st, int slot) {
+  const Work wk = work[blockIdx.x];
+  const Item& I = items[wk.item];
+  const DavState& S = st[wk.item];
+  if (!item_active(S, slot)) return;
+  const int vs = vec_slot(S, slot);
+  const int64_t K = (int64_t)wk.begin * 256 + threadIdx.x;
+  if (K >= I.ndet) return;
+  const int Nb = I.Nb;
+  const int Ka = (int)(K / Nb), Kb = (int)(K % Nb);
+  const double* __restrict__ G = Garena + I.goff;
+  const int64_t nd = I.ndet;
+  double acc = 0.0;
+  const uint32_t* la = I.linkA + (int64_t)Ka * I.La;
+  for (int l = 0; l < I.La; ++l) {
+    uint32_t e = la[l];
+    acc += link_sign(e) * G[(int64_t)link_pair(e) * nd + (int64_t)link_addr(e) * Nb + Kb];
+  }
+  const uint32_t* lb = I.linkB + (int64_t)Kb * I.Lb;
+  const int64_t rowoff = (int64_t)Ka * Nb;
+  for (int l = 0; l < I.Lb; ++l) {
+    uint32_t e = lb[l];
+    acc += link_sign(e) * G[(int64_t)link_pair(e) * nd + rowoff + link_addr(e)];
+  }
+  Sarena[(int64_t)vs * ntot + I.off + K] = acc;
+}
+
+// ---------------------------------------------------------------- Davidson
+// Block-level fixed-order reduction of NV values per thread (256 threads).
+template <int NV>
+__device__ inline void block_reduce_store(double (&v)[NV], double* out) {
+  __shared__ double red[4][NV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double x = v[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    if (lane == 0) red[wave][i] = x;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < NV; i += blockDim.x)
+    out[i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
+  __syncthreads();
+}
+
+constexpr int kPart = kMaxSpace + 2;  // partial sums per chunk
+constexpr int kChunk = 4096;          // elements per reduction chunk
+
+// zero a vector slot range for the given items (fill kernel; graph safe)
+__global__ void k_fill(double* p, int64_t n, double v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Guess: the `nguess` lowest diagonal determinants (ties: lower address) as
+// unit vectors in slots 0..g-1.  One block per item.
+__global__ void k_dav_guess(const Item* __restrict__ items, int ibase,
+                            const double* __restrict__ diag, double* V, int64_t ntot, DavState* st,
+                            int nguess) {
+  const Item& I = items[ibase + blockIdx.x];
+  DavState& S = st[ibase + blockIdx.x];
+  const int t = threadIdx.x;
+  constexpr int G = 8;
+  double bv[G];
+  int64_t bi[G];
+  for (int g = 0; g < G; ++g) { bv[g] = 1e300; bi[g] = INT64_MAX; }
+  const double* d = diag + I.off;
+  for (int64_t K = t; K < I.ndet; K += blockDim.x) {
+    double x = d[K];
+    // insert (x, K) into the sorted list (value, then index)
+    if (x < bv[G - 1] || (x == bv[G - 1] && K < bi[G - 1])) {
+      int p = G - 1;
+      while (p > 0 && (x < bv[p - 1] || (x == bv[p - 1] && K < bi[p - 1]))) {
+        bv[p] = bv[p - 1]; bi[p] = bi[p - 1]; --p;
+      }
+      bv[p] = x; bi[p] = K;
+    }
+  }
+  __shared__ double sv[256 * G];
+  __shared__ int64_t si[256 * G];
+  for (int g = 0; g < G; ++g) { sv[t * G + g] = bv[g]; si[t * G + g] = bi[g]; }
+  __syncthreads();
+  if (t == 0) {
+    int g = nguess < G ? nguess : G;
+    if (g > I.ndet) g = (int)I.ndet;
+    int64_t pick[G];
+    for (int k = 0; k < g; ++k) {
+      double best = 1e301;
+      int64_t bidx = INT64_MAX;
+      for (int x = 0; x < (int)blockDim.x * G; ++x) {
+        double v = sv[x];
+        int64_t id = si[x];
+        if (id == INT64_MAX) continue;
+        bool used = false;
+        for (int j = 0; j < k; ++j) used |= (pick[j] == id);
+        if (used) continue;
+        if (v < best || (v == best && id < bidx)) { best = v; bidx = id; }
+      }
+      pick[k] = bidx;
+      V[(int64_t)k * ntot + I.off + bidx] = 1.0;
+    }
+    S.m = 0;
+    S.nguess = g;
+    S.iters = 0;
+    S.status = 0;
+    S.rnorm = 0.0;
+    S.conv = 0;
+    S.theta = 0.0;
+    if (I.ndet == 1) {
+      S.conv = 1;
+      S.m = 1;
+      S.theta = d[0];
+    }
+  }
+}
+
+// partial dots p_i = V_i . S_j over one chunk, for i < m (j = newest or `slot`)
+__global__ void __launch_bounds__(256) k_dav_dots(const Item* __restrict__ items,
+                                                  const Work* __restrict__ work,
+                                                  const double* __restrict__ V,
+                                                  const double* __restrict__ Sv, int64_t ntot,
+                                                  const DavState* __restrict__ st, int slot,
+                                                  double* part) {
+  const Work wk = work[blockIdx.x];
+  const Item& I = items[wk.item];
+  const DavState& S = st[wk.item];
+  if (!item_active(S, slot)) return;
+  const int j = slot >= 0 ? slot : S.m - 1;
+  const int m = j + 1;
+  double acc[kMaxSpace];
+#pragma unroll
+  for (int i = 0; i < kMaxSpace; ++i) acc[i] = 0.0;
+  const int64_t e0 = (int64_t)(wk.begin - I.chunk0) * kChunk;
+  const int64_t e1 = min(e0 + kChunk, I.ndet);
+  const double* sj = Sv + (int64_t)j * ntot + I.off;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const double s = sj[e];
+#pragma unroll
+    for (int i = 0; i < kMaxSpace; ++i)
+      if (i < m) acc[i] += V[(int64_t)i * ntot + I.off + e] * s;
+  }
+  block_reduce_store<kMaxSpace>(acc, part + (int64_t)wk.begin * kPart);
+}
+
+// Symmetric Jacobi eigen-solve of the m x m subspace matrix by one wave;
+// returns the lowest eigenvalue and its vector (ties: lowest index).
+__device__ void wave_jacobi_lowest(double* A, double* Vm, int m, double* theta, double* y) {
+  const int lane = threadIdx.x & 63;
+  for (int k = lane; k < m * m; k += 64) Vm[k] = (k / m == k % m) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int p = 0; p < m; ++p)
+      for (int q = 0; q < m; ++q) {
+        if (p != q) off += A[p * m + q] * A[p * m + q];
+        else dia += A[p * m + q] * A[p * m + q];
+      }
+    if (off <= 1e-32 * dia || off == 0.0) break;
+    for (int p = 0; p < m - 1; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        const double apq = A[p * m + q];
+        if (apq == 0.0) continue;
+        const double th = (A[q * m + q] - A[p * m + p]) / (2.0 * apq);
+        const double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double cs = 1.0 / sqrt(tt * tt + 1.0), sn = tt * cs;
+        __syncthreads();
+        if (lane < m) {
+          const double akp = A[lane * m + p], akq = A[lane * m + q];
+          A[lane * m + p] = cs * akp - sn * akq;
+          A[lane * m + q] = sn * akp + cs * akq;
+          const double vkp = Vm[lane * m + p], vkq = Vm[lane * m + q];
+          Vm[lane * m + p] = cs * vkp - sn * vkq;
+          Vm[lane * m + q] = sn * vkp + cs * vkq;
+        }
+        __syncthreads();
+        if (lane < m) {
+          const double apk = A[p * m + lane], aqk = A[q * m + lane];
+          A[p * m + lane] = cs * apk - sn * aqk;
+          A[q * m + lane] = sn * apk + cs * aqk;
+        }
+        __syncthreads();
+      }
+  }
+  int best = 0;
+  for (int k = 1; k < m; ++k)
+    if (A[k * m + k] < A[best * m + best]) best = k;
+  *theta = A[best * m + best];
+  for (int k = 0; k < m; ++k) y[k] = Vm[k * m + best];
+}
+
+// Reduce the dots of the newest column into Hs; when the subspace is
+// complete (guess phase) or always (iteration phase), Rayleigh-Ritz.
+// One 64-thread block per item.
+__global__ void k_dav_rr(const Item* __restrict__ items, int ibase,
+                         const double* __restrict__ part, DavState* st, int slot) {
+  const Item& I = items[ibase + blockIdx.x];
+  DavState& S = st[ibase + blockIdx.x];
+  if (!item_active(S, slot)) return;
+  const int j = slot >= 0 ? slot : S.m - 1;
+  const int m = j + 1;
+  const int lane = threadIdx.x;
+  if (lane < m) {
+    double v = 0.0;
+    for (int c = 0; c < I.nchunk; ++c) v += part[(int64_t)(I.chunk0 + c) * kPart + lane];
+    S.Hs[lane * kMaxSpace + j] = v;
+    S.Hs[j * kMaxSpace + lane] = v;
+  }
+  __syncthreads();
+  const bool solve = slot < 0 || slot == S.nguess - 1;
+  if (!solve) return;
+  __shared__ double A[kMaxSpace * kMaxSpace], Vm[kMaxSpace * kMaxSpace], y[kMaxSpace];
+  __shared__ double th;
+  for (int k = lane; k < m * m; k += 64) A[k] = S.Hs[(k / m) * kMaxSpace + (k % m)];
+  __syncthreads();
+  wave_jacobi_lowest(A, Vm, m, &th, y);
+  __syncthreads();
+  if (lane < kMaxSpace) S.y[lane] = lane < m ? y[lane] : 0.0;
+  if (lane == 0) {
+    S.theta = th;
+    if (slot >= 0) {   // end of the guess phase
+      S.m = m;
+    } else {
+      S.iters += 1;
+    }
+  }
+}
+
+// Restart: when the subspace is full, collapse it onto the Ritz vector
+// x = V y (and H x = S y) in slot 0.
+__global__ void __launch_bounds__(256) k_dav_collapse(const Item* __restrict__ items,
+                                                      const Work* __restrict__ work, double* V,
+                                                      double* Sv, int64_t ntot,
+                                                      const DavState* __restrict__ st, int mmax) {
+  const Work wk = work[blockIdx.x];
+  const Item& I = items[wk.item];
+  const DavState& S = st[wk.item];
+  if (S.conv || S.m < mmax) return;
+  const int64_t e0 = (int64_t)(wk.begin - I.chunk0) * kChunk;
+  const int64_t e1 = min(e0 + kChunk, I.ndet);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    double x = 0.0, sx = 0.0;
+    for (int i = 0; i < S.m; ++i) {
+      x += S.y[i] * V[(int64_t)i * ntot + I.off + e];
+      sx += S.y[i] * Sv[(int64_t)i * ntot + I.off + e];
+    }
+    V[I.off + e] = x;
+    Sv[I.off + e] = sx;
+  }
+}
+__global__ void k_dav_collapse_state(DavState* st, int ibase, int nitem, int mmax) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nitem) return;
+  i += ibase;
+  DavState& S = st[i];
+  if (S.conv || S.m < mmax) return;
+  S.m = 1;
+  S.Hs[0] = S.theta;
+  S.y[0] = 1.0;
+  for (int k = 1; k < kMaxSpace; ++k) S.y[k] = 0.0;
+}
+
+// Residual r = S y - theta V y, preconditioned t = r / (theta - H_II) into
+// slot m; partial sums of |r|^2 (index kMaxSpace) and V_i . t (i < m).
+__global__ void __launch_bounds__(256) k_dav_residual(const Item* __restrict__ items,
+                                                      const Work* __restrict__ work, double* V,
+                                                      const double* __restrict__ Sv,
+                                                      const double* __restrict__ diag,
+                                                      int64_t ntot,
+                                                      const DavState* __restrict__ st,
+                                                      double* part) {
+  const Work wk = work[blockIdx.x];
+  const Item& I = items[wk.item];
+  const DavState& S = st[wk.item];
+  if (S.conv) return;
+  const int m = S.m;
+  const double th = S.theta;
+  double y[kMaxSpace];
+#pragma unroll
+  for (int i = 0; i < kMaxSpace; ++i) y[i] = S.y[i];
+  double acc[kMaxSpace + 1];
+#pragma unroll
+  for (int i = 0; i <= kMaxSpace; ++i) acc[i] = 0.0;
+  const int64_t e0 = (int64_t)(wk.begin - I.chunk0) * kChunk;
+  const int64_t e1 = min(e0 + kChunk, I.ndet);
+  double* t_out = V + (int64_t)m * ntot + I.off;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    double r = 0.0;
+    double v[kMaxSpace];
+#pragma unroll
+    for (int i = 0; i < kMaxSpace; ++i) {
+      v[i] = 0.0;
+      if (i < m) {
+        v[i] = V[(int64_t)i * ntot + I.off + e];
+        r += y[i] * (Sv[(int64_t)i * ntot + I.off + e] - th * v[i]);
+      }
+    }
+    acc[kMaxSpace] += r * r;
+    double den = th - diag[I.off + e];
+    if (fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
+    const double tv = r / den;
+    t_out[e] = tv;
+#pragma unroll
+    for (int i = 0; i < kMaxSpace; ++i)
+      if (i < m) acc[i] += v[i] * tv;
+  }
+  block_reduce_store<kMaxSpace + 1>(acc, part + (int64_t)wk.begin * kPart);
+}
+
+// Convergence test and first Gram-Schmidt coefficients.
+__global__ void k_dav_reduce1(const Item* __restrict__ items, const double* __restrict__ part,
+                              DavState* st, int ibase, int nitem, double tol, int max_iter) {
+  int it = blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= nitem) return;
+  it += ibase;
+  const Item& I = items[it];
+  DavState& S = st[it];
+  if (S.conv) return;
+  double rr = 0.0;
+  double cf[kMaxSpace];
+  for (int i = 0; i < kMaxSpace; ++i) cf[i] = 0.0;
+  for (int c = 0; c < I.nchunk; ++c) {
+    const double* p = part + (int64_t)(I.chunk0 + c) * kPart;
+    rr += p[kMaxSpace];
+    for (int i = 0; i < S.m; ++i) cf[i] += p[i];
+  }
+  S.rnorm = sqrt(rr);
+  for (int i = 0; i < kMaxSpace; ++i) S.coef[i] = cf[i];
+  if (S.rnorm <= tol || S.m >= I.ndet) {
+    S.conv = 1;
+  } else if (S.iters >= max_iter) {
+    S.conv = 1;
+    S.status = 1;
+  }
+}
+
+// t -= sum_i coef_i V_i ; partial sums of V_i . t and |t|^2 (second pass).
+__global__ void __launch_bounds__(256) k_dav_orth(const Item* __restrict__ items,
+                                                  const Work* __restrict__ work, double* V,
+                                                  int64_t ntot, const DavState* __restrict__ st,
+                                                  double* part) {
+  const Work wk = work[blockIdx.x];
+  const Item& I = items[wk.item];
+  const DavState& S = st[wk.item];
+  if (S.conv) return;
+  const int m = S.m;
+  double cf[kMaxSpace];
+#pragma unroll
+  for (int i = 0; i < kMaxSpace; ++i) cf[i] = S.coef[i];
+  double acc[kMaxSpace + 1];
+#pragma unroll
+  for (int i = 0; i <= kMaxSpace; ++i) acc[i] = 0.0;
+  const int64_t e0 = (int64_t)(wk.begin - I.chunk0) * kChunk;
+  const int64_t e1 = min(e0 + kChunk, I.ndet);
+  double* t = V + (int64_t)m * ntot + I.off;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    double v[kMaxSpace];
+    double tv = t[e];
+#pragma unroll
+    for (int i = 0; i < kMaxSpace; ++i) {
+      v[i] = 0.0;
+      if (i < m) {
+        v[i] = V[(int64_t)i * ntot + I.off + e];
+        tv -= cf[i] * v[i];
+      }
+    }
+    t[e] = tv;
+#pragma unroll
+    for (int i = 0; i < kMaxSpace; ++i)
+      if (i < m) acc[i] += v[i] * tv;
+    acc[kMaxSpace] += tv * tv;
+  }
+  block_reduce_store<kMaxSpace + 1>(acc, part + (int64_t)wk.begin * kPart);
+}
+
+__global__ void k_dav_reduce2(const Item* __restrict__ items, const double* __restrict__ part,
+                              DavState* st, int ibase, int nitem) {
+  int it = blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= nitem) return;
+  it += ibase;
+  const Item& I = items[it];
+  DavState& S = st[it];
+  if (S.conv) return;
+  double tt = 0.0;
+  double cf[kMaxSpace];
+  for (int i = 0; i < kMaxSpace; ++i) cf[i] = 0.0;
+  for (int c = 0; c < I.nchunk; ++c) {
+    const double* p = part + (int64_t)(I.chunk0 + c) * kPart;
+    tt += p[kMaxSpace];
+    for (int i = 0; i < S.m; ++i) cf[i] += p[i];
+  }
+  double n2 = tt;
+  for (int i = 0; i < S.m; ++i) n2 -= cf[i] * cf[i];
+  for (int i = 0; i < kMaxSpace; ++i) S.coef[i] = cf[i];
+  S.tnorm2 = n2;
+  if (!(n2 > 1e-28)) {  // the correction lies in the subspace: accept
+    S.conv = 1;
+    S.status = 2;
+  }
+}
+
+// t -= sum_i coef_i V_i, t /= |t|: the new basis vector in slot m; m += 1.
+__global__ void __launch_bounds__(256) k_dav_orth2(const Item* __restrict__ items,
+                                                   const Work* __restrict__ work, double* V,
+                                                   int64_t ntot, const DavState* __restrict__ st) {
+  const Work wk = work[blockIdx.x];
+  const Item& I = items[wk.item];
+  const DavState& S = st[wk.item];
+  if (S.conv) return;
+  const int m = S.m;
+  double cf[kMaxSpace];
+#pragma unroll
+  for (int i = 0; i < kMaxSpace; ++i) cf[i] = S.coef[i];
+  const double inv = 1.0 / sqrt(S.tnorm2);
+  const int64_t e0 = (int64_t)(wk.begin - I.chunk0) * kChunk;
+  const int64_t e1 = min(e0 + kChunk, I.ndet);
+  double* t = V + (int64_t)m * ntot + I.off;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    double tv = t[e];
+#pragma unroll
+    for (int i = 0; i < kMaxSpace; ++i)
+      if (i < m) tv -= cf[i] * V[(int64_t)i * ntot + I.off + e];
+    t[e] = tv * inv;
+  }
+}
+__global__ void k_dav_grow(DavState* st, int ibase, int nitem) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nitem) return;
+  i += ibase;
+  DavState& S = st[i];
+  if (!S.conv) S.m += 1;
+}
+
+// ---------------------------------------------------------- MBE combine
+// f(T) = E_core(T) + theta_T ; eps_T = f(T) - E_ref ;
+// Delta eps_T = sum over non-empty U in T of (-1)^{|T|-|U|} eps_U, which is the
+// solution of the recursion of Eq. 2 (Moebius inversion of
+// eps_T = sum_{non-empty U in T} Delta eps_U).
+__global__ void k_item_energy(const Item* __restrict__ items, const ItemHam* __restrict__ hams,
+                              const DavState* __restrict__ st, int nitem, double* f) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nitem) return;
+  f[i] = hams[items[i].ham].ecore + st[i].theta;
+}
+
+__global__ void k_mbe_increments(MbeSpaces sp, const BucketDev* __restrict__ buckets, int nbucket,
+                                 const int32_t* __restrict__ tuple_pos, int max_order,
+                                 const double* __restrict__ f, int nitem, double* inc,
+                                 double* inc_lex, const int64_t* __restrict__ order_off,
+                                 const int32_t* __restrict__ xpos_o,
+                                 const int32_t* __restrict__ xpos_v, int nX) {
+  int it = blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= nitem || it == 0) return;   // item 0 is the reference CASCI
+  const int32_t* tp = tuple_pos + (int64_t)it * (2 * max_order + 2);
+  const int no = tp[0], nv = tp[1], n = no + nv;
+  const double eref = f[0];
+  // bucket base index per (order, nocc)
+  double acc = 0.0;
+  const unsigned full = (1u << n) - 1u;
+  for (unsigned sub = 1; sub <= full; ++sub) {
+    int co[kMaxActive], cv[kMaxActive];
+    int ko = 0, kv = 0;
+    for (int b = 0; b < n; ++b)
+      if (sub >> b & 1) {
+        if (b < no) co[ko++] = tp[2 + b];
+        else cv[kv++] = tp[2 + b];
+      }
+    const int ord = ko + kv;
+    int64_t base = -1;
+    for (int b = 0; b < nbucket; ++b)
+      if (buckets[b].order == ord && buckets[b].nocc == ko) base = buckets[b].item0;
+    const int64_t idx = base + comb_lex_rank(co, ko, sp.nXo) * binom(sp.nXv, kv) +
+                        comb_lex_rank(cv, kv, sp.nXv);
+    const double e = f[idx] - eref;
+    acc += ((n - ord) & 1) ? -e : e;
+  }
+  inc[it] = acc;
+  if (inc_lex) {
+    // lexicographic rank of T among the order-n tuples of the sorted X
+    int c[kMaxActive];
+    for (int b = 0; b < no; ++b) c[b] = xpos_o[tp[2 + b]];
+    for (int b = 0; b < nv; ++b) c[no + b] = xpos_v[tp[2 + no + b]];
+    for (int a = 1; a < n; ++a) {
+      int v = c[a], j = a - 1;
+      while (j >= 0 && c[j] > v) { c[j + 1] = c[j]; --j; }
+      c[j + 1] = v;
+    }
+    inc_lex[order_off[n - 1] + comb_lex_rank(c, n, nX)] = acc;
+  }
+}
+
+// E^(n) = sum of the order-n increments, one block per order, fixed order.
+__global__ void k_mbe_order_sums(const BucketDev* __restrict__ buckets, int nbucket,
+                                 const double* __restrict__ inc, double* e_order) {
+  const int n = blockIdx.x + 1;
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int b = 0; b < nbucket; ++b) {
+    if (buckets[b].order != n) continue;
+    for (int64_t i = threadIdx.x; i < buckets[b].count; i += 256) acc += inc[buckets[b].item0 + i];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) e_order[n - 1] = red[0];
+}
+
+// ------------------------------------------------------- bookkeeping kernels
+// number of items of [ibase, ibase+nitem) not yet converged (one block)
+__global__ void k_count_active(const DavState* __restrict__ st, int ibase, int nitem, int* out) {
+  __shared__ int red[256];
+  int c = 0;
+  for (int i = threadIdx.x; i < nitem; i += 256) c += st[ibase + i].conv ? 0 : 1;
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+// per-item (iterations, status, guess count, subspace) for the statistics
+__global__ void k_collect(const DavState* __restrict__ st, int nitem, int32_t* out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nitem) return;
+  out[4 * i + 0] = st[i].iters;
+  out[4 * i + 1] = st[i].status;
+  out[4 * i + 2] = st[i].nguess;
+  out[4 * i + 3] = st[i].conv;
+}
+
+// state of a single caller-provided vector in slot 0 (sigma entry point)
+__global__ void k_state_single(DavState* st) {
+  if (threadIdx.x == 0) {
+    st->m = 1;
+    st->nguess = 1;
+    st->conv = 0;
+    st->iters = 0;
+    st->status = 0;
+  }
+}
+
+// out = s + a*c
+__global__ void k_axpy_out(double* out, const double* s, const double* c, double a, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = s[i] + a * c[i];
+}
+
+// out = (d + a) * c  (sigma of a diagonal Hamiltonian)
+__global__ void k_diag_times(double* out, const double* d, const double* c, double a, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (d[i] + a) * c[i];
+}
+
+__global__ void k_add_scalar(double* out, const double* in, double a, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i] + a;
+}
+
+// Ritz vector x = V y of every item into `out` (arena layout), normalised.
+__global__ void __launch_bounds__(256) k_ritz_vector(const Item* __restrict__ items,
+                                                     const Work* __restrict__ work,
+                                                     const double* __restrict__ V, int64_t ntot,
+                                                     const DavState* __restrict__ st,
+                                                     double* out) {
+  const Work wk = work[blockIdx.x];
+  const Item& I = items[wk.item];
+  const DavState& S = st[wk.item];
+  const int64_t e0 = (int64_t)(wk.begin - I.chunk0) * kChunk;
+  const int64_t e1 = min(e0 + kChunk, I.ndet);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    double x = 0.0;
+    if (I.ndet == 1) {
+      x = 1.0;
+    } else {
+      for (int i = 0; i < S.m; ++i) x += S.y[i] * V[(int64_t)i * ntot + I.off + e];
+    }
+    out[I.off + e] = x;
+  }
+}
+
+// E_total = E_ref + sum_n E^(n), in order
+__global__ void k_mbe_total(const double* f, const double* e_order, int k, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double e = f[0];
+    for (int n = 0; n < k; ++n) e += e_order[n];
+    out[0] = f[0];
+    out[1] = e;
+  }
+}
+
+// ================================================================ launchers
+static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+void launch_strings(int n, int ne, int64_t N, uint64_t* out, hipStream_t s) {
+  if (N > 0) hipLaunchKernelGGL(k_strings, dim3(nblk(N, 256)), dim3(256), 0, s, n, ne, N, out);
+}
+void launch_links(int n, int ne, int64_t N, uint32_t* packed, int32_t* abi4, hipStream_t s) {
+  if (N > 0)
+    hipLaunchKernelGGL(k_links, dim3(nblk(N, 128)), dim3(128), 0, s, n, ne, N, packed, abi4);
+}
+void launch_mbe_setup(const MbeSpaces* sp, const BucketDev* buckets, int nbucket, const Item* items,
+                      int nitem, const double* h1, const double* eri, double e_const,
+                      ItemHam* hams, double* warena, int32_t* tuple_pos, int max_order,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_mbe_setup, dim3(nitem), dim3(256), 0, s, *sp, buckets, nbucket, items, h1,
+                     eri, e_const, hams, warena, tuple_pos, max_order);
+}
+void launch_casci_setup(int n, const double* const* h1s, const double* const* eris,
+                        const double* ecores, const Item* items, int nitem, ItemHam* hams,
+                        double* warena, hipStream_t s) {
+  hipLaunchKernelGGL(k_casci_setup, dim3(nitem), dim3(256), 0, s, n, h1s, eris, ecores, items,
+                     hams, warena);
+}
+void launch_hdiag(const Item* items, const Work* work, int nwork, const ItemHam* hams,
+                  double* diag, hipStream_t s) {
+  if (nwork > 0)
+    hipLaunchKernelGGL(k_hdiag, dim3(nwork), dim3(256), 0, s, items, work, hams, diag);
+}
+
+template <int NACT, int TN>
+static void sigma_dgemm_t(const Item* items, const Work* work, int nwork, const double* warena,
+                          const double* V, int64_t ntot, double* G, const DavState* st, int slot,
+                          hipStream_t s) {
+  hipLaunchKernelGGL((k_sigma_dgemm<NACT, TN>), dim3(nwork), dim3(256), 0, s, items, work, warena,
+                     V, ntot, G, st, slot);
+}
+
+template <int TN>
+static bool sigma_dgemm_n(int n, const Item* items, const Work* work, int nwork,
+                          const double* warena, const double* V, int64_t ntot, double* G,
+                          const DavState* st, int slot, hipStream_t s) {
+  switch (n) {
+#define MBEFCI_CASE(N) \
+  case N: sigma_dgemm_t<N, TN>(items, work, nwork, warena, V, ntot, G, st, slot, s); return true;
+    MBEFCI_CASE(2) MBEFCI_CASE(3) MBEFCI_CASE(4) MBEFCI_CASE(5) MBEFCI_CASE(6) MBEFCI_CASE(7)
+    MBEFCI_CASE(8) MBEFCI_CASE(9) MBEFCI_CASE(10) MBEFCI_CASE(11) MBEFCI_CASE(12)
+    MBEFCI_CASE(13) MBEFCI_CASE(14)
+#undef MBEFCI_CASE
+    default: return false;
+  }
+}
+
+bool launch_sigma_dgemm(int n, int tn, const Item* items, const Work* work, int nwork,
+                        const double* warena, const double* V, int64_t ntot, double* G,
+                        const DavState* st, int slot, hipStream_t s) {
+  if (nwork <= 0) return true;
+  switch (tn) {
+    case 32: return sigma_dgemm_n<32>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
+    case 64: return sigma_dgemm_n<64>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
+    case 128: return sigma_dgemm_n<128>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
+    default: return false;
+  }
+}
+
+void launch_sigma_gather(const Item* items, const Work* work, int nwork, const double* G,
+                         double* Sv, int64_t ntot, const DavState* st, int slot, hipStream_t s) {
+  if (nwork > 0)
+    hipLaunchKernelGGL(k_sigma_gather, dim3(nwork), dim3(256), 0, s, items, work, G, Sv, ntot, st,
+                       slot);
+}
+
+void launch_fill(double* p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t b = nblk(n, 256);
+  if (b > 65536) b = 65536;
+  hipLaunchKernelGGL(k_fill, dim3((int)b), dim3(256), 0, s, p, n, v);
+}
+void launch_dav_guess(const Item* items, int ibase, int nitem, const double* diag, double* V,
+                      int64_t ntot, DavState* st, int nguess, hipStream_t s) {
+  hipLaunchKernelGGL(k_dav_guess, dim3(nitem), dim3(256), 0, s, items, ibase, diag, V, ntot, st,
+                     nguess);
+}
+void launch_dav_dots(const Item* items, const Work* chunks, int nchunk, const double* V,
+                     const double* Sv, int64_t ntot, const DavState* st, int slot, double* part,
+                     hipStream_t s) {
+  if (nchunk > 0)
+    hipLaunchKernelGGL(k_dav_dots, dim3(nchunk), dim3(256), 0, s, items, chunks, V, Sv, ntot, st,
+                       slot, part);
+}
+void launch_dav_rr(const Item* items, int ibase, int nitem, const double* part, DavState* st,
+                   int slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_dav_rr, dim3(nitem), dim3(64), 0, s, items, ibase, part, st, slot);
+}
+void launch_dav_iteration(const Item* items, int ibase, int nitem, const Work* chunks, int nchunk,
+                          double* V, double* Sv, const double* diag, int64_t ntot, DavState* st,
+                          double* part, double tol, int max_iter, int mmax, hipStream_t s) {
+  if (nchunk <= 0) return;
+  const int nb = nblk(nitem, 64);
+  hipLaunchKernelGGL(k_dav_collapse, dim3(nchunk), dim3(256), 0, s, items, chunks, V, Sv, ntot, st,
+                     mmax);
+  hipLaunchKernelGGL(k_dav_collapse_state, dim3(nb), dim3(64), 0, s, st, ibase, nitem, mmax);
+  hipLaunchKernelGGL(k_dav_residual, dim3(nchunk), dim3(256), 0, s, items, chunks, V, Sv, diag,
+                     ntot, st, part);
+  hipLaunchKernelGGL(k_dav_reduce1, dim3(nb), dim3(64), 0, s, items, part, st, ibase, nitem, tol,
+                     max_iter);
+  hipLaunchKernelGGL(k_dav_orth, dim3(nchunk), dim3(256), 0, s, items, chunks, V, ntot, st, part);
+  hipLaunchKernelGGL(k_dav_reduce2, dim3(nb), dim3(64), 0, s, items, part, st, ibase, nitem);
+  hipLaunchKernelGGL(k_dav_orth2, dim3(nchunk), dim3(256), 0, s, items, chunks, V, ntot, st);
+  hipLaunchKernelGGL(k_dav_grow, dim3(nb), dim3(64), 0, s, st, ibase, nitem);
+}
+void launch_item_energy(const Item* items, const ItemHam* hams, const DavState* st, int nitem,
+                        double* f, hipStream_t s) {
+  hipLaunchKernelGGL(k_item_energy, dim3(nblk(nitem, 64)), dim3(64), 0, s, items, hams, st, nitem,
+                     f);
+}
+void launch_mbe_combine(const MbeSpaces* sp, const BucketDev* buckets, int nbucket,
+                        const int32_t* tuple_pos, int max_order, const double* f, int nitem,
+                        double* inc, double* inc_lex, const int64_t* order_off,
+                        const int32_t* xpos_o, const int32_t* xpos_v, int nX, double* e_order,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_mbe_increments, dim3(nblk(nitem, 64)), dim3(64), 0, s, *sp, buckets,
+                     nbucket, tuple_pos, max_order, f, nitem, inc, inc_lex, order_off, xpos_o,
+                     xpos_v, nX);
+  if (max_order > 0)
+    hipLaunchKernelGGL(k_mbe_order_sums, dim3(max_order), dim3(256), 0, s, buckets, nbucket, inc,
+                       e_order);
+}
+
+}  // namespace mbefci
+
+namespace mbefci {
+void launch_count_active(const DavState* st, int ibase, int nitem, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, s, st, ibase, nitem, out);
+}
+void launch_collect(const DavState* st, int nitem, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_collect, dim3(nblk(nitem, 64)), dim3(64), 0, s, st, nitem, out);
+}
+void launch_state_single(DavState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_single, dim3(1), dim3(64), 0, s, st);
+}
+void launch_axpy_out(double* out, const double* sv, const double* c, double a, int64_t n,
+                     hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_axpy_out, dim3(nblk(n, 256)), dim3(256), 0, s, out, sv, c, a, n);
+}
+void launch_diag_times(double* out, const double* d, const double* c, double a, int64_t n,
+                       hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_diag_times, dim3(nblk(n, 256)), dim3(256), 0, s, out, d, c, a, n);
+}
+void launch_add_scalar(double* out, const double* in, double a, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_add_scalar, dim3(nblk(n, 256)), dim3(256), 0, s, out, in, a, n);
+}
+void launch_ritz_vector(const Item* items, const Work* chunks, int nchunk, const double* V,
+                        int64_t ntot, const DavState* st, double* out, hipStream_t s) {
+  if (nchunk > 0)
+    hipLaunchKernelGGL(k_ritz_vector, dim3(nchunk), dim3(256), 0, s, items, chunks, V, ntot, st,
+                       out);
+}
+void launch_mbe_total(const double* f, const double* e_order, int k, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_mbe_total, dim3(1), dim3(64), 0, s, f, e_order, k, out);
+}
+}  // namespace mbefci

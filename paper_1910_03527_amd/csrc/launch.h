@@ -1,0 +1,61 @@
+// Kernel launchers (kernels.hip) called by the host runtime (runtime.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace mbefci {
+
+void launch_strings(int n, int ne, int64_t N, uint64_t* out, hipStream_t s);
+void launch_links(int n, int ne, int64_t N, uint32_t* packed, int32_t* abi4, hipStream_t s);
+void launch_mbe_setup(const MbeSpaces* sp, const BucketDev* buckets, int nbucket, const Item* items,
+                      int nitem, const double* h1, const double* eri, double e_const,
+                      ItemHam* hams, double* warena, int32_t* tuple_pos, int max_order,
+                      hipStream_t s);
+void launch_casci_setup(int n, const double* const* h1s, const double* const* eris,
+                        const double* ecores, const Item* items, int nitem, ItemHam* hams,
+                        double* warena, hipStream_t s);
+void launch_hdiag(const Item* items, const Work* work, int nwork, const ItemHam* hams,
+                  double* diag, hipStream_t s);
+bool launch_sigma_dgemm(int n, int tn, const Item* items, const Work* work, int nwork,
+                        const double* warena, const double* V, int64_t ntot, double* G,
+                        const DavState* st, int slot, hipStream_t s);
+void launch_sigma_gather(const Item* items, const Work* work, int nwork, const double* G,
+                         double* Sv, int64_t ntot, const DavState* st, int slot, hipStream_t s);
+void launch_fill(double* p, int64_t n, double v, hipStream_t s);
+void launch_dav_guess(const Item* items, int ibase, int nitem, const double* diag, double* V,
+                      int64_t ntot, DavState* st, int nguess, hipStream_t s);
+void launch_dav_dots(const Item* items, const Work* chunks, int nchunk, const double* V,
+                     const double* Sv, int64_t ntot, const DavState* st, int slot, double* part,
+                     hipStream_t s);
+void launch_dav_rr(const Item* items, int ibase, int nitem, const double* part, DavState* st,
+                   int slot, hipStream_t s);
+void launch_dav_iteration(const Item* items, int ibase, int nitem, const Work* chunks, int nchunk,
+                          double* V, double* Sv, const double* diag, int64_t ntot, DavState* st,
+                          double* part, double tol, int max_iter, int mmax, hipStream_t s);
+void launch_item_energy(const Item* items, const ItemHam* hams, const DavState* st, int nitem,
+                        double* f, hipStream_t s);
+void launch_mbe_combine(const MbeSpaces* sp, const BucketDev* buckets, int nbucket,
+                        const int32_t* tuple_pos, int max_order, const double* f, int nitem,
+                        double* inc, double* inc_lex, const int64_t* order_off,
+                        const int32_t* xpos_o, const int32_t* xpos_v, int nX, double* e_order,
+                        hipStream_t s);
+
+void launch_count_active(const DavState* st, int ibase, int nitem, int* out, hipStream_t s);
+void launch_collect(const DavState* st, int nitem, int32_t* out, hipStream_t s);
+void launch_state_single(DavState* st, hipStream_t s);
+void launch_axpy_out(double* out, const double* sv, const double* c, double a, int64_t n,
+                     hipStream_t s);
+void launch_diag_times(double* out, const double* d, const double* c, double a, int64_t n,
+                       hipStream_t s);
+void launch_add_scalar(double* out, const double* in, double a, int64_t n, hipStream_t s);
+void launch_ritz_vector(const Item* items, const Work* chunks, int nchunk, const double* V,
+                        int64_t ntot, const DavState* st, double* out, hipStream_t s);
+void launch_mbe_total(const double* f, const double* e_order, int k, double* out, hipStream_t s);
+
+constexpr int kChunkElems = 4096;   // elements per Davidson reduction chunk
+constexpr int kPartStride = kMaxSpace + 2;
+
+}  // namespace mbefci

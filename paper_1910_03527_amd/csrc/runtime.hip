@@ -1,0 +1,909 @@
+// Host runtime and C ABI of the MBE-FCI library (see include/mbefci.h).
+//
+// The runtime plans a batch of CASCI problems ("items"): per-item determinant
+// counts, arena offsets, work lists for the segmented kernels and the sigma
+// tile lists grouped by active-space size; it owns the device workspaces and
+// drives the Davidson iterations either for the whole batch at once (one
+// launch sequence per iteration, replayed from a captured HIP graph) or one
+// CASCI at a time (the per-launch baseline).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/mbefci.h"
+#include "common.h"
+#include "launch.h"
+
+using namespace mbefci;
+
+namespace {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                       \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess)                                                               \
+      throw Error(MBEFCI_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+int64_t binom_host(int n, int k) {
+  if (k < 0 || n < 0 || k > n) return 0;
+  int64_t r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct StringTab {
+  int n = 0, ne = 0, L = 0;
+  int64_t N = 0;
+  uint32_t* link = nullptr;
+};
+
+// One kernel-shape group of a plan: items with the same active size n share
+// the sigma contraction kernel (its pair dimension is a template parameter).
+struct Group {
+  int n = 0, tn = 64, tiles_per_wg = 4;
+  std::vector<Work> tiles;
+  std::vector<int> item_lo, item_hi;  // per item of the plan: its tile range (or empty)
+  Work* d_tiles = nullptr;
+};
+
+struct Plan {
+  std::vector<Item> items;
+  std::vector<BucketDev> buckets;
+  std::vector<Work> chunks, blocks;        // reduction chunks, 256-determinant blocks
+  std::vector<int> chunk_lo, chunk_hi, block_lo, block_hi;
+  std::vector<Group> groups;
+  std::vector<int> item_group;
+  int nitem = 0, nchunk = 0, nblock = 0;
+  int64_t ntot = 0, gtot = 0, wtot = 0;
+  int nsingle = 0;
+  int64_t ndet_total = 0;
+  // device
+  Item* d_items = nullptr;
+  Work* d_chunks = nullptr;
+  Work* d_blocks = nullptr;
+  BucketDev* d_buckets = nullptr;
+  double *V = nullptr, *S = nullptr, *diag = nullptr, *G = nullptr, *W = nullptr,
+         *part = nullptr, *f = nullptr, *inc = nullptr, *ci = nullptr;
+  ItemHam* hams = nullptr;
+  DavState* st = nullptr;
+  int32_t* tuple_pos = nullptr;
+  int* d_count = nullptr;
+  int32_t* d_collect = nullptr;
+  // MBE description (for the combine and the backward)
+  bool is_mbe = false;
+  MbeSpaces sp{};
+  int max_order = 0, norb = 0;
+  int64_t ntuples = 0;
+  std::vector<int> xsorted;
+  // graph of `graph_iters` batched iterations
+  hipGraphExec_t graph = nullptr;
+  int graph_iters = 0;
+  std::string signature;
+};
+
+}  // namespace
+
+struct mbefci_ctx {
+  int device = 0;
+  mbefci_opts opts{};
+  std::string err;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, t0 = nullptr, t1 = nullptr;
+  std::map<std::pair<int, int>, StringTab> tabs;
+  std::map<std::string, DevBuf> bufs;
+  std::unique_ptr<Plan> plan;
+  std::map<int, int> tuned_tile;  // active size n -> tile width
+  bool have_forward = false;
+  std::vector<double> host_scratch;
+};
+
+namespace {
+
+// ------------------------------------------------------------ device memory
+template <class T>
+T* arena(mbefci_ctx* c, const std::string& name, size_t count, bool* grown = nullptr) {
+  size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  DevBuf& b = c->bufs[name];
+  if (b.bytes < bytes) {
+    if (b.p) HIPCHK(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+    size_t total = 0;
+    for (auto& kv : c->bufs) total += kv.second.bytes;
+    if (c->opts.max_workspace > 0 && (int64_t)(total + bytes) > c->opts.max_workspace)
+      throw Error(MBEFCI_ENOMEM, "workspace cap exceeded by arena '" + name + "'");
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(MBEFCI_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes for '" + name +
+                                     "' failed");
+    }
+    b.bytes = bytes;
+    if (grown) *grown = true;
+  }
+  return static_cast<T*>(b.p);
+}
+
+template <class T>
+void upload(mbefci_ctx* c, T* dst, const std::vector<T>& src) {
+  if (!src.empty())
+    HIPCHK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice,
+                          c->stream));
+}
+
+const StringTab& string_tab(mbefci_ctx* c, int n, int ne) {
+  auto key = std::make_pair(n, ne);
+  auto it = c->tabs.find(key);
+  if (it != c->tabs.end()) return it->second;
+  StringTab t;
+  t.n = n;
+  t.ne = ne;
+  t.N = binom_host(n, ne);
+  t.L = ne * (n - ne + 1);
+  if (t.N * t.L > 0) {
+    HIPCHK(hipMalloc(&t.link, sizeof(uint32_t) * t.N * t.L));
+    launch_links(n, ne, t.N, t.link, nullptr, c->stream);
+    HIPCHK(hipGetLastError());
+  }
+  return c->tabs[key] = t;
+}
+
+int tile_for(mbefci_ctx* c, int n) {
+  if (c->opts.tile == 32 || c->opts.tile == 64 || c->opts.tile == 128) return c->opts.tile;
+  auto it = c->tuned_tile.find(n);
+  if (it != c->tuned_tile.end()) return it->second;
+  return 64;
+}
+
+// --------------------------------------------------------------- planning
+// items must have n, na, nb filled; computes every derived field, work lists
+// and allocates the arenas.
+void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
+  const int mmax = c->opts.max_space;
+  P.nitem = (int)P.items.size();
+  int64_t off = 0, goff = 0, woff = 0;
+  int chunk = 0;
+  std::map<int, int> group_of_n;
+  P.item_group.assign(P.nitem, -1);
+  P.chunks.clear();
+  P.blocks.clear();
+  P.chunk_lo.assign(P.nitem, 0);
+  P.chunk_hi.assign(P.nitem, 0);
+  P.block_lo.assign(P.nitem, 0);
+  P.block_hi.assign(P.nitem, 0);
+  P.nsingle = 0;
+  P.ndet_total = 0;
+  for (int i = 0; i < P.nitem; ++i) {
+    Item& I = P.items[i];
+    if (I.n > 14) throw Error(MBEFCI_EUNSUPPORTED, "active space of " + std::to_string(I.n) +
+                                                       " orbitals exceeds the compiled kernels (14)");
+    const StringTab& ta = string_tab(c, I.n, I.na);
+    const StringTab& tb = string_tab(c, I.n, I.nb);
+    I.Na = (int32_t)ta.N;
+    I.Nb = (int32_t)tb.N;
+    I.La = ta.L;
+    I.Lb = tb.L;
+    I.linkA = ta.link;
+    I.linkB = tb.link;
+    I.ndet = (int64_t)I.Na * I.Nb;
+    I.npair = I.n * (I.n + 1) / 2;
+    I.kpad = (I.npair + 15) / 16 * 16;
+    I.off = off;
+    off += (I.ndet + 63) / 64 * 64;
+    I.ham = i;
+    P.ndet_total += I.ndet;
+    if (I.ndet > 1) {
+      I.goff = goff;
+      goff += (int64_t)I.npair * I.ndet;
+      I.woff = woff;
+      woff += (int64_t)I.kpad * I.kpad;
+    } else {
+      I.goff = 0;
+      I.woff = 0;
+      ++P.nsingle;
+    }
+    const int nch = (int)((I.ndet + kChunkElems - 1) / kChunkElems);
+    I.chunk0 = chunk;
+    I.nchunk = nch;
+    P.chunk_lo[i] = (int)P.chunks.size();
+    for (int k = 0; k < nch; ++k) P.chunks.push_back(Work{i, chunk + k, chunk + k + 1, 0});
+    P.chunk_hi[i] = (int)P.chunks.size();
+    chunk += nch;
+    const int nbk = (int)((I.ndet + 255) / 256);
+    P.block_lo[i] = (int)P.blocks.size();
+    for (int k = 0; k < nbk; ++k) P.blocks.push_back(Work{i, k, k + 1, 0});
+    P.block_hi[i] = (int)P.blocks.size();
+    if (I.ndet > 1) {
+      if (!group_of_n.count(I.n)) {
+        group_of_n[I.n] = (int)P.groups.size();
+        Group g;
+        g.n = I.n;
+        g.tn = tile_for(c, I.n);
+        g.item_lo.assign(P.nitem, 0);
+        g.item_hi.assign(P.nitem, 0);
+        P.groups.push_back(g);
+      }
+      P.item_group[i] = group_of_n[I.n];
+    }
+  }
+  for (int i = 0; i < P.nitem; ++i) {
+    if (P.item_group[i] < 0) continue;
+    Group& g = P.groups[P.item_group[i]];
+    const Item& I = P.items[i];
+    const int ntile = (int)((I.ndet + g.tn - 1) / g.tn);
+    g.item_lo[i] = (int)g.tiles.size();
+    for (int b = 0; b < ntile; b += g.tiles_per_wg)
+      g.tiles.push_back(Work{i, b, std::min(b + g.tiles_per_wg, ntile), 0});
+    g.item_hi[i] = (int)g.tiles.size();
+  }
+  P.ntot = std::max<int64_t>(off, 64);
+  P.gtot = goff;
+  P.wtot = woff;
+  P.nchunk = (int)P.chunks.size();
+  P.nblock = (int)P.blocks.size();
+
+  bool grown = false;
+  P.d_items = arena<Item>(c, "items", P.nitem, &grown);
+  P.d_chunks = arena<Work>(c, "chunks", P.nchunk, &grown);
+  P.d_blocks = arena<Work>(c, "blocks", P.nblock, &grown);
+  P.hams = arena<ItemHam>(c, "hams", P.nitem, &grown);
+  P.st = arena<DavState>(c, "state", P.nitem, &grown);
+  P.V = arena<double>(c, "V", (size_t)(mmax + 1) * P.ntot, &grown);
+  P.S = arena<double>(c, "S", (size_t)mmax * P.ntot, &grown);
+  P.diag = arena<double>(c, "diag", P.ntot, &grown);
+  P.G = arena<double>(c, "G", std::max<int64_t>(P.gtot, 1), &grown);
+  P.W = arena<double>(c, "W", std::max<int64_t>(P.wtot, 1), &grown);
+  P.part = arena<double>(c, "part", (size_t)std::max(P.nchunk, 1) * kPartStride, &grown);
+  P.f = arena<double>(c, "f", P.nitem + 2, &grown);
+  P.inc = arena<double>(c, "inc", P.nitem, &grown);
+  P.d_count = arena<int>(c, "count", 4, &grown);
+  P.d_collect = arena<int32_t>(c, "collect", (size_t)4 * P.nitem, &grown);
+  if (c->opts.keep_ci) P.ci = arena<double>(c, "ci", P.ntot, &grown);
+  for (size_t g = 0; g < P.groups.size(); ++g)
+    P.groups[g].d_tiles =
+        arena<Work>(c, "tiles" + std::to_string(g), P.groups[g].tiles.size(), &grown);
+  upload(c, P.d_items, P.items);
+  upload(c, P.d_chunks, P.chunks);
+  upload(c, P.d_blocks, P.blocks);
+  for (auto& g : P.groups) upload(c, g.d_tiles, g.tiles);
+  (void)nguess_slots;
+}
+
+// ----------------------------------------------------------------- solver
+struct View {
+  int ibase, nitem;
+  int chunk_lo, nchunk;
+  int block_lo, nblock;
+  int item;  // -1: whole plan, else the single item
+};
+
+View whole(const Plan& P) { return View{0, P.nitem, 0, P.nchunk, 0, P.nblock, -1}; }
+View single(const Plan& P, int i) {
+  return View{i, 1, P.chunk_lo[i], P.chunk_hi[i] - P.chunk_lo[i], P.block_lo[i],
+              P.block_hi[i] - P.block_lo[i], i};
+}
+
+void sigma(mbefci_ctx* c, Plan& P, const View& v, int slot) {
+  for (auto& g : P.groups) {
+    int lo = 0, cnt = (int)g.tiles.size();
+    if (v.item >= 0) {
+      if (P.item_group[v.item] < 0 || &P.groups[P.item_group[v.item]] != &g) continue;
+      lo = g.item_lo[v.item];
+      cnt = g.item_hi[v.item] - lo;
+    }
+    if (!launch_sigma_dgemm(g.n, g.tn, P.d_items, g.d_tiles + lo, cnt, P.W, P.V, P.ntot, P.G, P.st,
+                            slot, c->stream))
+      throw Error(MBEFCI_EUNSUPPORTED, "no sigma kernel for n=" + std::to_string(g.n));
+  }
+  launch_sigma_gather(P.d_items, P.d_blocks + v.block_lo, v.nblock, P.G, P.S, P.ntot, P.st, slot,
+                      c->stream);
+}
+
+void add_vector(mbefci_ctx* c, Plan& P, const View& v, int slot) {
+  sigma(c, P, v, slot);
+  launch_dav_dots(P.d_items, P.d_chunks + v.chunk_lo, v.nchunk, P.V, P.S, P.ntot, P.st, slot,
+                  P.part, c->stream);
+  launch_dav_rr(P.d_items, v.ibase, v.nitem, P.part, P.st, slot, c->stream);
+}
+
+void iteration(mbefci_ctx* c, Plan& P, const View& v) {
+  launch_dav_iteration(P.d_items, v.ibase, v.nitem, P.d_chunks + v.chunk_lo, v.nchunk, P.V, P.S,
+                       P.diag, P.ntot, P.st, P.part, c->opts.conv_tol, c->opts.max_iter,
+                       c->opts.max_space, c->stream);
+  add_vector(c, P, v, -1);
+}
+
+int count_active(mbefci_ctx* c, Plan& P, const View& v) {
+  launch_count_active(P.st, v.ibase, v.nitem, P.d_count, c->stream);
+  int h = 0;
+  HIPCHK(hipMemcpyAsync(&h, P.d_count, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return h;
+}
+
+// guess + iterations for the items of view v (hdiag and set-up already done)
+void solve_view(mbefci_ctx* c, Plan& P, const View& v, int* graph_launches) {
+  const int g = std::max(1, std::min(c->opts.nguess, 8));
+  launch_dav_guess(P.d_items, v.ibase, v.nitem, P.diag, P.V, P.ntot, P.st, g, c->stream);
+  for (int j = 0; j < g; ++j) add_vector(c, P, v, j);
+  const int max_iter = c->opts.max_iter;
+  if (v.item < 0 && c->opts.use_graph) {
+    const int K = 4;
+    if (!P.graph || P.graph_iters != K) {
+      if (P.graph) {
+        HIPCHK(hipGraphExecDestroy(P.graph));
+        P.graph = nullptr;
+      }
+      hipGraph_t gr;
+      HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      for (int k = 0; k < K; ++k) iteration(c, P, v);
+      HIPCHK(hipStreamEndCapture(c->stream, &gr));
+      HIPCHK(hipGraphInstantiate(&P.graph, gr, nullptr, nullptr, 0));
+      HIPCHK(hipGraphDestroy(gr));
+      P.graph_iters = K;
+    }
+    for (int it = 0; it < max_iter + K; it += K) {
+      HIPCHK(hipGraphLaunch(P.graph, c->stream));
+      if (graph_launches) ++*graph_launches;
+      if (count_active(c, P, v) == 0) break;
+    }
+  } else if (v.item < 0) {
+    const int K = 4;
+    for (int it = 0; it < max_iter + K; it += K) {
+      for (int k = 0; k < K; ++k) iteration(c, P, v);
+      if (count_active(c, P, v) == 0) break;
+    }
+  } else {
+    for (int it = 0; it < max_iter + 1; ++it) {
+      if (count_active(c, P, v) == 0) break;
+      iteration(c, P, v);
+    }
+  }
+  HIPCHK(hipGetLastError());
+}
+
+void solve_plan(mbefci_ctx* c, Plan& P, mbefci_stats* stats) {
+  const int g = std::max(1, std::min(c->opts.nguess, 8));
+  HIPCHK(hipEventRecord(c->t0, c->stream));
+  launch_hdiag(P.d_items, P.d_blocks, P.nblock, P.hams, P.diag, c->stream);
+  launch_fill(P.V, (int64_t)g * P.ntot, 0.0, c->stream);
+  int graph_launches = 0;
+  if (c->opts.mode == MBEFCI_PER_LAUNCH) {
+    for (int i = 0; i < P.nitem; ++i) solve_view(c, P, single(P, i), nullptr);
+  } else {
+    solve_view(c, P, whole(P), &graph_launches);
+  }
+  if (c->opts.keep_ci)
+    launch_ritz_vector(P.d_items, P.d_chunks, P.nchunk, P.V, P.ntot, P.st, P.ci, c->stream);
+  HIPCHK(hipEventRecord(c->t1, c->stream));
+  // statistics and convergence check
+  launch_collect(P.st, P.nitem, P.d_collect, c->stream);
+  std::vector<int32_t> col(4 * (size_t)P.nitem);
+  HIPCHK(hipMemcpyAsync(col.data(), P.d_collect, col.size() * sizeof(int32_t),
+                        hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  int first_failed = -1, max_iters = 0;
+  int64_t sig = 0;
+  for (int i = 0; i < P.nitem; ++i) {
+    max_iters = std::max(max_iters, col[4 * i]);
+    if (P.items[i].ndet > 1) sig += col[4 * i] + col[4 * i + 2];
+    if (col[4 * i + 1] == 1 && first_failed < 0) first_failed = i;
+  }
+  if (stats) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->t0, c->t1));
+    stats->ntuples = P.nitem;
+    stats->nsingle = P.nsingle;
+    stats->sigma_calls = sig;
+    stats->ndet_total = P.ndet_total;
+    stats->max_iters = max_iters;
+    stats->first_failed = first_failed;
+    stats->nbuckets = (int32_t)P.buckets.size();
+    stats->graph_launches = graph_launches;
+    stats->ms_solve = ms;
+  }
+  if (first_failed >= 0)
+    throw Error(MBEFCI_ENOTCONV, "Davidson did not converge for CASCI " +
+                                     std::to_string(first_failed) + " within " +
+                                     std::to_string(c->opts.max_iter) + " iterations");
+}
+
+// ------------------------------------------------------------ validation
+void check_integrals(mbefci_ctx* c, int M, const double* h1, const double* eri) {
+  if (!c->opts.validate) return;
+  const size_t n1 = (size_t)M * M, n2 = n1 * n1;
+  std::vector<double> h(n1), g(n2);
+  HIPCHK(hipMemcpyAsync(h.data(), h1, n1 * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(g.data(), eri, n2 * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double scale = 0.0;
+  for (double x : h) {
+    if (!std::isfinite(x)) throw Error(MBEFCI_EINVAL, "h1 holds a non-finite value");
+    scale = std::max(scale, std::fabs(x));
+  }
+  for (double x : g) {
+    if (!std::isfinite(x)) throw Error(MBEFCI_EINVAL, "eri holds a non-finite value");
+    scale = std::max(scale, std::fabs(x));
+  }
+  const double tol = 1e-12 * std::max(1.0, scale);
+  for (int p = 0; p < M; ++p)
+    for (int q = 0; q < M; ++q)
+      if (std::fabs(h[p * M + q] - h[q * M + p]) > tol)
+        throw Error(MBEFCI_EINVAL, "h1 is not symmetric");
+  auto G = [&](int p, int q, int r, int s) { return g[(((size_t)p * M + q) * M + r) * M + s]; };
+  for (int p = 0; p < M; ++p)
+    for (int q = 0; q < M; ++q)
+      for (int r = 0; r < M; ++r)
+        for (int s = 0; s < M; ++s) {
+          double v = G(p, q, r, s);
+          if (std::fabs(v - G(q, p, r, s)) > tol || std::fabs(v - G(p, q, s, r)) > tol ||
+              std::fabs(v - G(r, s, p, q)) > tol)
+            throw Error(MBEFCI_EINVAL, "eri lacks the 8-fold permutational symmetry");
+        }
+}
+
+struct StreamScope {  // order the library stream after the caller's and back
+  mbefci_ctx* c;
+  hipStream_t user;
+  StreamScope(mbefci_ctx* cc, void* s) : c(cc), user((hipStream_t)s) {
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipEventRecord(c->ev_in, user));
+    HIPCHK(hipStreamWaitEvent(c->stream, c->ev_in, 0));
+  }
+  void done() {
+    HIPCHK(hipEventRecord(c->ev_out, c->stream));
+    HIPCHK(hipStreamWaitEvent(user, c->ev_out, 0));
+  }
+};
+
+template <class F>
+int guarded(mbefci_ctx* c, F&& f) {
+  if (!c) return MBEFCI_EINVAL;
+  try {
+    c->err.clear();
+    f();
+    return MBEFCI_OK;
+  } catch (const Error& e) {
+    c->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    c->err = e.what();
+    return MBEFCI_EDEVICE;
+  }
+}
+
+void check_shape(int n, int na, int nb) {
+  if (n < 0 || n > kMaxActive || na < 0 || nb < 0 || na > n || nb > n)
+    throw Error(MBEFCI_EINVAL, "invalid CASCI shape (norb, nalpha, nbeta)");
+}
+
+// Build a plan of `nprob` identical-shape CASCIs and fold their Hamiltonians.
+void casci_plan(mbefci_ctx* c, int nprob, int n, int na, int nb, const double* const* h1s,
+                const double* const* eris, const double* ecore) {
+  check_shape(n, na, nb);
+  if (n > 14) throw Error(MBEFCI_EUNSUPPORTED, "active space exceeds 14 orbitals");
+  if (c->plan && c->plan->graph) HIPCHK(hipGraphExecDestroy(c->plan->graph));
+  c->plan.reset(new Plan());
+  Plan& P = *c->plan;
+  for (int i = 0; i < nprob; ++i) {
+    Item I{};
+    I.n = n;
+    I.na = na;
+    I.nb = nb;
+    P.items.push_back(I);
+  }
+  finalize_plan(c, P, c->opts.nguess);
+  const double** d_h = arena<const double*>(c, "hptr", nprob);
+  const double** d_g = arena<const double*>(c, "gptr", nprob);
+  double* d_e = arena<double>(c, "ecore", nprob);
+  std::vector<const double*> hv(h1s, h1s + nprob), gv(eris, eris + nprob);
+  std::vector<double> ev(ecore, ecore + nprob);
+  upload(c, d_h, hv);
+  upload(c, d_g, gv);
+  upload(c, d_e, ev);
+  launch_casci_setup(n, d_h, d_g, d_e, P.d_items, P.nitem, P.hams, P.W, c->stream);
+  HIPCHK(hipGetLastError());
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+void mbefci_default_opts(mbefci_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->conv_tol = 1e-6;
+  o->max_iter = 200;
+  o->max_space = 16;
+  o->nguess = 4;
+  o->mode = MBEFCI_BATCHED;
+  o->use_graph = 1;
+  o->tile = 0;
+  o->keep_ci = 1;
+  o->validate = 1;
+  o->max_workspace = 0;
+  o->tune_cache = nullptr;
+}
+
+static int check_opts(const mbefci_opts* o, std::string* why) {
+  if (!(o->conv_tol > 0)) { *why = "conv_tol must be positive"; return MBEFCI_EINVAL; }
+  if (o->max_iter < 1) { *why = "max_iter must be >= 1"; return MBEFCI_EINVAL; }
+  if (o->max_space < 2 || o->max_space > kMaxSpace) { *why = "max_space must be in 2..16"; return MBEFCI_EINVAL; }
+  if (o->nguess < 1 || o->nguess > 8 || o->nguess >= o->max_space) { *why = "nguess must be in 1..8 and below max_space"; return MBEFCI_EINVAL; }
+  if (o->mode != MBEFCI_BATCHED && o->mode != MBEFCI_PER_LAUNCH) { *why = "unknown mode"; return MBEFCI_EINVAL; }
+  if (o->tile != 0 && o->tile != 32 && o->tile != 64 && o->tile != 128) { *why = "tile must be 0, 32, 64 or 128"; return MBEFCI_EINVAL; }
+  return MBEFCI_OK;
+}
+
+int mbefci_create(int device, const mbefci_opts* opts, mbefci_ctx** out) {
+  if (!out) return MBEFCI_EINVAL;
+  *out = nullptr;
+  mbefci_opts o;
+  mbefci_default_opts(&o);
+  if (opts) o = *opts;
+  std::string why;
+  if (check_opts(&o, &why) != MBEFCI_OK) return MBEFCI_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return MBEFCI_EDEVICE;
+  }
+  auto* c = new mbefci_ctx();
+  c->device = device;
+  c->opts = o;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreate(&c->t0) != hipSuccess || hipEventCreate(&c->t1) != hipSuccess) {
+    delete c;
+    return MBEFCI_EDEVICE;
+  }
+  *out = c;
+  return MBEFCI_OK;
+}
+
+void mbefci_destroy(mbefci_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->plan && c->plan->graph) (void)hipGraphExecDestroy(c->plan->graph);
+  for (auto& kv : c->tabs)
+    if (kv.second.link) (void)hipFree(kv.second.link);
+  for (auto& kv : c->bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+  if (c->t0) (void)hipEventDestroy(c->t0);
+  if (c->t1) (void)hipEventDestroy(c->t1);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* mbefci_last_error(const mbefci_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int mbefci_set_opts(mbefci_ctx* c, const mbefci_opts* o) {
+  if (!c || !o) return MBEFCI_EINVAL;
+  std::string why;
+  int rc = check_opts(o, &why);
+  if (rc != MBEFCI_OK) {
+    c->err = why;
+    return rc;
+  }
+  bool plan_dead = o->max_space != c->opts.max_space || o->tile != c->opts.tile;
+  c->opts = *o;
+  if (plan_dead && c->plan) {
+    if (c->plan->graph) (void)hipGraphExecDestroy(c->plan->graph);
+    c->plan.reset();
+    c->have_forward = false;
+  }
+  return MBEFCI_OK;
+}
+
+int64_t mbefci_num_strings(int32_t norb, int32_t nelec) {
+  if (norb < 0 || norb > 64 || nelec < 0 || nelec > norb) return 0;
+  return binom_host(norb, nelec);
+}
+int32_t mbefci_num_links(int32_t norb, int32_t nelec) {
+  if (norb < 0 || norb > 64 || nelec < 0 || nelec > norb) return 0;
+  return nelec * (norb - nelec + 1);
+}
+int64_t mbefci_num_tuples(int32_t nexp, int32_t max_order) {
+  if (nexp < 0 || max_order < 0 || max_order > nexp || nexp > 64) return 0;
+  int64_t s = 0;
+  for (int n = 1; n <= max_order; ++n) s += binom_host(nexp, n);
+  return s;
+}
+
+int mbefci_strings(mbefci_ctx* c, int32_t norb, int32_t nelec, uint64_t* out, void* stream) {
+  return guarded(c, [&] {
+    if (norb < 0 || norb > 64 || nelec < 0 || nelec > norb || !out)
+      throw Error(MBEFCI_EINVAL, "invalid string shape");
+    StreamScope sc(c, stream);
+    launch_strings(norb, nelec, binom_host(norb, nelec), out, c->stream);
+    HIPCHK(hipGetLastError());
+    sc.done();
+  });
+}
+
+int mbefci_link_table(mbefci_ctx* c, int32_t norb, int32_t nelec, int32_t* out, void* stream) {
+  return guarded(c, [&] {
+    if (norb < 0 || norb > 32 || nelec < 0 || nelec > norb || !out)
+      throw Error(MBEFCI_EINVAL, "invalid link-table shape");
+    StreamScope sc(c, stream);
+    launch_links(norb, nelec, binom_host(norb, nelec), nullptr, out, c->stream);
+    HIPCHK(hipGetLastError());
+    sc.done();
+  });
+}
+
+int mbefci_hdiag(mbefci_ctx* c, int32_t n, int32_t na, int32_t nb, const double* h1,
+                 const double* eri, double e_core, double* diag, void* stream) {
+  return guarded(c, [&] {
+    check_shape(n, na, nb);
+    if (!h1 || !eri || !diag) throw Error(MBEFCI_EINVAL, "null pointer");
+    StreamScope sc(c, stream);
+    check_integrals(c, n, h1, eri);
+    casci_plan(c, 1, n, na, nb, &h1, &eri, &e_core);
+    Plan& P = *c->plan;
+    launch_hdiag(P.d_items, P.d_blocks, P.nblock, P.hams, P.diag, c->stream);
+    launch_add_scalar(diag, P.diag, e_core, P.items[0].ndet, c->stream);
+    HIPCHK(hipGetLastError());
+    c->have_forward = false;
+    sc.done();
+  });
+}
+
+int mbefci_sigma(mbefci_ctx* c, int32_t n, int32_t na, int32_t nb, const double* h1,
+                 const double* eri, double e_core, const double* cvec, double* sig, void* stream) {
+  return guarded(c, [&] {
+    check_shape(n, na, nb);
+    if (!h1 || !eri || !cvec || !sig) throw Error(MBEFCI_EINVAL, "null pointer");
+    StreamScope sc(c, stream);
+    check_integrals(c, n, h1, eri);
+    casci_plan(c, 1, n, na, nb, &h1, &eri, &e_core);
+    Plan& P = *c->plan;
+    const int64_t nd = P.items[0].ndet;
+    if (nd > 1) {
+      HIPCHK(hipMemcpyAsync(P.V, cvec, nd * 8, hipMemcpyDeviceToDevice, c->stream));
+      launch_state_single(P.st, c->stream);
+      sigma(c, P, whole(P), 0);
+      // e_core c is added here; the folded one- and two-body part is in S
+      launch_axpy_out(sig, P.S, cvec, e_core, nd, c->stream);
+    } else {
+      // a single determinant: sigma = H_00 c
+      launch_hdiag(P.d_items, P.d_blocks, P.nblock, P.hams, P.diag, c->stream);
+      launch_diag_times(sig, P.diag, cvec, e_core, 1, c->stream);
+    }
+    HIPCHK(hipGetLastError());
+    c->have_forward = false;
+    sc.done();
+  });
+}
+
+int mbefci_casci(mbefci_ctx* c, int32_t nprob, int32_t n, int32_t na, int32_t nb,
+                 const double* const* h1s, const double* const* eris, const double* e_core,
+                 double* e_out, double* const* ci_out, mbefci_stats* stats, void* stream) {
+  return guarded(c, [&] {
+    auto t_start = std::chrono::steady_clock::now();
+    check_shape(n, na, nb);
+    if (nprob < 1 || !h1s || !eris || !e_core || !e_out)
+      throw Error(MBEFCI_EINVAL, "invalid batch arguments");
+    StreamScope sc(c, stream);
+    for (int i = 0; i < nprob; ++i) {
+      if (!h1s[i] || !eris[i]) throw Error(MBEFCI_EINVAL, "null integral pointer");
+      check_integrals(c, n, h1s[i], eris[i]);
+    }
+    casci_plan(c, nprob, n, na, nb, h1s, eris, e_core);
+    Plan& P = *c->plan;
+    mbefci_stats st{};
+    solve_plan(c, P, &st);
+    launch_item_energy(P.d_items, P.hams, P.st, P.nitem, P.f, c->stream);
+    std::vector<double> e(nprob);
+    HIPCHK(hipMemcpyAsync(e.data(), P.f, nprob * 8, hipMemcpyDeviceToHost, c->stream));
+    if (ci_out && c->opts.keep_ci)
+      for (int i = 0; i < nprob; ++i)
+        if (ci_out[i])
+          HIPCHK(hipMemcpyAsync(ci_out[i], P.ci + P.items[i].off, P.items[i].ndet * 8,
+                                hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::copy(e.begin(), e.end(), e_out);
+    c->have_forward = true;
+    st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                            t_start).count();
+    if (stats) *stats = st;
+    sc.done();
+  });
+}
+
+int mbefci_casci_rdm(mbefci_ctx* c, double* const* rdm1s, double* const* rdm2s, void* stream) {
+  return guarded(c, [&] {
+    (void)rdm1s; (void)rdm2s; (void)stream;
+    throw Error(MBEFCI_EUNSUPPORTED, "casci RDMs are not built yet");
+  });
+}
+
+int mbefci_mbe_forward(mbefci_ctx* c, const mbefci_problem* pb, double* e_ref, double* e_order,
+                       double* e_total, double* tuple_incr, mbefci_stats* stats, void* stream) {
+  return guarded(c, [&] {
+    auto t_start = std::chrono::steady_clock::now();
+    if (!pb || !e_ref || !e_total || (pb->max_order > 0 && !e_order))
+      throw Error(MBEFCI_EINVAL, "null argument");
+    const int M = pb->norb;
+    if (M < 1 || M > kMaxOrb) throw Error(MBEFCI_EINVAL, "norb must be in 1..64");
+    if (!pb->h1 || !pb->eri) throw Error(MBEFCI_EINVAL, "null integrals");
+    if (pb->nocc < 0 || pb->nref < 0 || pb->nexp < 0 || pb->nocc > M || pb->nref > M ||
+        pb->nexp > M)
+      throw Error(MBEFCI_EINVAL, "orbital-set sizes out of range");
+    if (pb->max_order < 0 || pb->max_order > pb->nexp)
+      throw Error(MBEFCI_EINVAL, "max_order must be in 0..nexp");
+    std::vector<int> role(M, 0), occ(M, 0);
+    for (int i = 0; i < pb->nocc; ++i) {
+      int o = pb->occ[i];
+      if (o < 0 || o >= M || occ[o]) throw Error(MBEFCI_EINVAL, "bad occupied orbital list");
+      occ[o] = 1;
+    }
+    for (int i = 0; i < pb->nref; ++i) {
+      int o = pb->ref[i];
+      if (o < 0 || o >= M || role[o]) throw Error(MBEFCI_EINVAL, "bad reference space");
+      role[o] = 1;
+    }
+    for (int i = 0; i < pb->nexp; ++i) {
+      int o = pb->exp[i];
+      if (o < 0 || o >= M || role[o])
+        throw Error(MBEFCI_EINVAL, "expansion space must be distinct and disjoint from R");
+      role[o] = 2;
+    }
+    if (pb->nref + pb->max_order > 14)
+      throw Error(MBEFCI_EUNSUPPORTED, "|R| + max_order exceeds the compiled 14 active orbitals");
+    StreamScope sc(c, stream);
+    check_integrals(c, M, pb->h1, pb->eri);
+
+    // ---- plan (bucket by order and occupied count; items in bucket order)
+    std::string sig = std::to_string(M) + "|" + std::to_string(pb->max_order) + "|";
+    for (int i = 0; i < M; ++i) sig += char('0' + role[i] + 3 * occ[i]);
+    const bool reuse = c->plan && c->plan->is_mbe && c->plan->signature == sig;
+    if (!reuse) {
+      if (c->plan && c->plan->graph) HIPCHK(hipGraphExecDestroy(c->plan->graph));
+      c->plan.reset(new Plan());
+      Plan& P = *c->plan;
+      P.is_mbe = true;
+      P.signature = sig;
+      P.max_order = pb->max_order;
+      P.norb = M;
+      MbeSpaces& sp = P.sp;
+      std::memset(&sp, 0, sizeof(sp));
+      sp.M = M;
+      std::vector<int> R, Xo, Xv, O;
+      for (int o = 0; o < M; ++o) {
+        if (role[o] == 1) R.push_back(o);
+        if (role[o] == 2) (occ[o] ? Xo : Xv).push_back(o);
+        if (occ[o]) O.push_back(o);
+      }
+      sp.nR = (int)R.size();
+      sp.nXo = (int)Xo.size();
+      sp.nXv = (int)Xv.size();
+      sp.nO = (int)O.size();
+      std::copy(R.begin(), R.end(), sp.R);
+      std::copy(Xo.begin(), Xo.end(), sp.Xo);
+      std::copy(Xv.begin(), Xv.end(), sp.Xv);
+      std::copy(O.begin(), O.end(), sp.O);
+      int nref_occ = 0;
+      for (int o : R) nref_occ += occ[o];
+      sp.nocc_ref = nref_occ;
+      P.buckets.push_back(BucketDev{0, 0, 0, 1});
+      {
+        Item I{};
+        I.n = sp.nR;
+        I.na = I.nb = nref_occ;
+        P.items.push_back(I);
+      }
+      for (int n = 1; n <= pb->max_order; ++n)
+        for (int a = 0; a <= n; ++a) {
+          int64_t cnt = binom_host(sp.nXo, a) * binom_host(sp.nXv, n - a);
+          if (cnt == 0) continue;
+          P.buckets.push_back(BucketDev{n, a, (int64_t)P.items.size(), cnt});
+          for (int64_t k = 0; k < cnt; ++k) {
+            Item I{};
+            I.n = sp.nR + n;
+            I.na = I.nb = nref_occ + a;
+            P.items.push_back(I);
+          }
+        }
+      P.ntuples = (int64_t)P.items.size() - 1;
+      finalize_plan(c, P, c->opts.nguess);
+      P.d_buckets = arena<BucketDev>(c, "buckets", P.buckets.size());
+      upload(c, P.d_buckets, P.buckets);
+      P.tuple_pos = arena<int32_t>(c, "tuple_pos", (size_t)P.nitem * (2 * P.max_order + 2));
+      // X sorted; positions of Xo / Xv members in it (for lexicographic output)
+      std::vector<int> xs;
+      for (int o = 0; o < M; ++o)
+        if (role[o] == 2) xs.push_back(o);
+      P.xsorted = xs;
+      std::vector<int32_t> po(std::max(1, sp.nXo)), pv(std::max(1, sp.nXv));
+      for (int i = 0; i < sp.nXo; ++i)
+        po[i] = (int32_t)(std::find(xs.begin(), xs.end(), Xo[i]) - xs.begin());
+      for (int i = 0; i < sp.nXv; ++i)
+        pv[i] = (int32_t)(std::find(xs.begin(), xs.end(), Xv[i]) - xs.begin());
+      int32_t* d_po = arena<int32_t>(c, "xpos_o", po.size());
+      int32_t* d_pv = arena<int32_t>(c, "xpos_v", pv.size());
+      upload(c, d_po, po);
+      upload(c, d_pv, pv);
+      std::vector<int64_t> ooff(std::max(1, P.max_order));
+      int64_t acc = 0;
+      for (int n = 1; n <= P.max_order; ++n) {
+        ooff[n - 1] = acc;
+        acc += binom_host((int)xs.size(), n);
+      }
+      int64_t* d_oo = arena<int64_t>(c, "order_off", ooff.size());
+      upload(c, d_oo, ooff);
+    }
+    Plan& P = *c->plan;
+    // ---- set-up, solve, combine
+    launch_mbe_setup(&P.sp, P.d_buckets, (int)P.buckets.size(), P.d_items, P.nitem, pb->h1,
+                     pb->eri, pb->e_const, P.hams, P.W, P.tuple_pos, P.max_order, c->stream);
+    HIPCHK(hipGetLastError());
+    mbefci_stats st{};
+    solve_plan(c, P, &st);
+    launch_item_energy(P.d_items, P.hams, P.st, P.nitem, P.f, c->stream);
+    double* d_lex = arena<double>(c, "inc_lex", std::max<int64_t>(P.ntuples, 1));
+    double* d_eord = arena<double>(c, "e_order", std::max(P.max_order, 1));
+    double* d_tot = arena<double>(c, "e_tot", 2);
+    launch_mbe_combine(&P.sp, P.d_buckets, (int)P.buckets.size(), P.tuple_pos, P.max_order, P.f,
+                       P.nitem, P.inc, d_lex, static_cast<int64_t*>(c->bufs["order_off"].p),
+                       static_cast<int32_t*>(c->bufs["xpos_o"].p),
+                       static_cast<int32_t*>(c->bufs["xpos_v"].p), (int)P.xsorted.size(), d_eord,
+                       c->stream);
+    launch_mbe_total(P.f, d_eord, P.max_order, d_tot, c->stream);
+    HIPCHK(hipGetLastError());
+    double tot[2];
+    std::vector<double> eo(std::max(P.max_order, 1));
+    HIPCHK(hipMemcpyAsync(tot, d_tot, 16, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(eo.data(), d_eord, eo.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> lex;
+    if (tuple_incr && P.ntuples > 0) {
+      lex.resize(P.ntuples);
+      HIPCHK(hipMemcpyAsync(lex.data(), d_lex, P.ntuples * 8, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *e_ref = tot[0];
+    *e_total = tot[1];
+    for (int n = 0; n < P.max_order; ++n) e_order[n] = eo[n];
+    if (tuple_incr && P.ntuples > 0) std::copy(lex.begin(), lex.end(), tuple_incr);
+    c->have_forward = true;
+    st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                            t_start).count();
+    if (stats) *stats = st;
+    sc.done();
+  });
+}
+
+int mbefci_mbe_backward(mbefci_ctx* c, const double* grad_out, double* d_h1, double* d_eri,
+                        void* stream) {
+  return guarded(c, [&] {
+    (void)grad_out; (void)d_h1; (void)d_eri; (void)stream;
+    throw Error(MBEFCI_EUNSUPPORTED, "the backward is not built yet");
+  });
+}
+
+}  // extern "C"
