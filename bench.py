@@ -1,0 +1,238 @@
+#!/usr/bin/env python
+"""Throughput of the generalized MBE-FCI hot path on one MI355X.
+
+One step = one complete many-body-expanded FCI forward over the workload:
+tuple enumeration, frozen-core fold, strings/link tables (cached after the
+first call), diagonal + guesses, batched Davidson with sigma = Hc on FP64
+MFMA, and the Eq. 2 / Eq. 1 combine -- from device-resident integrals to
+E_ref, E^(n) and E_total on the host.
+
+Default workload: 1D Hubbard, 16 sites, open chain, t=1, U=4, half filling,
+a 6-MO reference space (3 occupied + 3 virtual MOs nearest the Fermi level),
+expansion over the other 10 MOs to order 4: 385 tuple CASCIs of 7..10
+orbitals (1,225..63,504 determinants) + the reference CASCI.
+
+Printed (one JSON line): batched CASCI solves/s (the headline value), the
+one-CASCI-per-launch rate on the same GPU at the same tolerance, the
+re-timed sigma kernels with their roofline fraction, and the CPU oracle timed
+on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import math
+import os
+import sys
+import time
+
+METRIC = "CASCI solves/s (batched vs per-launch) at 1e-9 Eh; σ-build GB/s vs HBM peak"
+HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E
+FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix
+
+
+def _buckets(prob):
+    occ = set(prob.occ)
+    xo = sorted(p for p in prob.exp if p in occ)
+    xv = sorted(p for p in prob.exp if p not in occ)
+    out = []
+    for n in range(1, prob.max_order + 1):
+        for a in range(0, n + 1):
+            cnt = math.comb(len(xo), a) * math.comb(len(xv), n - a)
+            if cnt:
+                out.append((n, a, cnt, tuple(sorted(xo[:a] + xv[:n - a]))))
+    return out
+
+
+def _oracle_job(args):
+    h, g, e_const, occ, active = args
+    from threadpoolctl import threadpool_limits
+    from oracle import fci
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        e = fci.casci(h, g, e_const, occ, active)
+        return e, time.perf_counter() - t0
+
+
+def cpu_baseline(prob, nsolve, workers):
+    """The CPU oracle (Slater-Condon CASCI, single-threaded per CASCI) on the
+    reference CASCI plus the first tuple of every bucket, run in parallel;
+    whole-workload rate extrapolated by bucket counts."""
+    from concurrent.futures import ProcessPoolExecutor
+    bks = _buckets(prob)
+    tups = [()] + [b[3] for b in bks]
+    jobs = [(prob.h1, prob.eri, prob.e_const, list(prob.occ), sorted(set(prob.ref) | set(t)))
+            for t in tups]
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        res = list(ex.map(_oracle_job, jobs))
+    wall = time.perf_counter() - t0
+    core_s = res[0][1] + sum(b[2] * r[1] for b, r in zip(bks, res[1:]))
+    return {
+        "value": nsolve / (core_s / workers),
+        "unit": "CASCI solves/s",
+        "cores": workers,
+        "kind": "oracle",
+        "sample": (f"reference CASCI + first tuple of each of {len(bks)} (order, n_occ) buckets "
+                   f"({len(tups)} CASCIs, {wall:.1f} s wall on {workers} processes, one thread "
+                   f"each); whole workload = sum over buckets of count x sampled time = "
+                   f"{core_s:.0f} core-s, spread over {workers} cores"),
+        "core_seconds_estimate": core_s,
+    }, dict(zip(tups, [r[0] for r in res]))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="hubbard16")
+    ap.add_argument("--per-launch-steps", type=int, default=1)
+    ap.add_argument("--reps", type=int, default=5, help="kernel re-timing repetitions")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--sigma-pass-mb", type=int, default=0)
+    ap.add_argument("--kernel-replay", action="store_true",
+                    help="profiling mode: a forward that stops after the guess sigma sweeps, then "
+                         "only the sigma-sweep replays (every sigma launch does the same work)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1910_03527_amd import PER_LAUNCH, BATCHED, Context
+
+    prob = W.problem(args.workload)
+    nsolve_expected = 1 + sum(math.comb(len(prob.exp), n) for n in range(1, prob.max_order + 1))
+    # the oracle runs first, in worker processes forked before this process
+    # touches the GPU
+    cb = fo = None
+    if not args.no_cpu_baseline:
+        workers = max(1, min(16, os.cpu_count() or 1))
+        cb, fo = cpu_baseline(prob, nsolve_expected, workers)
+
+    dev = torch.device("cuda", 0)
+    h1 = torch.as_tensor(prob.h1, dtype=torch.float64, device=dev)
+    eri = torch.as_tensor(prob.eri, dtype=torch.float64, device=dev)
+    ctx = Context(0, tile=args.tile, sigma_pass_mb=args.sigma_pass_mb)
+    if args.kernel_replay:
+        # residual tolerance above any residual: every CASCI stops after the
+        # guess sweeps, so each sigma launch of this process covers all CASCIs
+        ctx.set_opts(conv_tol=1e3)
+        ctx.mbe_forward(h1, eri, prob.occ, prob.ref, prob.exp, prob.max_order, prob.e_const)
+        kt = ctx.time_kernels(args.reps)
+        # calibration for HBM byte counters: one plain device copy of 512 MiB
+        src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "kernel-replay", "copy_bytes_each_way": src.numel() * 8, "workload": args.workload,
+                          "sigma_pass_mb": args.sigma_pass_mb, "reps": args.reps,
+                          "kernels": kt}), flush=True)
+        return
+
+    def step():
+        return ctx.mbe_forward(h1, eri, prob.occ, prob.ref, prob.exp, prob.max_order,
+                               prob.e_const, want_increments=True)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    stats = dict(ctx.last_stats)
+    nsolve = int(stats["ntuples"])
+    value = nsolve / (ms / 1e3)
+
+    # one CASCI per launch sequence, same kernels, same tolerance
+    per_launch = None
+    if args.per_launch_steps > 0:
+        ctx.set_opts(mode=PER_LAUNCH)
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.per_launch_steps):
+            res_pl = step()
+        torch.cuda.synchronize()
+        ms_pl = (time.perf_counter() - t0) * 1e3 / args.per_launch_steps
+        ctx.set_opts(mode=BATCHED)
+        step()
+        dmax = float(np.max(np.abs(np.array(res_pl["energies"]) - np.array(res["energies"]))))
+        per_launch = {"value": round(nsolve / (ms_pl / 1e3), 2), "ms_per_step": round(ms_pl, 3),
+                      "batched_speedup": round(ms_pl / ms, 2),
+                      "max_abs_energy_diff_vs_batched": dmax}
+
+    # sigma kernels re-timed on the library stream (HIP events)
+    kt = ctx.time_kernels(args.reps)
+    for k in kt:
+        k["tflops"] = k["flops"] / (k["ms_per_launch"] * 1e-3) / 1e12
+        k["gbps"] = k["bytes"] / (k["ms_per_launch"] * 1e-3) / 1e9
+    dom = max(kt, key=lambda k: k["ms_per_launch"] * k["launches"])
+    if dom["name"].startswith("sigma_dgemm"):
+        roof = {"kernel": dom["name"], "bound": "mfma", "achieved": round(dom["tflops"], 3),
+                "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(dom["tflops"] / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                "ms_per_launch": dom["ms_per_launch"], "launches_per_sweep": dom["launches"],
+                "algorithmic_flops": dom["flops"], "algorithmic_bytes": dom["bytes"]}
+    else:
+        roof = {"kernel": dom["name"], "bound": "hbm", "achieved": round(dom["gbps"], 1),
+                "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(dom["gbps"] / HBM_PEAK_GBPS, 4), "traffic": None,
+                "ms_per_launch": dom["ms_per_launch"], "launches_per_sweep": dom["launches"],
+                "algorithmic_bytes": dom["bytes"]}
+    sig_ms = sum(k["ms_per_launch"] * k["launches"] for k in kt)
+    sig_bytes = sum(k["bytes"] * k["launches"] for k in kt)
+    sig_flops = sum(k["flops"] * k["launches"] for k in kt)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "CASCI solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}-mbe{prob.max_order}", "norb": prob.norb,
+                   "nref": len(prob.ref), "nexp": len(prob.exp), "max_order": prob.max_order,
+                   "ncasci": nsolve, "nsingle": stats["nsingle"],
+                   "ndet_total": stats["ndet_total"], "buckets": stats["nbuckets"],
+                   "conv_tol": ctx.opts["conv_tol"], "nguess": ctx.opts["nguess"],
+                   "sigma_pass_mb": ctx.opts["sigma_pass_mb"], "mode": "batched"},
+        "per_launch": per_launch,
+        "solver": {"sigma_calls": stats["sigma_calls"], "max_iters": stats["max_iters"],
+                   "graph_launches": stats["graph_launches"], "ms_solve": stats["ms_solve"],
+                   "e_total": res["e_total"]},
+        "sigma_build": {"ms_per_sweep": round(sig_ms, 4),
+                        "gbps_algorithmic": round(sig_bytes / (sig_ms * 1e-3) / 1e9, 1),
+                        "frac_hbm": round(sig_bytes / (sig_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                        "tflops_mfma": round(sig_flops / (sig_ms * 1e-3) / 1e12, 3)},
+        "kernels": [{k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in k.items()}
+                    for k in kt],
+        "roofline": roof,
+    }
+    if cb is not None:
+        tl = list(itertools.chain.from_iterable(
+            itertools.combinations(sorted(prob.exp), n) for n in range(1, prob.max_order + 1)))
+        idx = {t: i for i, t in enumerate(tl)}
+        diffs = [abs(res["energies"][idx[t]] - e) for t, e in fo.items() if t]
+        diffs.append(abs(res["e_ref"] - fo[()]))
+        cb["gpu_vs_oracle_max_abs_energy_diff"] = max(diffs)
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

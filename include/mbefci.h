@@ -60,12 +60,17 @@ typedef struct {
   double conv_tol;       /* Davidson residual 2-norm tolerance (default 1e-6)       */
   int32_t max_iter;      /* Davidson iterations per CASCI (default 200)              */
   int32_t max_space;     /* subspace size before restart, 2..16 (default 16)        */
-  int32_t nguess;        /* lowest-diagonal unit guess vectors, 1..8 (default 4)    */
+  int32_t nguess;        /* lowest-diagonal unit guess vectors, 1..8 (default 2)    */
   int32_t mode;          /* MBEFCI_BATCHED (default) or MBEFCI_PER_LAUNCH            */
   int32_t use_graph;     /* batched mode: replay captured iterations (default 1)     */
   int32_t tile;          /* sigma tile width 32/64/128, 0 = autotuned (default 0)    */
   int32_t keep_ci;       /* keep converged CI vectors for the backward (default 1)   */
   int32_t validate;      /* host checks of integral symmetry/finiteness (default 1)  */
+  int32_t sigma_pass_mb; /* sigma sweeps run in passes whose G block (the W-contracted
+                            pair array) stays below this many MiB, so that it is
+                            re-read from the on-die cache and its memory is bounded;
+                            0 = one pass (default 0) */
+  int32_t pad_;
   int64_t max_workspace; /* workspace cap in bytes, 0 = no cap                       */
   const char* tune_cache;/* autotuner cache file (read/written) or NULL              */
 } mbefci_opts;
@@ -157,16 +162,35 @@ int mbefci_casci_rdm(mbefci_ctx* ctx, double* const* rdm1s, double* const* rdm2s
  * 1..max_order expansion orbitals, then forms the increments of Eq. 2 and the
  * order sums of Eq. 1.  Outputs (host): e_ref, e_order [max_order],
  * e_total = e_ref + sum e_order, tuple_incr [num_tuples] or NULL (order by
- * order, lexicographic tuples of the sorted X within an order).  Converged
+ * order, lexicographic tuples of the sorted X within an order) and
+ * tuple_energy [num_tuples] or NULL (the CASCI energies E(R u T), same order).  Converged
  * CI vectors are kept on ctx for mbefci_mbe_backward when keep_ci is set. */
 int mbefci_mbe_forward(mbefci_ctx* ctx, const mbefci_problem* prob, double* e_ref,
-                       double* e_order, double* e_total, double* tuple_incr, mbefci_stats* stats,
-                       void* hip_stream);
+                       double* e_order, double* e_total, double* tuple_incr,
+                       double* tuple_energy, mbefci_stats* stats, void* hip_stream);
 /* Gradient of L = g[0] E_ref + sum_n g[n] E^(n) (g host [1+max_order]) of the
  * last forward on ctx with respect to the MO integrals: d_h1 device [M*M]
  * (symmetric) and d_eri device [M^4] (8-fold symmetrised); both overwritten. */
 int mbefci_mbe_backward(mbefci_ctx* ctx, const double* grad_out, double* d_h1, double* d_eri,
                         void* hip_stream);
+
+/* ---- measurement ----------------------------------------------------------
+ * Re-times the sigma = Hc kernels of the last mbefci_casci / mbefci_mbe_forward
+ * on ctx: each kernel of one sigma sweep over the whole batch is replayed
+ * `reps` times between HIP events on the library stream (the stream the
+ * kernels run on).  Replays recompute identical values; the results of the
+ * last call are unchanged.  Fills up to `cap` records, *count = records. */
+typedef struct {
+  char name[64];          /* kernel and shape, e.g. "sigma_dgemm<n=10,tile=64>"       */
+  int32_t launches;       /* launches of this kernel in one sigma sweep               */
+  int32_t pad_;
+  double ms_per_launch;   /* average device time of one launch                        */
+  double flops;           /* algorithmic flops of one launch (average)                */
+  double bytes;           /* algorithmic HBM bytes of one launch (average)            */
+  double ndet;            /* determinants processed by one launch (average)           */
+} mbefci_kernel_time;
+int mbefci_time_kernels(mbefci_ctx* ctx, int32_t reps, mbefci_kernel_time* out, int32_t cap,
+                        int32_t* count);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,7 @@ EXPORTS = (
     "mbefci_default_opts", "mbefci_create", "mbefci_destroy", "mbefci_last_error",
     "mbefci_set_opts", "mbefci_num_strings", "mbefci_num_links", "mbefci_strings",
     "mbefci_link_table", "mbefci_num_tuples", "mbefci_hdiag", "mbefci_sigma", "mbefci_casci",
-    "mbefci_casci_rdm", "mbefci_mbe_forward", "mbefci_mbe_backward",
+    "mbefci_casci_rdm", "mbefci_mbe_forward", "mbefci_mbe_backward", "mbefci_time_kernels",
 )
 
 
@@ -37,6 +37,8 @@ class Opts(ctypes.Structure):
         ("tile", ctypes.c_int32),
         ("keep_ci", ctypes.c_int32),
         ("validate", ctypes.c_int32),
+        ("sigma_pass_mb", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
         ("max_workspace", ctypes.c_int64),
         ("tune_cache", ctypes.c_char_p),
     ]
@@ -74,6 +76,23 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 64),
+        ("launches", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("ms_per_launch", ctypes.c_double),
+        ("flops", ctypes.c_double),
+        ("bytes", ctypes.c_double),
+        ("ndet", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {"name": self.name.decode(), "launches": self.launches,
+                "ms_per_launch": self.ms_per_launch, "flops": self.flops, "bytes": self.bytes,
+                "ndet": self.ndet}
 
 
 _lib = None
@@ -120,10 +139,14 @@ def load():
     L.mbefci_casci_rdm.restype = ctypes.c_int
     L.mbefci_mbe_forward.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(dbl),
                                      ctypes.POINTER(dbl), ctypes.POINTER(dbl),
-                                     ctypes.POINTER(dbl), ctypes.POINTER(Stats), vp]
+                                     ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                     ctypes.POINTER(Stats), vp]
     L.mbefci_mbe_forward.restype = ctypes.c_int
     L.mbefci_mbe_backward.argtypes = [vp, ctypes.POINTER(dbl), vp, vp, vp]
     L.mbefci_mbe_backward.restype = ctypes.c_int
+    L.mbefci_time_kernels.argtypes = [vp, i32, ctypes.POINTER(KernelTime), i32,
+                                      ctypes.POINTER(i32)]
+    L.mbefci_time_kernels.restype = ctypes.c_int
     _lib = L
     return L
 

@@ -205,16 +205,27 @@ class Context:
         e_ord = (ctypes.c_double * max(1, max_order))()
         nt = num_tuples(len(exp), max_order)
         inc = (ctypes.c_double * max(1, nt))() if want_increments else None
+        fen = (ctypes.c_double * max(1, nt))() if want_increments else None
         st = _lib.Stats()
         self._check(self._L.mbefci_mbe_forward(self._h, ctypes.byref(pb), ctypes.byref(e_ref),
-                                               e_ord, ctypes.byref(e_tot), inc, ctypes.byref(st),
-                                               self._stream()))
+                                               e_ord, ctypes.byref(e_tot), inc, fen,
+                                               ctypes.byref(st), self._stream()))
         self.last_stats = st.as_dict()
         self._fwd = (M, max_order)
         out = {"e_ref": e_ref.value, "e_order": list(e_ord)[:max_order], "e_total": e_tot.value}
         if want_increments:
             out["increments"] = list(inc)[:nt]
+            out["energies"] = list(fen)[:nt]
         return out
+
+    def time_kernels(self, reps: int = 5):
+        """Per-launch device times of the sigma kernels of the last forward
+        (mbefci_time_kernels): list of dicts."""
+        cap = 64
+        arr = (_lib.KernelTime * cap)()
+        cnt = ctypes.c_int32()
+        self._check(self._L.mbefci_time_kernels(self._h, int(reps), arr, cap, ctypes.byref(cnt)))
+        return [arr[i].as_dict() for i in range(min(cnt.value, cap))]
 
     def mbe_backward(self, grad_out):
         """d(g0 E_ref + sum_n g_n E^(n)) / d(h1, eri) of the last forward."""

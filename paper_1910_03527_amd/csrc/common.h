@@ -33,6 +33,13 @@ __host__ __device__ inline int pair_index(int p, int q) {
   return a * (a + 1) / 2 + b;
 }
 
+// Load through the global address space (pointers read from device structs
+// are generic; this keeps the loads off the flat path).
+template <class T>
+__device__ inline T ldg(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+
 // One CASCI problem inside a batch.
 struct Item {
   int32_t n, na, nb, npair;
@@ -48,7 +55,19 @@ struct Item {
   int32_t pad_;
   const uint32_t* linkA;  // [Na][La]
   const uint32_t* linkB;  // [Nb][Lb]
+  const uint64_t* strA;   // [Na] alpha string bitmasks
+  const uint64_t* strB;   // [Nb] beta string bitmasks
+  const int32_t* pairA;   // [Na][npair] pair table (see pack_pair_entry)
+  const int32_t* pairB;   // [npair][Nb] the same for beta strings, pair-major
 };
+
+// Pair table entry of string K and orbital pair (a >= b): the single
+// excitation among E_ab K, E_ba K that does not vanish (at most one does for
+// a != b; E_aa K = K when a is occupied), stored as ((J + 1) << 1) | neg,
+// 0 when both vanish.
+__host__ __device__ inline int32_t pack_pair_entry(int J, int sign) {
+  return ((J + 1) << 1) | (sign < 0 ? 1 : 0);
+}
 
 // Active-space Hamiltonian of one CASCI after the frozen-core fold.
 struct ItemHam {

@@ -120,6 +120,33 @@ __global__ void k_links(int n, int ne, int64_t N, uint32_t* packed, int32_t* abi
   }
 }
 
+// One thread per string K: for every orbital pair a >= b the non-vanishing
+// member of {E_ab K, E_ba K} (see pack_pair_entry).
+__global__ void k_pair_table(int n, int ne, int64_t N, int32_t* out, int32_t* outT) {
+  int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (K >= N) return;
+  const int npair = n * (n + 1) / 2;
+  const uint64_t m = string_unrank(K, n, ne);
+  int32_t* row = out + K * npair;
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b <= a; ++b) {
+      int32_t v = 0;
+      const bool ia = m >> a & 1, ib = m >> b & 1;
+      if (a == b) {
+        if (ia) v = pack_pair_entry((int)K, 1);
+      } else if (ia != ib) {
+        // move the electron from the occupied one of (a, b) to the empty one
+        const int q = ia ? a : b, p = ia ? b : a;
+        const uint64_t r = (m & ~((uint64_t)1 << q)) | ((uint64_t)1 << p);
+        const uint64_t between = (((uint64_t)1 << a) - 1) & ~((((uint64_t)1 << b) << 1) - 1);
+        const int sign = (__builtin_popcountll(m & between) & 1) ? -1 : 1;
+        v = pack_pair_entry((int)string_addr(r), sign);
+      }
+      row[a * (a + 1) / 2 + b] = v;
+      outT[(int64_t)(a * (a + 1) / 2 + b) * N + K] = v;
+    }
+}
+
 // ------------------------------------------------------- Hamiltonian set-up
 // Frozen-core fold of the full-space Hamiltonian onto the active set A of one
 // CASCI (frozen F = O \ A doubly occupied, all other orbitals deleted):
@@ -285,7 +312,7 @@ __global__ void k_hdiag(const Item* __restrict__ items, const Work* __restrict__
   if (K >= I.ndet) return;
   const ItemHam& H = hams[I.ham];
   const int Ka = (int)(K / I.Nb), Kb = (int)(K % I.Nb);
-  uint64_t ma = string_unrank(Ka, I.n, I.na), mb = string_unrank(Kb, I.n, I.nb);
+  const uint64_t ma = I.strA[Ka], mb = I.strB[Kb];
   double e = 0.0;
   for (uint64_t x = ma; x; x &= x - 1) {
     int p = __builtin_ctzll(x);
@@ -335,12 +362,13 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
   constexpr int NP = NACT * (NACT + 1) / 2;
   constexpr int KPAD = (NP + 15) / 16 * 16;
   constexpr int KS = (NP + 3) / 4;       // MFMA k-steps (4 per step)
+  constexpr int KR = KS * 4;             // D+ rows held in LDS (zero beyond NP)
   constexpr int NRB = KPAD / 16;         // 16-row blocks of G
   constexpr int RBW = (NRB + 3) / 4;     // row blocks per wave
   constexpr int NCB = TN / 16;           // 16-column blocks per tile
   constexpr int NSUB = 256 / TN;
   constexpr int LDT = TN + 1;            // padded LDS row (doubles)
-  __shared__ double Ds[KS * 4 * LDT];
+  __shared__ double Ds[KR * LDT];
 
   const Work wk = work[blockIdx.x];
   const Item& I = items[wk.item];
@@ -349,11 +377,15 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
   const int vs = vec_slot(S, slot);
   const double* __restrict__ c = V + (int64_t)vs * ntot + I.off;
   double* __restrict__ G = Garena + I.goff;
-  const int Nb = I.Nb, La = I.La, Lb = I.Lb;
+  const int Nb = I.Nb;
   const int64_t ndet = I.ndet;
+  const int32_t* __restrict__ pA = I.pairA;
+  const int32_t* __restrict__ pB = I.pairB;
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int col = t % TN, sub = t / TN;
+  const int col = t % TN;
+  // row group of the D+ gather; wave-uniform when a tile row spans a wave
+  const int sub = (TN == 64) ? __builtin_amdgcn_readfirstlane(t / TN) : t / TN;
 
   // W rows of this wave's row blocks, as MFMA A operands: lane l holds
   // W[rb*16 + l%16][ks*4 + l/16] (B operand: lane l holds D+[ks*4 + l/16][l%16])
@@ -367,27 +399,33 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
       wreg[r][ks] = (rb < NRB) ? W[(rb * 16 + (lane & 15)) * KPAD + ks * 4 + (lane >> 4)] : 0.0;
   }
 
+  // padding rows NP..KR-1 of the D+ tile stay zero for every tile
+  for (int x = NP * LDT + t; x < KR * LDT; x += 256) Ds[x] = 0.0;
+  constexpr int NPER = (NP + NSUB - 1) / NSUB;  // D+ rows per thread
+  const int nd32 = (int)ndet;                    // every CASCI has < 2^31 determinants
+
   for (int tile = wk.begin; tile < wk.end; ++tile) {
     const int64_t K0 = (int64_t)tile * TN;
-    for (int x = t; x < KS * 4 * LDT; x += 256) Ds[x] = 0.0;
-    __syncthreads();
-    const int64_t K = K0 + col;
-    const bool valid = K < ndet;
-    const int Ka = valid ? (int)(K / Nb) : 0, Kb = valid ? (int)(K % Nb) : 0;
-    if (valid) {
-      const uint32_t* la = I.linkA + (int64_t)Ka * La;
-      for (int l = sub; l < La; l += NSUB) {
-        uint32_t e = la[l];
-        Ds[link_pair(e) * LDT + col] += link_sign(e) * c[(int64_t)link_addr(e) * Nb + Kb];
-      }
-    }
-    __syncthreads();
-    if (valid) {
-      const uint32_t* lb = I.linkB + (int64_t)Kb * Lb;
-      const double* crow = c + (int64_t)Ka * Nb;
-      for (int l = sub; l < Lb; l += NSUB) {
-        uint32_t e = lb[l];
-        Ds[link_pair(e) * LDT + col] += link_sign(e) * crow[link_addr(e)];
+    const int Kraw = (int)K0 + col;
+    const double keep = Kraw < nd32 ? 1.0 : 0.0;  // ragged last tile: zero columns
+    const int Kc = Kraw < nd32 ? Kraw : nd32 - 1;
+    const int Ka = Kc / Nb, Kb = Kc - Ka * Nb;
+    const int32_t* __restrict__ pa = pA + Ka * NP;
+    const int32_t* __restrict__ pb = pB + Kb;   // pair-major: entry ab at pb[ab * Nb]
+    const double* __restrict__ ca = c + Kb;     // alpha source: ca[Ja * Nb]
+    const double* __restrict__ cb = c + Ka * Nb;  // beta source: cb[Jb]
+    // D+[ab][col] = (alpha excitation) + (beta excitation) of pair ab, branch
+    // free: a vanishing excitation loads a valid element and scales it by 0
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) {
+      const int ab = sub + NSUB * i;
+      if (ab < NP) {
+        const int32_t ea = ldg(pa + ab), eb = ldg(pb + ab * Nb);
+        const int ja = ea ? (ea >> 1) - 1 : 0, jb = eb ? (eb >> 1) - 1 : 0;
+        const double fa = ea ? ((ea & 1) ? -keep : keep) : 0.0;
+        const double fb = eb ? ((eb & 1) ? -keep : keep) : 0.0;
+        const double xa = ldg(ca + ja * Nb), xb = ldg(cb + jb);
+        Ds[ab * LDT + col] = fa * xa + fb * xb;
       }
     }
     __syncthreads();
@@ -395,14 +433,19 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
     for (int r = 0; r < RBW; ++r) {
       const int rb = wave + 4 * r;
       if (rb >= NRB) continue;
+      double4_t acc[NCB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[cb] = (double4_t){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const double* brow = Ds + (ks * 4 + (lane >> 4)) * LDT + (lane & 15);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(wreg[r][ks], brow[cb * 16], acc[cb], 0,
+                                                         0, 0);
+      }
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
-        double4_t acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          const double b = Ds[(ks * 4 + (lane >> 4)) * LDT + cb * 16 + (lane & 15)];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wreg[r][ks], b, acc, 0, 0, 0);
-        }
         const int64_t Kc = K0 + cb * 16 + (lane & 15);
         if (Kc < ndet) {
 #pragma unroll
@@ -410,7 +453,7 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
             // gfx950 FP64 16x16x4 output layout: register v of lane l is
             // row l/16 + 4v, column l%16 of the 16x16 block
             const int row = rb * 16 + (lane >> 4) + 4 * v;
-            if (row < NP) G[(int64_t)row * ndet + Kc] = acc[v];
+            if (row < NP) G[(int64_t)row * ndet + Kc] = acc[cb][v];
           }
         }
       }
@@ -420,6 +463,9 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
 }
 
 // sigma_I = sum_{links (x,y,J,s) of Ia} s G_xy[J, Ib] + sum_{links of Ib} s G_xy[Ia, J]
+// One wave per 64-determinant segment of one alpha row (segments are
+// row-aligned), so the alpha string and its links are wave-uniform (scalar
+// loads) and the alpha-part reads of G are coalesced rows.
 __global__ void __launch_bounds__(256) k_sigma_gather(const Item* __restrict__ items,
                                                       const Work* __restrict__ work,
                                                       const double* __restrict__ Garena,
@@ -430,25 +476,50 @@ __global__ void __launch_bounds__(256) k_sigma_gather(const Item* __restrict__ i
   const DavState& S = st[wk.item];
   if (!item_active(S, slot)) return;
   const int vs = vec_slot(S, slot);
-  const int64_t K = (int64_t)wk.begin * 256 + threadIdx.x;
-  if (K >= I.ndet) return;
   const int Nb = I.Nb;
-  const int Ka = (int)(K / Nb), Kb = (int)(K % Nb);
+  const int segs = (Nb + 63) >> 6;  // segments per alpha row
+  const int seg = __builtin_amdgcn_readfirstlane(wk.begin * 4 + (threadIdx.x >> 6));
+  if (seg >= wk.end) return;
+  const int Ka = __builtin_amdgcn_readfirstlane(seg / segs);
+  const int Kb = (seg % segs) * 64 + (threadIdx.x & 63);
+  if (Kb >= Nb) return;
   const double* __restrict__ G = Garena + I.goff;
   const int64_t nd = I.ndet;
-  double acc = 0.0;
-  const uint32_t* la = I.linkA + (int64_t)Ka * I.La;
-  for (int l = 0; l < I.La; ++l) {
-    uint32_t e = la[l];
-    acc += link_sign(e) * G[(int64_t)link_pair(e) * nd + (int64_t)link_addr(e) * Nb + Kb];
+  const int La = I.La, Lb = I.Lb;
+  double acc0 = 0.0, acc1 = 0.0;
+  const uint32_t* __restrict__ la = I.linkA + Ka * La;
+  const double* __restrict__ Gcol = G + Kb;
+  int l = 0;
+  for (; l + 3 < La; l += 4) {
+    const uint32_t e0 = ldg(la + l), e1 = ldg(la + l + 1), e2 = ldg(la + l + 2), e3 = ldg(la + l + 3);
+    const double g0 = ldg(Gcol + (int64_t)link_pair(e0) * nd + link_addr(e0) * Nb);
+    const double g1 = ldg(Gcol + (int64_t)link_pair(e1) * nd + link_addr(e1) * Nb);
+    const double g2 = ldg(Gcol + (int64_t)link_pair(e2) * nd + link_addr(e2) * Nb);
+    const double g3 = ldg(Gcol + (int64_t)link_pair(e3) * nd + link_addr(e3) * Nb);
+    acc0 += link_sign(e0) * g0 + link_sign(e2) * g2;
+    acc1 += link_sign(e1) * g1 + link_sign(e3) * g3;
   }
-  const uint32_t* lb = I.linkB + (int64_t)Kb * I.Lb;
-  const int64_t rowoff = (int64_t)Ka * Nb;
-  for (int l = 0; l < I.Lb; ++l) {
-    uint32_t e = lb[l];
-    acc += link_sign(e) * G[(int64_t)link_pair(e) * nd + rowoff + link_addr(e)];
+  for (; l < La; ++l) {
+    const uint32_t e0 = ldg(la + l);
+    acc0 += link_sign(e0) * ldg(Gcol + (int64_t)link_pair(e0) * nd + link_addr(e0) * Nb);
   }
-  Sarena[(int64_t)vs * ntot + I.off + K] = acc;
+  const uint32_t* __restrict__ lb = I.linkB + Kb * Lb;
+  const double* __restrict__ Grow = G + Ka * Nb;
+  l = 0;
+  for (; l + 3 < Lb; l += 4) {
+    const uint32_t e0 = ldg(lb + l), e1 = ldg(lb + l + 1), e2 = ldg(lb + l + 2), e3 = ldg(lb + l + 3);
+    const double g0 = ldg(Grow + (int64_t)link_pair(e0) * nd + link_addr(e0));
+    const double g1 = ldg(Grow + (int64_t)link_pair(e1) * nd + link_addr(e1));
+    const double g2 = ldg(Grow + (int64_t)link_pair(e2) * nd + link_addr(e2));
+    const double g3 = ldg(Grow + (int64_t)link_pair(e3) * nd + link_addr(e3));
+    acc0 += link_sign(e0) * g0 + link_sign(e2) * g2;
+    acc1 += link_sign(e1) * g1 + link_sign(e3) * g3;
+  }
+  for (; l < Lb; ++l) {
+    const uint32_t e0 = ldg(lb + l);
+    acc0 += link_sign(e0) * ldg(Grow + (int64_t)link_pair(e0) * nd + link_addr(e0));
+  }
+  Sarena[(int64_t)vs * ntot + I.off + (int64_t)Ka * Nb + Kb] = acc0 + acc1;
 }
 
 // ---------------------------------------------------------------- Davidson
@@ -503,29 +574,35 @@ __global__ void k_dav_guess(const Item* __restrict__ items, int ibase,
       bv[p] = x; bi[p] = K;
     }
   }
-  __shared__ double sv[256 * G];
-  __shared__ int64_t si[256 * G];
-  for (int g = 0; g < G; ++g) { sv[t * G + g] = bv[g]; si[t * G + g] = bi[g]; }
-  __syncthreads();
-  if (t == 0) {
-    int g = nguess < G ? nguess : G;
-    if (g > I.ndet) g = (int)I.ndet;
-    int64_t pick[G];
-    for (int k = 0; k < g; ++k) {
-      double best = 1e301;
-      int64_t bidx = INT64_MAX;
-      for (int x = 0; x < (int)blockDim.x * G; ++x) {
-        double v = sv[x];
-        int64_t id = si[x];
-        if (id == INT64_MAX) continue;
-        bool used = false;
-        for (int j = 0; j < k; ++j) used |= (pick[j] == id);
-        if (used) continue;
-        if (v < best || (v == best && id < bidx)) { best = v; bidx = id; }
+  // g rounds of a block-wide argmin over the heads of the per-thread lists
+  __shared__ double rv[256];
+  __shared__ int64_t ri[256];
+  __shared__ int rth[256];
+  int g = nguess < G ? nguess : G;
+  if (g > I.ndet) g = (int)I.ndet;
+  int head = 0;
+  for (int k = 0; k < g; ++k) {
+    rv[t] = head < G ? bv[head] : 1e300;
+    ri[t] = head < G ? bi[head] : INT64_MAX;
+    rth[t] = t;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w) {
+        const double v2 = rv[t + w];
+        const int64_t i2 = ri[t + w];
+        if (v2 < rv[t] || (v2 == rv[t] && i2 < ri[t])) {
+          rv[t] = v2;
+          ri[t] = i2;
+          rth[t] = rth[t + w];
+        }
       }
-      pick[k] = bidx;
-      V[(int64_t)k * ntot + I.off + bidx] = 1.0;
+      __syncthreads();
     }
+    if (t == rth[0]) ++head;
+    if (t == 0) V[(int64_t)k * ntot + I.off + ri[0]] = 1.0;
+    __syncthreads();
+  }
+  if (t == 0) {
     S.m = 0;
     S.nguess = g;
     S.iters = 0;
@@ -569,50 +646,71 @@ __global__ void __launch_bounds__(256) k_dav_dots(const Item* __restrict__ items
   block_reduce_store<kMaxSpace>(acc, part + (int64_t)wk.begin * kPart);
 }
 
-// Symmetric Jacobi eigen-solve of the m x m subspace matrix by one wave;
-// returns the lowest eigenvalue and its vector (ties: lowest index).
-__device__ void wave_jacobi_lowest(double* A, double* Vm, int m, double* theta, double* y) {
+// Symmetric Jacobi eigen-solve of the m x m subspace matrix by one wave of
+// 64 lanes, parallel ordering: every round applies m/2 disjoint plane
+// rotations at once (round-robin pairing of the indices), m-1 rounds per
+// sweep.  A rotation is skipped when |a_pq| <= 1e-18 (|a_pp| + |a_qq|); the
+// sweeps stop when a whole sweep rotates nothing.  Returns the lowest
+// eigenvalue and its eigenvector (ties: lowest index).
+__device__ void wave_jacobi_lowest(double* A, double* B, double* Vm, double* Vt, int m,
+                                   double* theta, double* y) {
   const int lane = threadIdx.x & 63;
+  __shared__ double rc[kMaxSpace], rt[kMaxSpace];
+  __shared__ int partner[kMaxSpace];
+  __shared__ int rotated;
+  const int N = m + (m & 1);  // even number of players (index m is a dummy when m is odd)
   for (int k = lane; k < m * m; k += 64) Vm[k] = (k / m == k % m) ? 1.0 : 0.0;
   __syncthreads();
-  for (int sweep = 0; sweep < 50; ++sweep) {
-    double off = 0.0, dia = 0.0;
-    for (int p = 0; p < m; ++p)
-      for (int q = 0; q < m; ++q) {
-        if (p != q) off += A[p * m + q] * A[p * m + q];
-        else dia += A[p * m + q] * A[p * m + q];
-      }
-    if (off <= 1e-32 * dia || off == 0.0) break;
-    for (int p = 0; p < m - 1; ++p)
-      for (int q = p + 1; q < m; ++q) {
-        const double apq = A[p * m + q];
-        if (apq == 0.0) continue;
-        const double th = (A[q * m + q] - A[p * m + p]) / (2.0 * apq);
-        const double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-        const double cs = 1.0 / sqrt(tt * tt + 1.0), sn = tt * cs;
-        __syncthreads();
-        if (lane < m) {
-          const double akp = A[lane * m + p], akq = A[lane * m + q];
-          A[lane * m + p] = cs * akp - sn * akq;
-          A[lane * m + q] = sn * akp + cs * akq;
-          const double vkp = Vm[lane * m + p], vkq = Vm[lane * m + q];
-          Vm[lane * m + p] = cs * vkp - sn * vkq;
-          Vm[lane * m + q] = sn * vkp + cs * vkq;
+  for (int sweep = 0; sweep < 40 && N > 1; ++sweep) {
+    if (lane == 0) rotated = 0;
+    __syncthreads();
+    for (int r = 0; r < N - 1; ++r) {
+      // round-robin pairs: position 0 holds index 0, positions 1..N-1 rotate
+      if (lane < N / 2) {
+        const int k = lane;
+        const int a0 = (k == 0) ? 0 : 1 + ((k - 1 + r) % (N - 1));
+        const int b0 = 1 + ((N - 2 - k + r) % (N - 1));
+        const int p = a0 < b0 ? a0 : b0, q = a0 < b0 ? b0 : a0;
+        double c = 1.0, t = 0.0;
+        bool rot = false;
+        if (q < m) {
+          const double apq = A[p * m + q], app = A[p * m + p], aqq = A[q * m + q];
+          if (fabs(apq) > 1e-18 * (fabs(app) + fabs(aqq)) && apq != 0.0) {
+            const double th = (aqq - app) / (2.0 * apq);
+            const double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(tt * tt + 1.0);
+            t = tt * c;
+            rot = true;
+          }
         }
-        __syncthreads();
-        if (lane < m) {
-          const double apk = A[p * m + lane], aqk = A[q * m + lane];
-          A[p * m + lane] = cs * apk - sn * aqk;
-          A[q * m + lane] = sn * apk + cs * aqk;
-        }
-        __syncthreads();
+        if (p < m) { partner[p] = rot ? q : p; rc[p] = c; rt[p] = rot ? -t : 0.0; }
+        if (q < m) { partner[q] = rot ? p : q; rc[q] = c; rt[q] = rot ? t : 0.0; }
+        if (rot) rotated = 1;
       }
+      __syncthreads();
+      // B = A J, V = V J : column j <- c_j col_j + t_j col_partner(j)
+      for (int e = lane; e < m * m; e += 64) {
+        const int i = e / m, j = e % m, pj = partner[j];
+        B[e] = rc[j] * A[i * m + j] + rt[j] * A[i * m + pj];
+        Vt[e] = rc[j] * Vm[i * m + j] + rt[j] * Vm[i * m + pj];
+      }
+      __syncthreads();
+      // A = J^T B : row i <- c_i row_i + t_i row_partner(i)
+      for (int e = lane; e < m * m; e += 64) {
+        const int i = e / m, j = e % m, pi = partner[i];
+        A[e] = rc[i] * B[i * m + j] + rt[i] * B[pi * m + j];
+        Vm[e] = Vt[e];
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
   }
   int best = 0;
   for (int k = 1; k < m; ++k)
     if (A[k * m + k] < A[best * m + best]) best = k;
   *theta = A[best * m + best];
-  for (int k = 0; k < m; ++k) y[k] = Vm[k * m + best];
+  for (int k = lane; k < m; k += 64) y[k] = Vm[k * m + best];
+  __syncthreads();
 }
 
 // Reduce the dots of the newest column into Hs; when the subspace is
@@ -635,11 +733,15 @@ __global__ void k_dav_rr(const Item* __restrict__ items, int ibase,
   __syncthreads();
   const bool solve = slot < 0 || slot == S.nguess - 1;
   if (!solve) return;
-  __shared__ double A[kMaxSpace * kMaxSpace], Vm[kMaxSpace * kMaxSpace], y[kMaxSpace];
+  __shared__ double A[kMaxSpace * kMaxSpace], B[kMaxSpace * kMaxSpace];
+  __shared__ double Vm[kMaxSpace * kMaxSpace], Vt[kMaxSpace * kMaxSpace], y[kMaxSpace];
   __shared__ double th;
   for (int k = lane; k < m * m; k += 64) A[k] = S.Hs[(k / m) * kMaxSpace + (k % m)];
   __syncthreads();
-  wave_jacobi_lowest(A, Vm, m, &th, y);
+  double thl;
+  wave_jacobi_lowest(A, B, Vm, Vt, m, &thl, y);
+  if (lane == 0) th = thl;
+  __syncthreads();
   __syncthreads();
   if (lane < kMaxSpace) S.y[lane] = lane < m ? y[lane] : 0.0;
   if (lane == 0) {
@@ -872,7 +974,8 @@ __global__ void k_item_energy(const Item* __restrict__ items, const ItemHam* __r
 __global__ void k_mbe_increments(MbeSpaces sp, const BucketDev* __restrict__ buckets, int nbucket,
                                  const int32_t* __restrict__ tuple_pos, int max_order,
                                  const double* __restrict__ f, int nitem, double* inc,
-                                 double* inc_lex, const int64_t* __restrict__ order_off,
+                                 double* inc_lex, double* f_lex,
+                                 const int64_t* __restrict__ order_off,
                                  const int32_t* __restrict__ xpos_o,
                                  const int32_t* __restrict__ xpos_v, int nX) {
   int it = blockIdx.x * blockDim.x + threadIdx.x;
@@ -911,7 +1014,9 @@ __global__ void k_mbe_increments(MbeSpaces sp, const BucketDev* __restrict__ buc
       while (j >= 0 && c[j] > v) { c[j + 1] = c[j]; --j; }
       c[j + 1] = v;
     }
-    inc_lex[order_off[n - 1] + comb_lex_rank(c, n, nX)] = acc;
+    const int64_t lx = order_off[n - 1] + comb_lex_rank(c, n, nX);
+    inc_lex[lx] = acc;
+    if (f_lex) f_lex[lx] = f[it];
   }
 }
 
@@ -968,6 +1073,12 @@ __global__ void k_state_single(DavState* st) {
     st->iters = 0;
     st->status = 0;
   }
+}
+
+// mark every multi-determinant item unconverged (kernel re-timing)
+__global__ void k_state_unconv(const Item* __restrict__ items, DavState* st, int nitem) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nitem && items[i].ndet > 1) st[i].conv = 0;
 }
 
 // out = s + a*c
@@ -1028,6 +1139,10 @@ void launch_strings(int n, int ne, int64_t N, uint64_t* out, hipStream_t s) {
 void launch_links(int n, int ne, int64_t N, uint32_t* packed, int32_t* abi4, hipStream_t s) {
   if (N > 0)
     hipLaunchKernelGGL(k_links, dim3(nblk(N, 128)), dim3(128), 0, s, n, ne, N, packed, abi4);
+}
+void launch_pair_table(int n, int ne, int64_t N, int32_t* out, int32_t* outT, hipStream_t s) {
+  if (N > 0)
+    hipLaunchKernelGGL(k_pair_table, dim3(nblk(N, 128)), dim3(128), 0, s, n, ne, N, out, outT);
 }
 void launch_mbe_setup(const MbeSpaces* sp, const BucketDev* buckets, int nbucket, const Item* items,
                       int nitem, const double* h1, const double* eri, double e_const,
@@ -1136,12 +1251,12 @@ void launch_item_energy(const Item* items, const ItemHam* hams, const DavState* 
 }
 void launch_mbe_combine(const MbeSpaces* sp, const BucketDev* buckets, int nbucket,
                         const int32_t* tuple_pos, int max_order, const double* f, int nitem,
-                        double* inc, double* inc_lex, const int64_t* order_off,
+                        double* inc, double* inc_lex, double* f_lex, const int64_t* order_off,
                         const int32_t* xpos_o, const int32_t* xpos_v, int nX, double* e_order,
                         hipStream_t s) {
   hipLaunchKernelGGL(k_mbe_increments, dim3(nblk(nitem, 64)), dim3(64), 0, s, *sp, buckets,
-                     nbucket, tuple_pos, max_order, f, nitem, inc, inc_lex, order_off, xpos_o,
-                     xpos_v, nX);
+                     nbucket, tuple_pos, max_order, f, nitem, inc, inc_lex, f_lex, order_off,
+                     xpos_o, xpos_v, nX);
   if (max_order > 0)
     hipLaunchKernelGGL(k_mbe_order_sums, dim3(max_order), dim3(256), 0, s, buckets, nbucket, inc,
                        e_order);
@@ -1175,6 +1290,9 @@ void launch_ritz_vector(const Item* items, const Work* chunks, int nchunk, const
   if (nchunk > 0)
     hipLaunchKernelGGL(k_ritz_vector, dim3(nchunk), dim3(256), 0, s, items, chunks, V, ntot, st,
                        out);
+}
+void launch_state_unconv(const Item* items, DavState* st, int nitem, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_unconv, dim3(nblk(nitem, 64)), dim3(64), 0, s, items, st, nitem);
 }
 void launch_mbe_total(const double* f, const double* e_order, int k, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_mbe_total, dim3(1), dim3(64), 0, s, f, e_order, k, out);

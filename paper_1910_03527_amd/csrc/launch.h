@@ -10,6 +10,7 @@ namespace mbefci {
 
 void launch_strings(int n, int ne, int64_t N, uint64_t* out, hipStream_t s);
 void launch_links(int n, int ne, int64_t N, uint32_t* packed, int32_t* abi4, hipStream_t s);
+void launch_pair_table(int n, int ne, int64_t N, int32_t* out, int32_t* outT, hipStream_t s);
 void launch_mbe_setup(const MbeSpaces* sp, const BucketDev* buckets, int nbucket, const Item* items,
                       int nitem, const double* h1, const double* eri, double e_const,
                       ItemHam* hams, double* warena, int32_t* tuple_pos, int max_order,
@@ -39,7 +40,7 @@ void launch_item_energy(const Item* items, const ItemHam* hams, const DavState* 
                         double* f, hipStream_t s);
 void launch_mbe_combine(const MbeSpaces* sp, const BucketDev* buckets, int nbucket,
                         const int32_t* tuple_pos, int max_order, const double* f, int nitem,
-                        double* inc, double* inc_lex, const int64_t* order_off,
+                        double* inc, double* inc_lex, double* f_lex, const int64_t* order_off,
                         const int32_t* xpos_o, const int32_t* xpos_v, int nX, double* e_order,
                         hipStream_t s);
 
@@ -53,6 +54,7 @@ void launch_diag_times(double* out, const double* d, const double* c, double a, 
 void launch_add_scalar(double* out, const double* in, double a, int64_t n, hipStream_t s);
 void launch_ritz_vector(const Item* items, const Work* chunks, int nchunk, const double* V,
                         int64_t ntot, const DavState* st, double* out, hipStream_t s);
+void launch_state_unconv(const Item* items, DavState* st, int nitem, hipStream_t s);
 void launch_mbe_total(const double* f, const double* e_order, int k, double* out, hipStream_t s);
 
 constexpr int kChunkElems = 4096;   // elements per Davidson reduction chunk

@@ -55,6 +55,9 @@ struct StringTab {
   int n = 0, ne = 0, L = 0;
   int64_t N = 0;
   uint32_t* link = nullptr;
+  uint64_t* str = nullptr;
+  int32_t* pair = nullptr;
+  int32_t* pairT = nullptr;
 };
 
 // One kernel-shape group of a plan: items with the same active size n share
@@ -66,14 +69,25 @@ struct Group {
   Work* d_tiles = nullptr;
 };
 
+// One pass of a sigma sweep: a contiguous item range whose G blocks are
+// written by the contraction kernels and read back by the gather before the
+// next pass reuses the same G memory.
+struct Pass {
+  int item_lo = 0, item_hi = 0;
+  std::vector<int> tile_lo, tile_hi;  // per group
+  int seg_lo = 0, seg_hi = 0;
+};
+
 struct Plan {
   std::vector<Item> items;
+  std::vector<Pass> passes;
   std::vector<BucketDev> buckets;
   std::vector<Work> chunks, blocks;        // reduction chunks, 256-determinant blocks
-  std::vector<int> chunk_lo, chunk_hi, block_lo, block_hi;
+  std::vector<Work> segs;                  // sigma gather: 4 row-aligned 64-segments per block
+  std::vector<int> chunk_lo, chunk_hi, block_lo, block_hi, seg_lo, seg_hi;
   std::vector<Group> groups;
   std::vector<int> item_group;
-  int nitem = 0, nchunk = 0, nblock = 0;
+  int nitem = 0, nchunk = 0, nblock = 0, nseg = 0;
   int64_t ntot = 0, gtot = 0, wtot = 0;
   int nsingle = 0;
   int64_t ndet_total = 0;
@@ -81,6 +95,7 @@ struct Plan {
   Item* d_items = nullptr;
   Work* d_chunks = nullptr;
   Work* d_blocks = nullptr;
+  Work* d_segs = nullptr;
   BucketDev* d_buckets = nullptr;
   double *V = nullptr, *S = nullptr, *diag = nullptr, *G = nullptr, *W = nullptr,
          *part = nullptr, *f = nullptr, *inc = nullptr, *ci = nullptr;
@@ -164,6 +179,13 @@ const StringTab& string_tab(mbefci_ctx* c, int n, int ne) {
     launch_links(n, ne, t.N, t.link, nullptr, c->stream);
     HIPCHK(hipGetLastError());
   }
+  HIPCHK(hipMalloc(&t.str, sizeof(uint64_t) * std::max<int64_t>(t.N, 1)));
+  launch_strings(n, ne, t.N, t.str, c->stream);
+  const int64_t npair = (int64_t)n * (n + 1) / 2;
+  HIPCHK(hipMalloc(&t.pair, sizeof(int32_t) * std::max<int64_t>(t.N * npair, 1)));
+  HIPCHK(hipMalloc(&t.pairT, sizeof(int32_t) * std::max<int64_t>(t.N * npair, 1)));
+  launch_pair_table(n, ne, t.N, t.pair, t.pairT, c->stream);
+  HIPCHK(hipGetLastError());
   return c->tabs[key] = t;
 }
 
@@ -190,6 +212,9 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
   P.chunk_hi.assign(P.nitem, 0);
   P.block_lo.assign(P.nitem, 0);
   P.block_hi.assign(P.nitem, 0);
+  P.segs.clear();
+  P.seg_lo.assign(P.nitem, 0);
+  P.seg_hi.assign(P.nitem, 0);
   P.nsingle = 0;
   P.ndet_total = 0;
   for (int i = 0; i < P.nitem; ++i) {
@@ -204,6 +229,10 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
     I.Lb = tb.L;
     I.linkA = ta.link;
     I.linkB = tb.link;
+    I.strA = ta.str;
+    I.strB = tb.str;
+    I.pairA = ta.pair;
+    I.pairB = tb.pairT;
     I.ndet = (int64_t)I.Na * I.Nb;
     I.npair = I.n * (I.n + 1) / 2;
     I.kpad = (I.npair + 15) / 16 * 16;
@@ -232,6 +261,12 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
     P.block_lo[i] = (int)P.blocks.size();
     for (int k = 0; k < nbk; ++k) P.blocks.push_back(Work{i, k, k + 1, 0});
     P.block_hi[i] = (int)P.blocks.size();
+    P.seg_lo[i] = (int)P.segs.size();
+    if (I.ndet > 1) {
+      const int nsg = I.Na * ((I.Nb + 63) / 64);
+      for (int b = 0; b * 4 < nsg; ++b) P.segs.push_back(Work{i, b, nsg, 0});
+    }
+    P.seg_hi[i] = (int)P.segs.size();
     if (I.ndet > 1) {
       if (!group_of_n.count(I.n)) {
         group_of_n[I.n] = (int)P.groups.size();
@@ -255,16 +290,59 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
       g.tiles.push_back(Work{i, b, std::min(b + g.tiles_per_wg, ntile), 0});
     g.item_hi[i] = (int)g.tiles.size();
   }
+  // sigma passes: G offsets restart at every pass
+  {
+    const int64_t cap = c->opts.sigma_pass_mb > 0 ? (int64_t)c->opts.sigma_pass_mb << 20 : INT64_MAX;
+    P.passes.clear();
+    int64_t gpass = 0, gmax = 0;
+    Pass cur;
+    cur.tile_lo.assign(P.groups.size(), INT32_MAX);
+    cur.tile_hi.assign(P.groups.size(), 0);
+    cur.seg_lo = INT32_MAX;
+    cur.seg_hi = 0;
+    auto close = [&](int end) {
+      cur.item_hi = end;
+      for (size_t g = 0; g < P.groups.size(); ++g)
+        if (cur.tile_lo[g] == INT32_MAX) cur.tile_lo[g] = cur.tile_hi[g] = 0;
+      if (cur.seg_lo == INT32_MAX) cur.seg_lo = cur.seg_hi = 0;
+      P.passes.push_back(cur);
+      gmax = std::max(gmax, gpass);
+      cur = Pass();
+      cur.item_lo = end;
+      cur.tile_lo.assign(P.groups.size(), INT32_MAX);
+      cur.tile_hi.assign(P.groups.size(), 0);
+      cur.seg_lo = INT32_MAX;
+      cur.seg_hi = 0;
+      gpass = 0;
+    };
+    for (int i = 0; i < P.nitem; ++i) {
+      Item& I = P.items[i];
+      if (I.ndet <= 1) continue;
+      const int64_t gb = (int64_t)I.npair * I.ndet;
+      if (gpass > 0 && (gpass + gb) * 8 > cap) close(i);
+      I.goff = gpass;
+      gpass += gb;
+      const int g = P.item_group[i];
+      cur.tile_lo[g] = std::min(cur.tile_lo[g], P.groups[g].item_lo[i]);
+      cur.tile_hi[g] = std::max(cur.tile_hi[g], P.groups[g].item_hi[i]);
+      cur.seg_lo = std::min(cur.seg_lo, P.seg_lo[i]);
+      cur.seg_hi = std::max(cur.seg_hi, P.seg_hi[i]);
+    }
+    close(P.nitem);
+    goff = gmax;
+  }
   P.ntot = std::max<int64_t>(off, 64);
   P.gtot = goff;
   P.wtot = woff;
   P.nchunk = (int)P.chunks.size();
   P.nblock = (int)P.blocks.size();
+  P.nseg = (int)P.segs.size();
 
   bool grown = false;
   P.d_items = arena<Item>(c, "items", P.nitem, &grown);
   P.d_chunks = arena<Work>(c, "chunks", P.nchunk, &grown);
   P.d_blocks = arena<Work>(c, "blocks", P.nblock, &grown);
+  P.d_segs = arena<Work>(c, "segs", P.nseg, &grown);
   P.hams = arena<ItemHam>(c, "hams", P.nitem, &grown);
   P.st = arena<DavState>(c, "state", P.nitem, &grown);
   P.V = arena<double>(c, "V", (size_t)(mmax + 1) * P.ntot, &grown);
@@ -284,6 +362,7 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
   upload(c, P.d_items, P.items);
   upload(c, P.d_chunks, P.chunks);
   upload(c, P.d_blocks, P.blocks);
+  upload(c, P.d_segs, P.segs);
   for (auto& g : P.groups) upload(c, g.d_tiles, g.tiles);
   (void)nguess_slots;
 }
@@ -292,30 +371,58 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
 struct View {
   int ibase, nitem;
   int chunk_lo, nchunk;
-  int block_lo, nblock;
+  int seg_lo, nseg;
   int item;  // -1: whole plan, else the single item
 };
 
-View whole(const Plan& P) { return View{0, P.nitem, 0, P.nchunk, 0, P.nblock, -1}; }
+View whole(const Plan& P) { return View{0, P.nitem, 0, P.nchunk, 0, P.nseg, -1}; }
 View single(const Plan& P, int i) {
-  return View{i, 1, P.chunk_lo[i], P.chunk_hi[i] - P.chunk_lo[i], P.block_lo[i],
-              P.block_hi[i] - P.block_lo[i], i};
+  return View{i, 1, P.chunk_lo[i], P.chunk_hi[i] - P.chunk_lo[i], P.seg_lo[i],
+              P.seg_hi[i] - P.seg_lo[i], i};
+}
+
+// One launch of the sigma sweep: kind 0 = contraction of group `group`,
+// kind 1 = gather; work-list range [lo, lo + cnt).
+struct SigmaLaunch {
+  int kind, group, lo, cnt;
+};
+
+std::vector<SigmaLaunch> sigma_launches(const Plan& P, const View& v) {
+  std::vector<SigmaLaunch> out;
+  if (v.item >= 0) {
+    const int g = P.item_group[v.item];
+    if (g < 0) return out;
+    out.push_back({0, g, P.groups[g].item_lo[v.item],
+                   P.groups[g].item_hi[v.item] - P.groups[g].item_lo[v.item]});
+    out.push_back({1, -1, v.seg_lo, v.nseg});
+    return out;
+  }
+  for (const Pass& ps : P.passes) {
+    bool any = false;
+    for (size_t g = 0; g < P.groups.size(); ++g)
+      if (ps.tile_hi[g] > ps.tile_lo[g]) {
+        out.push_back({0, (int)g, ps.tile_lo[g], ps.tile_hi[g] - ps.tile_lo[g]});
+        any = true;
+      }
+    if (any) out.push_back({1, -1, ps.seg_lo, ps.seg_hi - ps.seg_lo});
+  }
+  return out;
+}
+
+void sigma_launch(mbefci_ctx* c, Plan& P, const SigmaLaunch& L, int slot) {
+  if (L.kind == 0) {
+    const Group& g = P.groups[L.group];
+    if (!launch_sigma_dgemm(g.n, g.tn, P.d_items, g.d_tiles + L.lo, L.cnt, P.W, P.V, P.ntot, P.G,
+                            P.st, slot, c->stream))
+      throw Error(MBEFCI_EUNSUPPORTED, "no sigma kernel for n=" + std::to_string(g.n));
+  } else {
+    launch_sigma_gather(P.d_items, P.d_segs + L.lo, L.cnt, P.G, P.S, P.ntot, P.st, slot,
+                        c->stream);
+  }
 }
 
 void sigma(mbefci_ctx* c, Plan& P, const View& v, int slot) {
-  for (auto& g : P.groups) {
-    int lo = 0, cnt = (int)g.tiles.size();
-    if (v.item >= 0) {
-      if (P.item_group[v.item] < 0 || &P.groups[P.item_group[v.item]] != &g) continue;
-      lo = g.item_lo[v.item];
-      cnt = g.item_hi[v.item] - lo;
-    }
-    if (!launch_sigma_dgemm(g.n, g.tn, P.d_items, g.d_tiles + lo, cnt, P.W, P.V, P.ntot, P.G, P.st,
-                            slot, c->stream))
-      throw Error(MBEFCI_EUNSUPPORTED, "no sigma kernel for n=" + std::to_string(g.n));
-  }
-  launch_sigma_gather(P.d_items, P.d_blocks + v.block_lo, v.nblock, P.G, P.S, P.ntot, P.st, slot,
-                      c->stream);
+  for (const SigmaLaunch& L : sigma_launches(P, v)) sigma_launch(c, P, L, slot);
 }
 
 void add_vector(mbefci_ctx* c, Plan& P, const View& v, int slot) {
@@ -361,6 +468,7 @@ void solve_view(mbefci_ctx* c, Plan& P, const View& v, int* graph_launches) {
       HIPCHK(hipGraphDestroy(gr));
       P.graph_iters = K;
     }
+    if (count_active(c, P, v) == 0) return;
     for (int it = 0; it < max_iter + K; it += K) {
       HIPCHK(hipGraphLaunch(P.graph, c->stream));
       if (graph_launches) ++*graph_launches;
@@ -368,6 +476,7 @@ void solve_view(mbefci_ctx* c, Plan& P, const View& v, int* graph_launches) {
     }
   } else if (v.item < 0) {
     const int K = 4;
+    if (count_active(c, P, v) == 0) return;
     for (int it = 0; it < max_iter + K; it += K) {
       for (int k = 0; k < K; ++k) iteration(c, P, v);
       if (count_active(c, P, v) == 0) break;
@@ -535,12 +644,13 @@ void mbefci_default_opts(mbefci_opts* o) {
   o->conv_tol = 1e-6;
   o->max_iter = 200;
   o->max_space = 16;
-  o->nguess = 4;
+  o->nguess = 2;
   o->mode = MBEFCI_BATCHED;
   o->use_graph = 1;
   o->tile = 0;
   o->keep_ci = 1;
   o->validate = 1;
+  o->sigma_pass_mb = 0;
   o->max_workspace = 0;
   o->tune_cache = nullptr;
 }
@@ -552,6 +662,7 @@ static int check_opts(const mbefci_opts* o, std::string* why) {
   if (o->nguess < 1 || o->nguess > 8 || o->nguess >= o->max_space) { *why = "nguess must be in 1..8 and below max_space"; return MBEFCI_EINVAL; }
   if (o->mode != MBEFCI_BATCHED && o->mode != MBEFCI_PER_LAUNCH) { *why = "unknown mode"; return MBEFCI_EINVAL; }
   if (o->tile != 0 && o->tile != 32 && o->tile != 64 && o->tile != 128) { *why = "tile must be 0, 32, 64 or 128"; return MBEFCI_EINVAL; }
+  if (o->sigma_pass_mb < 0) { *why = "sigma_pass_mb must be >= 0"; return MBEFCI_EINVAL; }
   return MBEFCI_OK;
 }
 
@@ -588,8 +699,12 @@ void mbefci_destroy(mbefci_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->plan && c->plan->graph) (void)hipGraphExecDestroy(c->plan->graph);
-  for (auto& kv : c->tabs)
+  for (auto& kv : c->tabs) {
     if (kv.second.link) (void)hipFree(kv.second.link);
+    if (kv.second.str) (void)hipFree(kv.second.str);
+    if (kv.second.pair) (void)hipFree(kv.second.pair);
+    if (kv.second.pairT) (void)hipFree(kv.second.pairT);
+  }
   for (auto& kv : c->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
@@ -610,7 +725,8 @@ int mbefci_set_opts(mbefci_ctx* c, const mbefci_opts* o) {
     c->err = why;
     return rc;
   }
-  bool plan_dead = o->max_space != c->opts.max_space || o->tile != c->opts.tile;
+  bool plan_dead = o->max_space != c->opts.max_space || o->tile != c->opts.tile ||
+                   o->sigma_pass_mb != c->opts.sigma_pass_mb;
   c->opts = *o;
   if (plan_dead && c->plan) {
     if (c->plan->graph) (void)hipGraphExecDestroy(c->plan->graph);
@@ -744,7 +860,8 @@ int mbefci_casci_rdm(mbefci_ctx* c, double* const* rdm1s, double* const* rdm2s, 
 }
 
 int mbefci_mbe_forward(mbefci_ctx* c, const mbefci_problem* pb, double* e_ref, double* e_order,
-                       double* e_total, double* tuple_incr, mbefci_stats* stats, void* stream) {
+                       double* e_total, double* tuple_incr, double* tuple_energy,
+                       mbefci_stats* stats, void* stream) {
   return guarded(c, [&] {
     auto t_start = std::chrono::steady_clock::now();
     if (!pb || !e_ref || !e_total || (pb->max_order > 0 && !e_order))
@@ -867,10 +984,12 @@ int mbefci_mbe_forward(mbefci_ctx* c, const mbefci_problem* pb, double* e_ref, d
     solve_plan(c, P, &st);
     launch_item_energy(P.d_items, P.hams, P.st, P.nitem, P.f, c->stream);
     double* d_lex = arena<double>(c, "inc_lex", std::max<int64_t>(P.ntuples, 1));
+    double* d_flex = arena<double>(c, "f_lex", std::max<int64_t>(P.ntuples, 1));
     double* d_eord = arena<double>(c, "e_order", std::max(P.max_order, 1));
     double* d_tot = arena<double>(c, "e_tot", 2);
     launch_mbe_combine(&P.sp, P.d_buckets, (int)P.buckets.size(), P.tuple_pos, P.max_order, P.f,
-                       P.nitem, P.inc, d_lex, static_cast<int64_t*>(c->bufs["order_off"].p),
+                       P.nitem, P.inc, d_lex, d_flex,
+                       static_cast<int64_t*>(c->bufs["order_off"].p),
                        static_cast<int32_t*>(c->bufs["xpos_o"].p),
                        static_cast<int32_t*>(c->bufs["xpos_v"].p), (int)P.xsorted.size(), d_eord,
                        c->stream);
@@ -880,16 +999,22 @@ int mbefci_mbe_forward(mbefci_ctx* c, const mbefci_problem* pb, double* e_ref, d
     std::vector<double> eo(std::max(P.max_order, 1));
     HIPCHK(hipMemcpyAsync(tot, d_tot, 16, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(eo.data(), d_eord, eo.size() * 8, hipMemcpyDeviceToHost, c->stream));
-    std::vector<double> lex;
+    std::vector<double> lex, flex;
     if (tuple_incr && P.ntuples > 0) {
       lex.resize(P.ntuples);
       HIPCHK(hipMemcpyAsync(lex.data(), d_lex, P.ntuples * 8, hipMemcpyDeviceToHost, c->stream));
+    }
+    if (tuple_energy && P.ntuples > 0) {
+      flex.resize(P.ntuples);
+      HIPCHK(hipMemcpyAsync(flex.data(), d_flex, P.ntuples * 8, hipMemcpyDeviceToHost,
+                            c->stream));
     }
     HIPCHK(hipStreamSynchronize(c->stream));
     *e_ref = tot[0];
     *e_total = tot[1];
     for (int n = 0; n < P.max_order; ++n) e_order[n] = eo[n];
     if (tuple_incr && P.ntuples > 0) std::copy(lex.begin(), lex.end(), tuple_incr);
+    if (tuple_energy && P.ntuples > 0) std::copy(flex.begin(), flex.end(), tuple_energy);
     c->have_forward = true;
     st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
                                                             t_start).count();
@@ -903,6 +1028,95 @@ int mbefci_mbe_backward(mbefci_ctx* c, const double* grad_out, double* d_h1, dou
   return guarded(c, [&] {
     (void)grad_out; (void)d_h1; (void)d_eri; (void)stream;
     throw Error(MBEFCI_EUNSUPPORTED, "the backward is not built yet");
+  });
+}
+
+
+int mbefci_time_kernels(mbefci_ctx* c, int32_t reps, mbefci_kernel_time* out, int32_t cap,
+                        int32_t* count) {
+  return guarded(c, [&] {
+    if (!c->plan || !c->have_forward) throw Error(MBEFCI_EINVAL, "no forward to re-time");
+    if (reps < 1 || !count || (cap > 0 && !out)) throw Error(MBEFCI_EINVAL, "invalid arguments");
+    HIPCHK(hipSetDevice(c->device));
+    Plan& P = *c->plan;
+    DavState* backup = arena<DavState>(c, "state_backup", P.nitem);
+    HIPCHK(hipMemcpyAsync(backup, P.st, sizeof(DavState) * P.nitem, hipMemcpyDeviceToDevice,
+                          c->stream));
+    launch_state_unconv(P.d_items, P.st, P.nitem, c->stream);
+    // replay whole sigma sweeps exactly as the solver runs them, with events
+    // around every launch
+    const std::vector<SigmaLaunch> Ls = sigma_launches(P, whole(P));
+    std::vector<hipEvent_t> ev(2 * Ls.size());
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    std::vector<double> ms(Ls.size(), 0.0);
+    sigma(c, P, whole(P), -1);  // warm
+    for (int r = 0; r < reps; ++r) {
+      for (size_t k = 0; k < Ls.size(); ++k) {
+        HIPCHK(hipEventRecord(ev[2 * k], c->stream));
+        sigma_launch(c, P, Ls[k], -1);
+        HIPCHK(hipEventRecord(ev[2 * k + 1], c->stream));
+      }
+      HIPCHK(hipStreamSynchronize(c->stream));
+      for (size_t k = 0; k < Ls.size(); ++k) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]));
+        ms[k] += t;
+      }
+    }
+    for (auto& e : ev) HIPCHK(hipEventDestroy(e));
+    // aggregate per kernel: algorithmic work from the items each launch covers
+    std::map<std::string, mbefci_kernel_time> agg;
+    std::vector<std::string> order;
+    for (size_t k = 0; k < Ls.size(); ++k) {
+      const SigmaLaunch& L = Ls[k];
+      double nd = 0.0, flops = 0.0, bytes = 0.0;
+      std::string name;
+      if (L.kind == 0) {
+        const Group& g = P.groups[L.group];
+        for (int w = L.lo; w < L.lo + L.cnt; ++w)
+          if (g.tiles[w].begin == 0) nd += (double)P.items[g.tiles[w].item].ndet;
+        const double np = g.n * (g.n + 1) / 2;
+        flops = 2.0 * np * np * nd;
+        bytes = 8.0 * (1.0 + np) * nd;  // c read once, G written once
+        name = "sigma_dgemm<n=" + std::to_string(g.n) + ",tile=" + std::to_string(g.tn) + ">";
+      } else {
+        for (int w = L.lo; w < L.lo + L.cnt; ++w)
+          if (P.segs[w].begin == 0) {
+            const Item& I = P.items[P.segs[w].item];
+            nd += (double)I.ndet;
+            bytes += 8.0 * (I.npair + 1.0) * I.ndet;  // G read once, sigma written once
+          }
+        name = "sigma_gather";
+      }
+      if (!agg.count(name)) {
+        order.push_back(name);
+        mbefci_kernel_time z{};
+        std::snprintf(z.name, sizeof(z.name), "%s", name.c_str());
+        agg[name] = z;
+      }
+      mbefci_kernel_time& a = agg[name];
+      a.launches += 1;
+      a.ms_per_launch += ms[k] / reps;
+      a.flops += flops;
+      a.bytes += bytes;
+      a.ndet += nd;
+    }
+    std::vector<mbefci_kernel_time> recs;
+    for (const std::string& nm : order) {
+      mbefci_kernel_time a = agg[nm];
+      a.ms_per_launch /= a.launches;
+      a.flops /= a.launches;
+      a.bytes /= a.launches;
+      a.ndet /= a.launches;
+      recs.push_back(a);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(P.st, backup, sizeof(DavState) * P.nitem, hipMemcpyDeviceToDevice,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int n = std::min<int>((int)recs.size(), cap);
+    for (int i = 0; i < n; ++i) out[i] = recs[i];
+    *count = (int32_t)recs.size();
   });
 }
 

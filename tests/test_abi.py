@@ -49,12 +49,12 @@ def test_integer_closed_forms(lib):
 def test_default_options(lib):
     o = _lib.Opts()
     lib.mbefci_default_opts(ctypes.byref(o))
-    assert o.conv_tol == 1e-6 and o.max_space == 16 and o.nguess == 4
+    assert o.conv_tol == 1e-6 and o.max_space == 16 and o.nguess == 2
     assert o.mode == _lib.BATCHED and o.keep_ci == 1 and o.validate == 1
 
 
 def test_null_context_is_rejected(lib):
-    assert lib.mbefci_mbe_forward(None, None, None, None, None, None, None, None) == _lib.EINVAL
+    assert lib.mbefci_mbe_forward(None, None, None, None, None, None, None, None, None) == _lib.EINVAL
     assert lib.mbefci_strings(None, 4, 2, None, None) == _lib.EINVAL
     assert lib.mbefci_last_error(None) == b"null context"
 
