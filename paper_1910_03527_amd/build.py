@@ -42,7 +42,9 @@ def build(verbose: bool = False) -> str:
         cmd = [cc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True, stderr=None if verbose else subprocess.PIPE)
+        r = subprocess.run(cmd, stderr=None if verbose else subprocess.PIPE, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr or ''}")
         objs.append(obj)
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -40,6 +40,13 @@ __device__ inline T ldg(const T* p) {
   return *(const __attribute__((address_space(1))) T*)p;
 }
 
+// Load through the constant address space: lets the compiler use scalar
+// loads when the address is wave-uniform (read-only tables).
+template <class T>
+__device__ inline T ldc(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)p;
+}
+
 // One CASCI problem inside a batch.
 struct Item {
   int32_t n, na, nb, npair;

@@ -352,6 +352,21 @@ __device__ inline bool item_active(const DavState& st, int slot) {
   return slot < 0 || slot < st.nguess;
 }
 
+// Contraction G = W D+ on FP64 MFMA.  A tile is one alpha string Ka and TN
+// consecutive beta strings; a workgroup keeps one beta block (TN strings)
+// and walks down a range of alpha strings (tiles are numbered column-major:
+// tile = block * Na + Ka).  Per workgroup the beta pair-table block is staged
+// once in LDS; per tile the c row of Ka is staged in LDS, so the beta half of
+// every D+ entry is two LDS reads.  The alpha half is wave-uniform: a scalar
+// pair-table load and a coalesced row segment of c.  D+ [pair][TN] (B
+// operand) is staged in LDS, the wave's W rows (A operand) sit in registers.
+// G is stored [Ka][pair][Kb].
+constexpr int64_t binom_c(int n, int k) {
+  int64_t r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
 template <int NACT, int TN>
 __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ items,
                                                      const Work* __restrict__ work,
@@ -361,14 +376,18 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
                                                      const DavState* __restrict__ st, int slot) {
   constexpr int NP = NACT * (NACT + 1) / 2;
   constexpr int KPAD = (NP + 15) / 16 * 16;
-  constexpr int KS = (NP + 3) / 4;       // MFMA k-steps (4 per step)
+  constexpr int KS = (NP + 3) / 4;       // MFMA k-steps (4 pair rows per step)
   constexpr int KR = KS * 4;             // D+ rows held in LDS (zero beyond NP)
   constexpr int NRB = KPAD / 16;         // 16-row blocks of G
   constexpr int RBW = (NRB + 3) / 4;     // row blocks per wave
   constexpr int NCB = TN / 16;           // 16-column blocks per tile
-  constexpr int NSUB = 256 / TN;
+  constexpr int NSUB = 256 / TN;         // row groups of the gather
+  constexpr int NPER = (NP + NSUB - 1) / NSUB;
   constexpr int LDT = TN + 1;            // padded LDS row (doubles)
+  constexpr int CMAX = (int)binom_c(NACT, NACT / 2);  // largest string count for NACT
   __shared__ double Ds[KR * LDT];
+  __shared__ int32_t Tb[NP * TN];
+  __shared__ double Cr[CMAX];
 
   const Work wk = work[blockIdx.x];
   const Item& I = items[wk.item];
@@ -377,15 +396,19 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
   const int vs = vec_slot(S, slot);
   const double* __restrict__ c = V + (int64_t)vs * ntot + I.off;
   double* __restrict__ G = Garena + I.goff;
-  const int Nb = I.Nb;
-  const int64_t ndet = I.ndet;
+  const int Na = I.Na, Nb = I.Nb;
   const int32_t* __restrict__ pA = I.pairA;
   const int32_t* __restrict__ pB = I.pairB;
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int col = t % TN;
-  // row group of the D+ gather; wave-uniform when a tile row spans a wave
-  const int sub = (TN == 64) ? __builtin_amdgcn_readfirstlane(t / TN) : t / TN;
+  const int sub = (TN >= 64) ? __builtin_amdgcn_readfirstlane(t / TN) : t / TN;
+
+  const int blk = wk.begin / Na;          // every work unit stays inside one beta block
+  const int Kb0 = blk * TN;
+  const int Kb = Kb0 + col;
+  const double keep = Kb < Nb ? 1.0 : 0.0;  // ragged end of the row: zero columns
+  const int Kbc = Kb < Nb ? Kb : Nb - 1;
 
   // W rows of this wave's row blocks, as MFMA A operands: lane l holds
   // W[rb*16 + l%16][ks*4 + l/16] (B operand: lane l holds D+[ks*4 + l/16][l%16])
@@ -396,36 +419,33 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
     const int rb = wave + 4 * r;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
-      wreg[r][ks] = (rb < NRB) ? W[(rb * 16 + (lane & 15)) * KPAD + ks * 4 + (lane >> 4)] : 0.0;
+      wreg[r][ks] = (rb < NRB) ? ldg(W + (rb * 16 + (lane & 15)) * KPAD + ks * 4 + (lane >> 4))
+                               : 0.0;
   }
-
-  // padding rows NP..KR-1 of the D+ tile stay zero for every tile
+  // beta pair-table block [pair][TN] and the zero padding rows of D+
+  for (int x = t; x < NP * TN; x += 256) {
+    const int ab = x / TN, cc = x - ab * TN;
+    const int kb = Kb0 + cc < Nb ? Kb0 + cc : Nb - 1;
+    Tb[x] = ldg(pB + ab * Nb + kb);
+  }
   for (int x = NP * LDT + t; x < KR * LDT; x += 256) Ds[x] = 0.0;
-  constexpr int NPER = (NP + NSUB - 1) / NSUB;  // D+ rows per thread
-  const int nd32 = (int)ndet;                    // every CASCI has < 2^31 determinants
 
   for (int tile = wk.begin; tile < wk.end; ++tile) {
-    const int64_t K0 = (int64_t)tile * TN;
-    const int Kraw = (int)K0 + col;
-    const double keep = Kraw < nd32 ? 1.0 : 0.0;  // ragged last tile: zero columns
-    const int Kc = Kraw < nd32 ? Kraw : nd32 - 1;
-    const int Ka = Kc / Nb, Kb = Kc - Ka * Nb;
-    const int32_t* __restrict__ pa = pA + Ka * NP;
-    const int32_t* __restrict__ pb = pB + Kb;   // pair-major: entry ab at pb[ab * Nb]
-    const double* __restrict__ ca = c + Kb;     // alpha source: ca[Ja * Nb]
-    const double* __restrict__ cb = c + Ka * Nb;  // beta source: cb[Jb]
-    // D+[ab][col] = (alpha excitation) + (beta excitation) of pair ab, branch
-    // free: a vanishing excitation loads a valid element and scales it by 0
+    const int Ka = tile - blk * Na;              // uniform
+    for (int x = t; x < Nb; x += 256) Cr[x] = ldg(c + Ka * Nb + x);
+    __syncthreads();
+    const int32_t* __restrict__ pa = pA + Ka * NP;       // uniform row of the alpha table
+    const double* __restrict__ ca = c + Kbc;             // alpha source: ca[Ja * Nb]
 #pragma unroll
     for (int i = 0; i < NPER; ++i) {
       const int ab = sub + NSUB * i;
       if (ab < NP) {
-        const int32_t ea = ldg(pa + ab), eb = ldg(pb + ab * Nb);
+        const int32_t ea = ldc(pa + ab);   // uniform: scalar load
+        const int32_t eb = Tb[ab * TN + col];
         const int ja = ea ? (ea >> 1) - 1 : 0, jb = eb ? (eb >> 1) - 1 : 0;
         const double fa = ea ? ((ea & 1) ? -keep : keep) : 0.0;
         const double fb = eb ? ((eb & 1) ? -keep : keep) : 0.0;
-        const double xa = ldg(ca + ja * Nb), xb = ldg(cb + jb);
-        Ds[ab * LDT + col] = fa * xa + fb * xb;
+        Ds[ab * LDT + col] = fa * ldg(ca + ja * Nb) + fb * Cr[jb];
       }
     }
     __syncthreads();
@@ -435,25 +455,26 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
       if (rb >= NRB) continue;
       double4_t acc[NCB];
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) acc[cb] = (double4_t){0.0, 0.0, 0.0, 0.0};
+      for (int cb2 = 0; cb2 < NCB; ++cb2) acc[cb2] = (double4_t){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         const double* brow = Ds + (ks * 4 + (lane >> 4)) * LDT + (lane & 15);
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(wreg[r][ks], brow[cb * 16], acc[cb], 0,
-                                                         0, 0);
+        for (int cb2 = 0; cb2 < NCB; ++cb2)
+          acc[cb2] = __builtin_amdgcn_mfma_f64_16x16x4f64(wreg[r][ks], brow[cb2 * 16], acc[cb2],
+                                                          0, 0, 0);
       }
+      double* __restrict__ Grow = G + (int64_t)Ka * NP * Nb;
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
-        const int64_t Kc = K0 + cb * 16 + (lane & 15);
-        if (Kc < ndet) {
+      for (int cb2 = 0; cb2 < NCB; ++cb2) {
+        const int Kc = Kb0 + cb2 * 16 + (lane & 15);
+        if (Kc < Nb) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             // gfx950 FP64 16x16x4 output layout: register v of lane l is
             // row l/16 + 4v, column l%16 of the 16x16 block
             const int row = rb * 16 + (lane >> 4) + 4 * v;
-            if (row < NP) G[(int64_t)row * ndet + Kc] = acc[cb][v];
+            if (row < NP) Grow[row * Nb + Kc] = acc[cb2][v];
           }
         }
       }
@@ -487,37 +508,38 @@ __global__ void __launch_bounds__(256) k_sigma_gather(const Item* __restrict__ i
   const int64_t nd = I.ndet;
   const int La = I.La, Lb = I.Lb;
   double acc0 = 0.0, acc1 = 0.0;
+  const int np = I.npair;
   const uint32_t* __restrict__ la = I.linkA + Ka * La;
-  const double* __restrict__ Gcol = G + Kb;
+  const double* __restrict__ Gcol = G + Kb;  // G[(Ja * npair + pair) * Nb + Kb]
   int l = 0;
   for (; l + 3 < La; l += 4) {
-    const uint32_t e0 = ldg(la + l), e1 = ldg(la + l + 1), e2 = ldg(la + l + 2), e3 = ldg(la + l + 3);
-    const double g0 = ldg(Gcol + (int64_t)link_pair(e0) * nd + link_addr(e0) * Nb);
-    const double g1 = ldg(Gcol + (int64_t)link_pair(e1) * nd + link_addr(e1) * Nb);
-    const double g2 = ldg(Gcol + (int64_t)link_pair(e2) * nd + link_addr(e2) * Nb);
-    const double g3 = ldg(Gcol + (int64_t)link_pair(e3) * nd + link_addr(e3) * Nb);
+    const uint32_t e0 = ldc(la + l), e1 = ldc(la + l + 1), e2 = ldc(la + l + 2), e3 = ldc(la + l + 3);
+    const double g0 = ldg(Gcol + (int64_t)(link_addr(e0) * np + link_pair(e0)) * Nb);
+    const double g1 = ldg(Gcol + (int64_t)(link_addr(e1) * np + link_pair(e1)) * Nb);
+    const double g2 = ldg(Gcol + (int64_t)(link_addr(e2) * np + link_pair(e2)) * Nb);
+    const double g3 = ldg(Gcol + (int64_t)(link_addr(e3) * np + link_pair(e3)) * Nb);
     acc0 += link_sign(e0) * g0 + link_sign(e2) * g2;
     acc1 += link_sign(e1) * g1 + link_sign(e3) * g3;
   }
   for (; l < La; ++l) {
-    const uint32_t e0 = ldg(la + l);
-    acc0 += link_sign(e0) * ldg(Gcol + (int64_t)link_pair(e0) * nd + link_addr(e0) * Nb);
+    const uint32_t e0 = ldc(la + l);
+    acc0 += link_sign(e0) * ldg(Gcol + (int64_t)(link_addr(e0) * np + link_pair(e0)) * Nb);
   }
   const uint32_t* __restrict__ lb = I.linkB + Kb * Lb;
-  const double* __restrict__ Grow = G + Ka * Nb;
+  const double* __restrict__ Grow = G + (int64_t)Ka * np * Nb;  // G[(Ka * npair + pair) * Nb + Jb]
   l = 0;
   for (; l + 3 < Lb; l += 4) {
     const uint32_t e0 = ldg(lb + l), e1 = ldg(lb + l + 1), e2 = ldg(lb + l + 2), e3 = ldg(lb + l + 3);
-    const double g0 = ldg(Grow + (int64_t)link_pair(e0) * nd + link_addr(e0));
-    const double g1 = ldg(Grow + (int64_t)link_pair(e1) * nd + link_addr(e1));
-    const double g2 = ldg(Grow + (int64_t)link_pair(e2) * nd + link_addr(e2));
-    const double g3 = ldg(Grow + (int64_t)link_pair(e3) * nd + link_addr(e3));
+    const double g0 = ldg(Grow + link_pair(e0) * Nb + link_addr(e0));
+    const double g1 = ldg(Grow + link_pair(e1) * Nb + link_addr(e1));
+    const double g2 = ldg(Grow + link_pair(e2) * Nb + link_addr(e2));
+    const double g3 = ldg(Grow + link_pair(e3) * Nb + link_addr(e3));
     acc0 += link_sign(e0) * g0 + link_sign(e2) * g2;
     acc1 += link_sign(e1) * g1 + link_sign(e3) * g3;
   }
   for (; l < Lb; ++l) {
     const uint32_t e0 = ldg(lb + l);
-    acc0 += link_sign(e0) * ldg(Grow + (int64_t)link_pair(e0) * nd + link_addr(e0));
+    acc0 += link_sign(e0) * ldg(Grow + link_pair(e0) * Nb + link_addr(e0));
   }
   Sarena[(int64_t)vs * ntot + I.off + (int64_t)Ka * Nb + Kb] = acc0 + acc1;
 }
@@ -1180,8 +1202,13 @@ static bool sigma_dgemm_n(int n, const Item* items, const Work* work, int nwork,
   case N: sigma_dgemm_t<N, TN>(items, work, nwork, warena, V, ntot, G, st, slot, s); return true;
     MBEFCI_CASE(2) MBEFCI_CASE(3) MBEFCI_CASE(4) MBEFCI_CASE(5) MBEFCI_CASE(6) MBEFCI_CASE(7)
     MBEFCI_CASE(8) MBEFCI_CASE(9) MBEFCI_CASE(10) MBEFCI_CASE(11) MBEFCI_CASE(12)
-    MBEFCI_CASE(13) MBEFCI_CASE(14)
 #undef MBEFCI_CASE
+    case 13:
+      if constexpr (TN <= 64) { sigma_dgemm_t<13, TN>(items, work, nwork, warena, V, ntot, G, st, slot, s); return true; }
+      return false;
+    case 14:
+      if constexpr (TN <= 64) { sigma_dgemm_t<14, TN>(items, work, nwork, warena, V, ntot, G, st, slot, s); return true; }
+      return false;
     default: return false;
   }
 }
@@ -1193,7 +1220,10 @@ bool launch_sigma_dgemm(int n, int tn, const Item* items, const Work* work, int 
   switch (tn) {
     case 32: return sigma_dgemm_n<32>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
     case 64: return sigma_dgemm_n<64>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
-    case 128: return sigma_dgemm_n<128>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
+    case 128:
+      // n >= 13 needs more LDS than one CU holds at 128 columns
+      if (n >= 13) return sigma_dgemm_n<64>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
+      return sigma_dgemm_n<128>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
     default: return false;
   }
 }

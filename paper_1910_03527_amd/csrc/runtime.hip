@@ -63,7 +63,7 @@ struct StringTab {
 // One kernel-shape group of a plan: items with the same active size n share
 // the sigma contraction kernel (its pair dimension is a template parameter).
 struct Group {
-  int n = 0, tn = 64, tiles_per_wg = 4;
+  int n = 0, tn = 64, tiles_per_wg = 16;
   std::vector<Work> tiles;
   std::vector<int> item_lo, item_hi;  // per item of the plan: its tile range (or empty)
   Work* d_tiles = nullptr;
@@ -190,10 +190,11 @@ const StringTab& string_tab(mbefci_ctx* c, int n, int ne) {
 }
 
 int tile_for(mbefci_ctx* c, int n) {
-  if (c->opts.tile == 32 || c->opts.tile == 64 || c->opts.tile == 128) return c->opts.tile;
+  if (c->opts.tile == 32 || c->opts.tile == 64 || c->opts.tile == 128)
+    return (n >= 13 && c->opts.tile == 128) ? 64 : c->opts.tile;
   auto it = c->tuned_tile.find(n);
   if (it != c->tuned_tile.end()) return it->second;
-  return 64;
+  return n >= 10 ? 32 : 64;  // measured defaults when nothing is tuned
 }
 
 // --------------------------------------------------------------- planning
@@ -284,10 +285,13 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
     if (P.item_group[i] < 0) continue;
     Group& g = P.groups[P.item_group[i]];
     const Item& I = P.items[i];
-    const int ntile = (int)((I.ndet + g.tn - 1) / g.tn);
+    // work unit: tiles (one alpha string x tn beta strings) numbered
+    // column-major, tile = block * Na + Ka; a unit never crosses a beta block
+    const int nblk = (I.Nb + g.tn - 1) / g.tn;
     g.item_lo[i] = (int)g.tiles.size();
-    for (int b = 0; b < ntile; b += g.tiles_per_wg)
-      g.tiles.push_back(Work{i, b, std::min(b + g.tiles_per_wg, ntile), 0});
+    for (int bk = 0; bk < nblk; ++bk)
+      for (int a = 0; a < I.Na; a += g.tiles_per_wg)
+        g.tiles.push_back(Work{i, bk * I.Na + a, bk * I.Na + std::min(a + g.tiles_per_wg, I.Na), 0});
     g.item_hi[i] = (int)g.tiles.size();
   }
   // sigma passes: G offsets restart at every pass
