@@ -233,7 +233,8 @@ __device__ void build_item_hamiltonian(const ActiveSet& s, int M, const double* 
 __global__ void k_mbe_setup(MbeSpaces sp, const BucketDev* __restrict__ buckets, int nbucket,
                             const Item* __restrict__ items, const double* __restrict__ h1,
                             const double* __restrict__ eri, double e_const, ItemHam* hams,
-                            double* warena, int32_t* tuple_pos, int max_order) {
+                            double* warena, int32_t* tuple_pos, int max_order,
+                            int32_t* act_out) {
   const int it = blockIdx.x;
   __shared__ ActiveSet s;
   if (threadIdx.x == 0) {
@@ -268,6 +269,8 @@ __global__ void k_mbe_setup(MbeSpaces sp, const BucketDev* __restrict__ buckets,
       if (!in) s.frz[s.nf++] = o;
     }
     s.na = sp.nocc_ref + bk.nocc;
+    if (act_out)
+      for (int i = 0; i < kMaxActive; ++i) act_out[it * kMaxActive + i] = i < nt ? tmp[i] : -1;
     if (tuple_pos) {
       // positions: occupied part (indices into Xo), then virtual part (into Xv)
       int32_t* tp = tuple_pos + (int64_t)it * (2 * max_order + 2);
@@ -981,6 +984,300 @@ __global__ void k_dav_grow(DavState* st, int ibase, int nitem) {
   if (!S.conv) S.m += 1;
 }
 
+// ------------------------------------------------------------------- RDMs
+// For a converged CASCI vector c (normalised):
+//   gamma+_ab  = sum_K c_K D+_ab[K]            (= 2 gamma_ab for a > b, gamma_aa)
+//   Gamma+_{ab,cd} = sum_K D+_ab[K] D+_cd[K]   (a symmetric rank-update on FP64 MFMA)
+// with gamma_pq = <E_pq>, Gamma_pqrs = <E_pq E_rs> - d_qr gamma_ps.  The CI
+// vector itself is carried as row NP of the D+ tile (a padding row), so
+// gamma+ is column NP of Gamma+ and Gamma+_{NP,NP} = |c|^2.  Each workgroup
+// accumulates the upper 16x16 blocks over its tiles in registers and writes
+// one partial; k_rdm_reduce sums the partials in a fixed order.
+template <int NACT, int TN>
+__global__ void __launch_bounds__(256) k_rdm_syrk(const Item* __restrict__ items,
+                                                  const Work* __restrict__ work,
+                                                  const double* __restrict__ civ,
+                                                  double* __restrict__ part) {
+  constexpr int NP = NACT * (NACT + 1) / 2;
+  constexpr int KPAD = (NP + 15) / 16 * 16;
+  constexpr int KR = ((NP + 1) + 3) / 4 * 4;  // D+ rows plus the c row
+  constexpr int NRB = KPAD / 16;
+  constexpr int NBLK = NRB * (NRB + 1) / 2;   // upper 16x16 blocks
+  constexpr int BPW = (NBLK + 3) / 4;         // blocks per wave
+  constexpr int NSUB = 256 / TN;
+  constexpr int NPER = (NP + NSUB - 1) / NSUB;
+  constexpr int LDT = TN + 1;
+  constexpr int CMAX = (int)binom_c(NACT, NACT / 2);
+  static_assert(NP < KPAD, "the c row needs a padding row");
+  __shared__ double Ds[KPAD * LDT];
+  __shared__ int32_t Tb[NP * TN];
+  __shared__ double Cr[CMAX];
+
+  const Work wk = work[blockIdx.x];
+  const Item& I = items[wk.item];
+  const double* __restrict__ c = civ + I.off;
+  const int Na = I.Na, Nb = I.Nb;
+  const int32_t* __restrict__ pA = I.pairA;
+  const int32_t* __restrict__ pB = I.pairB;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int col = t % TN;
+  const int sub = (TN >= 64) ? __builtin_amdgcn_readfirstlane(t / TN) : t / TN;
+  const int blk = wk.begin / Na;
+  const int Kb0 = blk * TN;
+  const int Kb = Kb0 + col;
+  const double keep = Kb < Nb ? 1.0 : 0.0;
+  const int Kbc = Kb < Nb ? Kb : Nb - 1;
+  for (int x = t; x < NP * TN; x += 256) {
+    const int ab = x / TN, cc = x - ab * TN;
+    const int kb = Kb0 + cc < Nb ? Kb0 + cc : Nb - 1;
+    Tb[x] = ldg(pB + ab * Nb + kb);
+  }
+  for (int x = (NP + 1) * LDT + t; x < KPAD * LDT; x += 256) Ds[x] = 0.0;
+  // this wave's output blocks (rb <= cb) in a fixed enumeration
+  int brb[BPW], bcb[BPW];
+  double4_t acc[BPW];
+#pragma unroll
+  for (int u = 0; u < BPW; ++u) {
+    int id = wave + 4 * u, rb = 0;
+    while (id >= NRB - rb && rb < NRB) { id -= NRB - rb; ++rb; }
+    brb[u] = rb;
+    bcb[u] = rb + id;
+    acc[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  }
+  for (int tile = wk.begin; tile < wk.end; ++tile) {
+    const int Ka = tile - blk * Na;
+    for (int x = t; x < Nb; x += 256) Cr[x] = ldg(c + Ka * Nb + x);
+    __syncthreads();
+    const int32_t* __restrict__ pa = pA + Ka * NP;
+    const double* __restrict__ ca = c + Kbc;
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) {
+      const int ab = sub + NSUB * i;
+      if (ab < NP) {
+        const int32_t ea = ldc(pa + ab);
+        const int32_t eb = Tb[ab * TN + col];
+        const int ja = ea ? (ea >> 1) - 1 : 0, jb = eb ? (eb >> 1) - 1 : 0;
+        const double fa = ea ? ((ea & 1) ? -keep : keep) : 0.0;
+        const double fb = eb ? ((eb & 1) ? -keep : keep) : 0.0;
+        Ds[ab * LDT + col] = fa * ldg(ca + ja * Nb) + fb * Cr[jb];
+      }
+    }
+    if (sub == 0) Ds[NP * LDT + col] = keep * Cr[Kbc];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < BPW; ++u) {
+      if (wave + 4 * u >= NBLK) continue;
+      const double* ar = Ds + (brb[u] * 16 + (lane & 15)) * LDT + (lane >> 4);
+      const double* br = Ds + (bcb[u] * 16 + (lane & 15)) * LDT + (lane >> 4);
+#pragma unroll
+      for (int k = 0; k < TN; k += 4)
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[k], br[k], acc[u], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* out = part + (int64_t)blockIdx.x * KPAD * KPAD;
+#pragma unroll
+  for (int u = 0; u < BPW; ++u) {
+    if (wave + 4 * u >= NBLK) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = brb[u] * 16 + (lane >> 4) + 4 * v, cc = bcb[u] * 16 + (lane & 15);
+      out[r * KPAD + cc] = acc[u][v];
+    }
+  }
+}
+
+// Sum the partials of every item in work order; fill the lower triangle.
+// rdmp: [item][KPAD*KPAD] (KPAD of that item).
+__global__ void k_rdm_reduce(const Item* __restrict__ items, const int32_t* __restrict__ wlo,
+                             const int32_t* __restrict__ whi, const double* __restrict__ part,
+                             const int64_t* __restrict__ poff, double* rdmp,
+                             const int64_t* __restrict__ roff) {
+  const int it = blockIdx.x;
+  const Item& I = items[it];
+  const int kp = I.kpad;
+  double* out = rdmp + roff[it];
+  for (int x = threadIdx.x; x < kp * kp; x += blockDim.x) {
+    const int r = x / kp, cc = x % kp;
+    const int rr = r < cc ? r : cc, c2 = r < cc ? cc : r;  // upper triangle holds the data
+    double sacc = 0.0;
+    if (I.ndet == 1) {
+      // single determinant: D+_aa = occupation, c = 1
+      sacc = 0.0;
+    } else {
+      for (int w = wlo[it]; w < whi[it]; ++w) sacc += part[poff[w] + rr * kp + c2];
+    }
+    out[x] = sacc;
+  }
+}
+
+// ------------------------------------------------------ gradient assembly
+// Weight of f(U) in L = g_0 E_ref + sum_n g_n E^(n): from the closed form
+// E^(n) = sum_{|U| <= n} (-1)^{n-|U|} C(M_exp - |U|, n - |U|) f(U), f(()) = E_ref
+// (the Moebius solution of the recursion of Eq. 2).
+__global__ void k_mbe_weights(const BucketDev* __restrict__ buckets, int nbucket, int nitem,
+                              int nexp, int max_order, const double* __restrict__ g, double* w) {
+  int it = blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= nitem) return;
+  int b = 0;
+  while (b + 1 < nbucket && buckets[b + 1].item0 <= it) ++b;
+  const int u = buckets[b].order;
+  double acc = (u == 0) ? g[0] : 0.0;
+  for (int n = (u > 1 ? u : 1); n <= max_order; ++n) {
+    const double cb = (double)binom(nexp - u, n - u);
+    acc += (((n - u) & 1) ? -cb : cb) * g[n];
+  }
+  w[it] = acc;
+}
+
+// Orbital class of p in CASCI `it`: >= 0 local active index, -1 frozen
+// (doubly occupied), -2 deleted.  A single-determinant CASCI has its active
+// orbitals either all occupied or all empty and is treated as frozen/deleted.
+__device__ inline int orb_class(const int32_t* __restrict__ act, int n, bool single,
+                                uint64_t occmask, int p) {
+  if (!single)
+    for (int t = 0; t < n; ++t)
+      if (act[t] == p) return t;
+  return (occmask >> p & 1) ? -1 : -2;
+}
+
+// gamma_tu of an item from Gamma+ (column NP holds gamma+ = D+ c)
+__device__ inline double act_gamma(const double* __restrict__ R, int kp, int np, int t, int u) {
+  const double g = R[pair_index(t, u) * kp + np];
+  return t == u ? g : 0.5 * g;
+}
+
+// 1/4 [G_pqrs + G_qprs + G_pqsr + G_qpsr] of the full-space 2-RDM of one
+// CASCI, G = <E_pq E_rs> - d_qr gamma_ps (frozen orbitals doubly occupied).
+__device__ double sym_gamma2(int p, int q, int r, int s, int cp, int cq, int cr, int cs,
+                             const double* __restrict__ R, int kp, int np) {
+  if (cp == -2 || cq == -2 || cr == -2 || cs == -2) return 0.0;
+  if (cp >= 0 && cq >= 0 && cr >= 0 && cs >= 0) {
+    const double mpq = cp == cq ? 2.0 : 1.0, mrs = cr == cs ? 2.0 : 1.0;
+    double v = mpq * mrs * R[pair_index(cp, cq) * kp + pair_index(cr, cs)];
+    if (cq == cr) v -= act_gamma(R, kp, np, cp, cs);
+    if (cp == cr) v -= act_gamma(R, kp, np, cq, cs);
+    if (cq == cs) v -= act_gamma(R, kp, np, cp, cr);
+    if (cp == cs) v -= act_gamma(R, kp, np, cq, cr);
+    return 0.25 * v;
+  }
+  // some index frozen: average the raw element over the four index orders
+  const int P[4][4] = {{p, q, r, s}, {q, p, r, s}, {p, q, s, r}, {q, p, s, r}};
+  const int C[4][4] = {{cp, cq, cr, cs}, {cq, cp, cr, cs}, {cp, cq, cs, cr}, {cq, cp, cs, cr}};
+  double acc = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    const int a = P[k][0], b = P[k][1], c = P[k][2], d = P[k][3];
+    const int ca = C[k][0], cb = C[k][1], cc = C[k][2], cd = C[k][3];
+    const bool Fa = ca == -1, Fb = cb == -1, Fc = cc == -1, Fd = cd == -1;
+    const bool Aa = ca >= 0, Ab = cb >= 0, Ac = cc >= 0, Ad = cd >= 0;
+    double v = 0.0;
+    if (Fa && Fb && Fc && Fd) {
+      if (a == b && c == d) v = (a == c) ? 2.0 : 4.0;
+      else if (a == d && b == c) v = -2.0;
+    } else if (Fa && Fb && a == b && Ac && Ad) {
+      v = 2.0 * act_gamma(R, kp, np, cc, cd);
+    } else if (Fc && Fd && c == d && Aa && Ab) {
+      v = 2.0 * act_gamma(R, kp, np, ca, cb);
+    } else if (Fb && Fc && b == c && Aa && Ad) {
+      v = -act_gamma(R, kp, np, ca, cd);
+    } else if (Fa && Fd && a == d && Ab && Ac) {
+      v = -act_gamma(R, kp, np, cc, cb);
+    }
+    acc += v;
+  }
+  return 0.25 * acc;
+}
+
+// dE/dh_pq = sum_it w_it gamma_full(p, q)
+__global__ void k_grad_h(const Item* __restrict__ items, int nitem, const int32_t* __restrict__ act,
+                         uint64_t occmask, int M, const double* __restrict__ w,
+                         const double* __restrict__ rdmp, const int64_t* __restrict__ roff,
+                         double* out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= M * M) return;
+  const int p = x / M, q = x % M;
+  double acc = 0.0;
+  for (int it = 0; it < nitem; ++it) {
+    const double wt = w[it];
+    if (wt == 0.0) continue;
+    const Item& I = items[it];
+    const bool single = I.ndet == 1;
+    const int32_t* a = act + it * kMaxActive;
+    const int cp = orb_class(a, I.n, single, occmask, p), cq = orb_class(a, I.n, single, occmask, q);
+    double v = 0.0;
+    if (cp == -1 && cq == -1 && p == q) v = 2.0;
+    else if (cp >= 0 && cq >= 0) v = act_gamma(rdmp + roff[it], I.kpad, I.npair, cp, cq);
+    acc += wt * v;
+  }
+  out[x] = acc;
+}
+
+// dE/d(pq|rs) = sum_it w_it 1/2 Sym8(Gamma_full)_pqrs
+__global__ void k_grad_g(const Item* __restrict__ items, int nitem, const int32_t* __restrict__ act,
+                         uint64_t occmask, int M, const double* __restrict__ w,
+                         const double* __restrict__ rdmp, const int64_t* __restrict__ roff,
+                         double* out) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t M2 = (int64_t)M * M;
+  if (x >= M2 * M2) return;
+  const int p = (int)(x / (M2 * M)), q = (int)((x / M2) % M), r = (int)((x / M) % M),
+            s = (int)(x % M);
+  double acc = 0.0;
+  for (int it = 0; it < nitem; ++it) {
+    const double wt = w[it];
+    if (wt == 0.0) continue;
+    const Item& I = items[it];
+    const bool single = I.ndet == 1;
+    const int32_t* a = act + it * kMaxActive;
+    const int cp = orb_class(a, I.n, single, occmask, p);
+    if (cp == -2) continue;
+    const int cq = orb_class(a, I.n, single, occmask, q);
+    if (cq == -2) continue;
+    const int cr = orb_class(a, I.n, single, occmask, r);
+    if (cr == -2) continue;
+    const int cs = orb_class(a, I.n, single, occmask, s);
+    if (cs == -2) continue;
+    acc += wt * 0.5 * sym_gamma2(p, q, r, s, cp, cq, cr, cs, rdmp + roff[it], I.kpad, I.npair);
+  }
+  out[x] = acc;
+}
+
+// RDMs of one whole-space CASCI: rdm1 = gamma, rdm2 = Sym8(Gamma).
+__global__ void k_casci_rdm_out(const Item* __restrict__ items, int it,
+                                const double* __restrict__ rdmp, const int64_t* __restrict__ roff,
+                                double* rdm1, double* rdm2) {
+  const Item& I = items[it];
+  const int n = I.n;
+  const double* R = rdmp + roff[it];
+  const int64_t n2 = (int64_t)n * n;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n2 * n2;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const int p = (int)(x / (n2 * n)), q = (int)((x / n2) % n), r = (int)((x / n) % n),
+              s = (int)(x % n);
+    if (rdm2) {
+      double v;
+      if (I.ndet == 1) {
+        // every active orbital doubly occupied (nalpha = nbeta = n) or empty
+        const bool full = I.na == n;
+        v = 0.0;
+        if (full) {
+          if (p == q && r == s) v = (p == r) ? 2.0 : 4.0;
+          else if (p == s && q == r) v = -1.0;  // Sym8 of -2 over the (ij|ji) orbit
+          else if ((p == r && q == s) && p != q) v = -1.0;
+        }
+      } else {
+        v = sym_gamma2(p, q, r, s, p, q, r, s, R, I.kpad, I.npair);
+      }
+      rdm2[x] = v;
+    }
+    if (rdm1 && x < n2) {
+      const int a = (int)(x / n), b = (int)(x % n);
+      rdm1[x] = I.ndet == 1 ? ((a == b && I.na == n) ? 2.0 : 0.0)
+                            : act_gamma(R, I.kpad, I.npair, a, b);
+    }
+  }
+}
+
 // ---------------------------------------------------------- MBE combine
 // f(T) = E_core(T) + theta_T ; eps_T = f(T) - E_ref ;
 // Delta eps_T = sum over non-empty U in T of (-1)^{|T|-|U|} eps_U, which is the
@@ -1169,9 +1466,9 @@ void launch_pair_table(int n, int ne, int64_t N, int32_t* out, int32_t* outT, hi
 void launch_mbe_setup(const MbeSpaces* sp, const BucketDev* buckets, int nbucket, const Item* items,
                       int nitem, const double* h1, const double* eri, double e_const,
                       ItemHam* hams, double* warena, int32_t* tuple_pos, int max_order,
-                      hipStream_t s) {
+                      int32_t* act_out, hipStream_t s) {
   hipLaunchKernelGGL(k_mbe_setup, dim3(nitem), dim3(256), 0, s, *sp, buckets, nbucket, items, h1,
-                     eri, e_const, hams, warena, tuple_pos, max_order);
+                     eri, e_const, hams, warena, tuple_pos, max_order, act_out);
 }
 void launch_casci_setup(int n, const double* const* h1s, const double* const* eris,
                         const double* ecores, const Item* items, int nitem, ItemHam* hams,
@@ -1326,5 +1623,55 @@ void launch_state_unconv(const Item* items, DavState* st, int nitem, hipStream_t
 }
 void launch_mbe_total(const double* f, const double* e_order, int k, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_mbe_total, dim3(1), dim3(64), 0, s, f, e_order, k, out);
+}
+}  // namespace mbefci
+
+namespace mbefci {
+template <int NACT, int TN>
+static void rdm_syrk_t(const Item* items, const Work* work, int nwork, const double* civ,
+                       double* part, hipStream_t s) {
+  hipLaunchKernelGGL((k_rdm_syrk<NACT, TN>), dim3(nwork), dim3(256), 0, s, items, work, civ, part);
+}
+bool launch_rdm_syrk(int n, int tn, const Item* items, const Work* work, int nwork,
+                     const double* civ, double* part, hipStream_t s) {
+  if (nwork <= 0) return true;
+  if (tn != 64) return false;
+  switch (n) {
+#define MBEFCI_CASE(N) \
+  case N: rdm_syrk_t<N, 64>(items, work, nwork, civ, part, s); return true;
+    MBEFCI_CASE(2) MBEFCI_CASE(3) MBEFCI_CASE(4) MBEFCI_CASE(5) MBEFCI_CASE(6) MBEFCI_CASE(7)
+    MBEFCI_CASE(8) MBEFCI_CASE(9) MBEFCI_CASE(10) MBEFCI_CASE(11) MBEFCI_CASE(12)
+    MBEFCI_CASE(13) MBEFCI_CASE(14)
+#undef MBEFCI_CASE
+    default: return false;
+  }
+}
+void launch_rdm_reduce(const Item* items, int nitem, const int32_t* wlo, const int32_t* whi,
+                       const double* part, const int64_t* poff, double* rdmp, const int64_t* roff,
+                       hipStream_t s) {
+  if (nitem > 0)
+    hipLaunchKernelGGL(k_rdm_reduce, dim3(nitem), dim3(256), 0, s, items, wlo, whi, part, poff,
+                       rdmp, roff);
+}
+void launch_mbe_weights(const BucketDev* buckets, int nbucket, int nitem, int nexp, int max_order,
+                        const double* g, double* w, hipStream_t s) {
+  hipLaunchKernelGGL(k_mbe_weights, dim3(nblk(nitem, 64)), dim3(64), 0, s, buckets, nbucket, nitem,
+                     nexp, max_order, g, w);
+}
+void launch_grad(const Item* items, int nitem, const int32_t* act, uint64_t occmask, int M,
+                 const double* w, const double* rdmp, const int64_t* roff, double* dh, double* dg,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_h, dim3(nblk((int64_t)M * M, 256)), dim3(256), 0, s, items, nitem, act,
+                     occmask, M, w, rdmp, roff, dh);
+  const int64_t M4 = (int64_t)M * M * M * M;
+  hipLaunchKernelGGL(k_grad_g, dim3(nblk(M4, 256)), dim3(256), 0, s, items, nitem, act, occmask, M,
+                     w, rdmp, roff, dg);
+}
+void launch_casci_rdm_out(const Item* items, int it, int n, const double* rdmp,
+                          const int64_t* roff, double* rdm1, double* rdm2, hipStream_t s) {
+  const int64_t n4 = (int64_t)n * n * n * n;
+  int b = nblk(n4, 256);
+  if (b > 4096) b = 4096;
+  hipLaunchKernelGGL(k_casci_rdm_out, dim3(b), dim3(256), 0, s, items, it, rdmp, roff, rdm1, rdm2);
 }
 }  // namespace mbefci

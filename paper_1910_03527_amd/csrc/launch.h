@@ -14,7 +14,7 @@ void launch_pair_table(int n, int ne, int64_t N, int32_t* out, int32_t* outT, hi
 void launch_mbe_setup(const MbeSpaces* sp, const BucketDev* buckets, int nbucket, const Item* items,
                       int nitem, const double* h1, const double* eri, double e_const,
                       ItemHam* hams, double* warena, int32_t* tuple_pos, int max_order,
-                      hipStream_t s);
+                      int32_t* act_out, hipStream_t s);
 void launch_casci_setup(int n, const double* const* h1s, const double* const* eris,
                         const double* ecores, const Item* items, int nitem, ItemHam* hams,
                         double* warena, hipStream_t s);
@@ -56,6 +56,19 @@ void launch_ritz_vector(const Item* items, const Work* chunks, int nchunk, const
                         int64_t ntot, const DavState* st, double* out, hipStream_t s);
 void launch_state_unconv(const Item* items, DavState* st, int nitem, hipStream_t s);
 void launch_mbe_total(const double* f, const double* e_order, int k, double* out, hipStream_t s);
+
+bool launch_rdm_syrk(int n, int tn, const Item* items, const Work* work, int nwork,
+                     const double* civ, double* part, hipStream_t s);
+void launch_rdm_reduce(const Item* items, int nitem, const int32_t* wlo, const int32_t* whi,
+                       const double* part, const int64_t* poff, double* rdmp, const int64_t* roff,
+                       hipStream_t s);
+void launch_mbe_weights(const BucketDev* buckets, int nbucket, int nitem, int nexp, int max_order,
+                        const double* g, double* w, hipStream_t s);
+void launch_grad(const Item* items, int nitem, const int32_t* act, uint64_t occmask, int M,
+                 const double* w, const double* rdmp, const int64_t* roff, double* dh, double* dg,
+                 hipStream_t s);
+void launch_casci_rdm_out(const Item* items, int it, int n, const double* rdmp,
+                          const int64_t* roff, double* rdm1, double* rdm2, hipStream_t s);
 
 constexpr int kChunkElems = 4096;   // elements per Davidson reduction chunk
 constexpr int kPartStride = kMaxSpace + 2;

@@ -102,6 +102,7 @@ struct Plan {
   ItemHam* hams = nullptr;
   DavState* st = nullptr;
   int32_t* tuple_pos = nullptr;
+  int32_t* act = nullptr;  // [item][kMaxActive] active orbitals (MBE) or -1
   int* d_count = nullptr;
   int32_t* d_collect = nullptr;
   // MBE description (for the combine and the backward)
@@ -637,6 +638,76 @@ void casci_plan(mbefci_ctx* c, int nprob, int n, int na, int nb, const double* c
   HIPCHK(hipGetLastError());
 }
 
+// ------------------------------------------------------------- RDM pass
+// Gamma+ and gamma+ of every multi-determinant CASCI of the plan from the
+// CI vectors kept by the last solve (P.ci), into the "rdm" arena
+// [item][kpad*kpad] (offsets roff).  Returns the device pointers.
+struct RdmOut {
+  double* rdmp;
+  int64_t* roff;
+};
+
+RdmOut rdm_pass(mbefci_ctx* c, Plan& P) {
+  const int TN = 64;
+  std::vector<std::vector<Work>> gwork(P.groups.size());
+  std::vector<int32_t> wlo(P.nitem, 0), whi(P.nitem, 0);
+  std::vector<int64_t> roff(P.nitem, 0);
+  int64_t rtot = 0;
+  for (int i = 0; i < P.nitem; ++i) {
+    roff[i] = rtot;
+    rtot += (int64_t)P.items[i].kpad * P.items[i].kpad;
+  }
+  // work units: per beta block, alpha ranges sized so that one CASCI has at
+  // most about 512 partials
+  std::vector<int> order;  // global work order: group by group, item by item
+  std::vector<int64_t> poff;
+  int64_t ptot = 0;
+  int gcount = 0;
+  std::vector<int> wstart(P.groups.size(), 0);
+  for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+    wstart[gi] = gcount;
+    for (int i = 0; i < P.nitem; ++i) {
+      if (P.item_group[i] != (int)gi) continue;
+      const Item& I = P.items[i];
+      const int nblk = (I.Nb + TN - 1) / TN;
+      const int csz = std::max(16, (int)(((int64_t)I.Na * nblk + 511) / 512));
+      wlo[i] = gcount + (int)gwork[gi].size();
+      for (int bk = 0; bk < nblk; ++bk)
+        for (int a = 0; a < I.Na; a += csz)
+          gwork[gi].push_back(Work{i, bk * I.Na + a, bk * I.Na + std::min(a + csz, I.Na), 0});
+      whi[i] = gcount + (int)gwork[gi].size();
+    }
+    for (size_t k = 0; k < gwork[gi].size(); ++k) {
+      poff.push_back(ptot);
+      ptot += (int64_t)P.items[gwork[gi][k].item].kpad * P.items[gwork[gi][k].item].kpad;
+    }
+    gcount += (int)gwork[gi].size();
+  }
+  double* part = arena<double>(c, "rdm_part", std::max<int64_t>(ptot, 1));
+  double* rdmp = arena<double>(c, "rdm", std::max<int64_t>(rtot, 1));
+  int64_t* d_roff = arena<int64_t>(c, "rdm_roff", P.nitem);
+  int64_t* d_poff = arena<int64_t>(c, "rdm_poff", std::max<size_t>(poff.size(), 1));
+  int32_t* d_wlo = arena<int32_t>(c, "rdm_wlo", P.nitem);
+  int32_t* d_whi = arena<int32_t>(c, "rdm_whi", P.nitem);
+  Work* d_work = arena<Work>(c, "rdm_work", std::max(gcount, 1));
+  std::vector<Work> all;
+  for (auto& v : gwork) all.insert(all.end(), v.begin(), v.end());
+  upload(c, d_roff, roff);
+  upload(c, d_poff, poff);
+  upload(c, d_wlo, wlo);
+  upload(c, d_whi, whi);
+  upload(c, d_work, all);
+  for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+    if (!launch_rdm_syrk(P.groups[gi].n, TN, P.d_items, d_work + wstart[gi],
+                         (int)gwork[gi].size(), P.ci, part + (gwork[gi].empty() ? 0 : poff[wstart[gi]]),
+                         c->stream))
+      throw Error(MBEFCI_EUNSUPPORTED, "no RDM kernel for n=" + std::to_string(P.groups[gi].n));
+  }
+  launch_rdm_reduce(P.d_items, P.nitem, d_wlo, d_whi, part, d_poff, rdmp, d_roff, c->stream);
+  HIPCHK(hipGetLastError());
+  return RdmOut{rdmp, d_roff};
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -858,8 +929,17 @@ int mbefci_casci(mbefci_ctx* c, int32_t nprob, int32_t n, int32_t na, int32_t nb
 
 int mbefci_casci_rdm(mbefci_ctx* c, double* const* rdm1s, double* const* rdm2s, void* stream) {
   return guarded(c, [&] {
-    (void)rdm1s; (void)rdm2s; (void)stream;
-    throw Error(MBEFCI_EUNSUPPORTED, "casci RDMs are not built yet");
+    if (!c->plan || c->plan->is_mbe || !c->have_forward)
+      throw Error(MBEFCI_EINVAL, "mbefci_casci_rdm needs a preceding mbefci_casci on ctx");
+    if (!c->opts.keep_ci) throw Error(MBEFCI_EINVAL, "CI vectors were not kept (keep_ci = 0)");
+    StreamScope sc(c, stream);
+    Plan& P = *c->plan;
+    RdmOut R = rdm_pass(c, P);
+    for (int i = 0; i < P.nitem; ++i)
+      launch_casci_rdm_out(P.d_items, i, P.items[i].n, R.rdmp, R.roff, rdm1s ? rdm1s[i] : nullptr,
+                           rdm2s ? rdm2s[i] : nullptr, c->stream);
+    HIPCHK(hipGetLastError());
+    sc.done();
   });
 }
 
@@ -956,6 +1036,7 @@ int mbefci_mbe_forward(mbefci_ctx* c, const mbefci_problem* pb, double* e_ref, d
       P.d_buckets = arena<BucketDev>(c, "buckets", P.buckets.size());
       upload(c, P.d_buckets, P.buckets);
       P.tuple_pos = arena<int32_t>(c, "tuple_pos", (size_t)P.nitem * (2 * P.max_order + 2));
+      P.act = arena<int32_t>(c, "act", (size_t)P.nitem * kMaxActive);
       // X sorted; positions of Xo / Xv members in it (for lexicographic output)
       std::vector<int> xs;
       for (int o = 0; o < M; ++o)
@@ -982,7 +1063,7 @@ int mbefci_mbe_forward(mbefci_ctx* c, const mbefci_problem* pb, double* e_ref, d
     Plan& P = *c->plan;
     // ---- set-up, solve, combine
     launch_mbe_setup(&P.sp, P.d_buckets, (int)P.buckets.size(), P.d_items, P.nitem, pb->h1,
-                     pb->eri, pb->e_const, P.hams, P.W, P.tuple_pos, P.max_order, c->stream);
+                     pb->eri, pb->e_const, P.hams, P.W, P.tuple_pos, P.max_order, P.act, c->stream);
     HIPCHK(hipGetLastError());
     mbefci_stats st{};
     solve_plan(c, P, &st);
@@ -1030,11 +1111,30 @@ int mbefci_mbe_forward(mbefci_ctx* c, const mbefci_problem* pb, double* e_ref, d
 int mbefci_mbe_backward(mbefci_ctx* c, const double* grad_out, double* d_h1, double* d_eri,
                         void* stream) {
   return guarded(c, [&] {
-    (void)grad_out; (void)d_h1; (void)d_eri; (void)stream;
-    throw Error(MBEFCI_EUNSUPPORTED, "the backward is not built yet");
+    if (!c->plan || !c->plan->is_mbe || !c->have_forward)
+      throw Error(MBEFCI_EINVAL, "mbefci_mbe_backward needs a preceding mbefci_mbe_forward on ctx");
+    if (!c->opts.keep_ci) throw Error(MBEFCI_EINVAL, "CI vectors were not kept (keep_ci = 0)");
+    if (!grad_out || !d_h1 || !d_eri) throw Error(MBEFCI_EINVAL, "null argument");
+    Plan& P = *c->plan;
+    for (int n = 0; n <= P.max_order; ++n)
+      if (!std::isfinite(grad_out[n])) throw Error(MBEFCI_EINVAL, "grad_out holds a non-finite value");
+    StreamScope sc(c, stream);
+    RdmOut R = rdm_pass(c, P);
+    double* d_g = arena<double>(c, "grad_out", P.max_order + 1);
+    double* d_w = arena<double>(c, "weights", P.nitem);
+    std::vector<double> g(grad_out, grad_out + P.max_order + 1);
+    upload(c, d_g, g);
+    launch_mbe_weights(P.d_buckets, (int)P.buckets.size(), P.nitem, (int)P.xsorted.size(),
+                       P.max_order, d_g, d_w, c->stream);
+    uint64_t occmask = 0;
+    for (int i = 0; i < P.sp.nO; ++i) occmask |= (uint64_t)1 << P.sp.O[i];
+    launch_grad(P.d_items, P.nitem, P.act, occmask, P.norb, d_w, R.rdmp, R.roff, d_h1, d_eri,
+                c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    sc.done();
   });
 }
-
 
 int mbefci_time_kernels(mbefci_ctx* c, int32_t reps, mbefci_kernel_time* out, int32_t cap,
                         int32_t* count) {
