@@ -63,7 +63,9 @@ typedef struct {
   int32_t nguess;        /* lowest-diagonal unit guess vectors, 1..8 (default 2)    */
   int32_t mode;          /* MBEFCI_BATCHED (default) or MBEFCI_PER_LAUNCH            */
   int32_t use_graph;     /* batched mode: replay captured iterations (default 1)     */
-  int32_t tile;          /* sigma tile width 32/64/128, 0 = autotuned (default 0)    */
+  int32_t tile;          /* sigma tile width 32/64/128; 0 = autotuned schedule: the
+                            first batched solve of a plan times the candidates per
+                            active size and keeps the fastest (default 0)       */
   int32_t keep_ci;       /* keep converged CI vectors for the backward (default 1)   */
   int32_t validate;      /* host checks of integral symmetry/finiteness (default 1)  */
   int32_t sigma_pass_mb; /* sigma sweeps run in passes whose G block (the W-contracted
@@ -72,7 +74,8 @@ typedef struct {
                             0 = one pass (default 0) */
   int32_t pad_;
   int64_t max_workspace; /* workspace cap in bytes, 0 = no cap                       */
-  const char* tune_cache;/* autotuner cache file (read/written) or NULL              */
+  const char* tune_cache;/* autotuner cache file (read/written) or NULL: one line per
+                            active size n, "n tile tiles_per_workgroup"          */
 } mbefci_opts;
 
 typedef struct {
@@ -100,6 +103,7 @@ typedef struct {
   int32_t graph_launches;    /* replays of the captured iteration graph           */
   double ms_total;           /* wall time of the call (host clock)                */
   double ms_solve;           /* device time of the Davidson phase (HIP events)    */
+  double ms_tune;            /* host time spent autotuning so far on this context */
 } mbefci_stats;
 
 /* ---- context ------------------------------------------------------------ */

@@ -72,6 +72,7 @@ class Stats(ctypes.Structure):
         ("graph_launches", ctypes.c_int32),
         ("ms_total", ctypes.c_double),
         ("ms_solve", ctypes.c_double),
+        ("ms_tune", ctypes.c_double),
     ]
 
     def as_dict(self):

@@ -107,6 +107,7 @@ struct Plan {
   int32_t* d_collect = nullptr;
   // MBE description (for the combine and the backward)
   bool is_mbe = false;
+  bool tuned = false;
   MbeSpaces sp{};
   int max_order = 0, norb = 0;
   int64_t ntuples = 0;
@@ -128,7 +129,11 @@ struct mbefci_ctx {
   std::map<std::pair<int, int>, StringTab> tabs;
   std::map<std::string, DevBuf> bufs;
   std::unique_ptr<Plan> plan;
-  std::map<int, int> tuned_tile;  // active size n -> tile width
+  // autotuned sigma-contraction schedule per active size n: (tile width,
+  // tiles per workgroup); loaded from / saved to opts.tune_cache when set
+  std::map<int, std::pair<int, int>> tuned;
+  bool cache_loaded = false;
+  double ms_tune = 0.0;
   bool have_forward = false;
   std::vector<double> host_scratch;
 };
@@ -193,12 +198,104 @@ const StringTab& string_tab(mbefci_ctx* c, int n, int ne) {
 int tile_for(mbefci_ctx* c, int n) {
   if (c->opts.tile == 32 || c->opts.tile == 64 || c->opts.tile == 128)
     return (n >= 13 && c->opts.tile == 128) ? 64 : c->opts.tile;
-  auto it = c->tuned_tile.find(n);
-  if (it != c->tuned_tile.end()) return it->second;
+  auto it = c->tuned.find(n);
+  if (it != c->tuned.end()) return it->second.first;
   return n >= 10 ? 32 : 64;  // measured defaults when nothing is tuned
+}
+int tpw_for(mbefci_ctx* c, int n) {
+  auto it = c->tuned.find(n);
+  if (c->opts.tile == 0 && it != c->tuned.end()) return it->second.second;
+  return 16;
+}
+
+// tune cache: one line per active size, "n tile tiles_per_wg"
+void load_tune_cache(mbefci_ctx* c) {
+  if (c->cache_loaded || !c->opts.tune_cache) return;
+  c->cache_loaded = true;
+  FILE* f = std::fopen(c->opts.tune_cache, "r");
+  if (!f) return;
+  int n, tn, tpw;
+  char line[128];
+  while (std::fgets(line, sizeof(line), f))
+    if (std::sscanf(line, "%d %d %d", &n, &tn, &tpw) == 3 && n >= 2 && n <= 14 &&
+        (tn == 32 || tn == 64 || tn == 128) && tpw >= 1 && tpw <= 256)
+      c->tuned[n] = {tn, tpw};
+  std::fclose(f);
+}
+void save_tune_cache(mbefci_ctx* c) {
+  if (!c->opts.tune_cache) return;
+  FILE* f = std::fopen(c->opts.tune_cache, "w");
+  if (!f) return;
+  std::fprintf(f, "# n tile tiles_per_workgroup (sigma contraction schedule, gfx950)\n");
+  for (auto& kv : c->tuned) std::fprintf(f, "%d %d %d\n", kv.first, kv.second.first, kv.second.second);
+  std::fclose(f);
 }
 
 // --------------------------------------------------------------- planning
+// Sigma-contraction work units of group gi: tiles (one alpha string x tn beta
+// strings) numbered column-major, tile = block * Na + Ka; a unit covers
+// tiles_per_wg alpha strings of one beta block and never crosses a block.
+void build_tiles(Plan& P, int gi) {
+  Group& g = P.groups[gi];
+  g.tiles.clear();
+  for (int i = 0; i < P.nitem; ++i) {
+    if (P.item_group[i] != gi) continue;
+    const Item& I = P.items[i];
+    const int nblk = (I.Nb + g.tn - 1) / g.tn;
+    g.item_lo[i] = (int)g.tiles.size();
+    for (int bk = 0; bk < nblk; ++bk)
+      for (int a = 0; a < I.Na; a += g.tiles_per_wg)
+        g.tiles.push_back(Work{i, bk * I.Na + a, bk * I.Na + std::min(a + g.tiles_per_wg, I.Na), 0});
+    g.item_hi[i] = (int)g.tiles.size();
+  }
+}
+
+// Sigma passes (contiguous item ranges whose G blocks stay below
+// sigma_pass_mb): sets every item's pass-relative G offset and the pass work
+// ranges; returns the largest pass's G size (doubles).
+int64_t build_passes(mbefci_ctx* c, Plan& P) {
+  {
+    const int64_t cap = c->opts.sigma_pass_mb > 0 ? (int64_t)c->opts.sigma_pass_mb << 20 : INT64_MAX;
+    P.passes.clear();
+    int64_t gpass = 0, gmax = 0;
+    Pass cur;
+    cur.tile_lo.assign(P.groups.size(), INT32_MAX);
+    cur.tile_hi.assign(P.groups.size(), 0);
+    cur.seg_lo = INT32_MAX;
+    cur.seg_hi = 0;
+    auto close = [&](int end) {
+      cur.item_hi = end;
+      for (size_t g = 0; g < P.groups.size(); ++g)
+        if (cur.tile_lo[g] == INT32_MAX) cur.tile_lo[g] = cur.tile_hi[g] = 0;
+      if (cur.seg_lo == INT32_MAX) cur.seg_lo = cur.seg_hi = 0;
+      P.passes.push_back(cur);
+      gmax = std::max(gmax, gpass);
+      cur = Pass();
+      cur.item_lo = end;
+      cur.tile_lo.assign(P.groups.size(), INT32_MAX);
+      cur.tile_hi.assign(P.groups.size(), 0);
+      cur.seg_lo = INT32_MAX;
+      cur.seg_hi = 0;
+      gpass = 0;
+    };
+    for (int i = 0; i < P.nitem; ++i) {
+      Item& I = P.items[i];
+      if (I.ndet <= 1) continue;
+      const int64_t gb = (int64_t)I.npair * I.ndet;
+      if (gpass > 0 && (gpass + gb) * 8 > cap) close(i);
+      I.goff = gpass;
+      gpass += gb;
+      const int g = P.item_group[i];
+      cur.tile_lo[g] = std::min(cur.tile_lo[g], P.groups[g].item_lo[i]);
+      cur.tile_hi[g] = std::max(cur.tile_hi[g], P.groups[g].item_hi[i]);
+      cur.seg_lo = std::min(cur.seg_lo, P.seg_lo[i]);
+      cur.seg_hi = std::max(cur.seg_hi, P.seg_hi[i]);
+    }
+    close(P.nitem);
+    return gmax;
+  }
+}
+
 // items must have n, na, nb filled; computes every derived field, work lists
 // and allocates the arenas.
 void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
@@ -275,6 +372,7 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
         Group g;
         g.n = I.n;
         g.tn = tile_for(c, I.n);
+        g.tiles_per_wg = tpw_for(c, I.n);
         g.item_lo.assign(P.nitem, 0);
         g.item_hi.assign(P.nitem, 0);
         P.groups.push_back(g);
@@ -282,60 +380,8 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
       P.item_group[i] = group_of_n[I.n];
     }
   }
-  for (int i = 0; i < P.nitem; ++i) {
-    if (P.item_group[i] < 0) continue;
-    Group& g = P.groups[P.item_group[i]];
-    const Item& I = P.items[i];
-    // work unit: tiles (one alpha string x tn beta strings) numbered
-    // column-major, tile = block * Na + Ka; a unit never crosses a beta block
-    const int nblk = (I.Nb + g.tn - 1) / g.tn;
-    g.item_lo[i] = (int)g.tiles.size();
-    for (int bk = 0; bk < nblk; ++bk)
-      for (int a = 0; a < I.Na; a += g.tiles_per_wg)
-        g.tiles.push_back(Work{i, bk * I.Na + a, bk * I.Na + std::min(a + g.tiles_per_wg, I.Na), 0});
-    g.item_hi[i] = (int)g.tiles.size();
-  }
-  // sigma passes: G offsets restart at every pass
-  {
-    const int64_t cap = c->opts.sigma_pass_mb > 0 ? (int64_t)c->opts.sigma_pass_mb << 20 : INT64_MAX;
-    P.passes.clear();
-    int64_t gpass = 0, gmax = 0;
-    Pass cur;
-    cur.tile_lo.assign(P.groups.size(), INT32_MAX);
-    cur.tile_hi.assign(P.groups.size(), 0);
-    cur.seg_lo = INT32_MAX;
-    cur.seg_hi = 0;
-    auto close = [&](int end) {
-      cur.item_hi = end;
-      for (size_t g = 0; g < P.groups.size(); ++g)
-        if (cur.tile_lo[g] == INT32_MAX) cur.tile_lo[g] = cur.tile_hi[g] = 0;
-      if (cur.seg_lo == INT32_MAX) cur.seg_lo = cur.seg_hi = 0;
-      P.passes.push_back(cur);
-      gmax = std::max(gmax, gpass);
-      cur = Pass();
-      cur.item_lo = end;
-      cur.tile_lo.assign(P.groups.size(), INT32_MAX);
-      cur.tile_hi.assign(P.groups.size(), 0);
-      cur.seg_lo = INT32_MAX;
-      cur.seg_hi = 0;
-      gpass = 0;
-    };
-    for (int i = 0; i < P.nitem; ++i) {
-      Item& I = P.items[i];
-      if (I.ndet <= 1) continue;
-      const int64_t gb = (int64_t)I.npair * I.ndet;
-      if (gpass > 0 && (gpass + gb) * 8 > cap) close(i);
-      I.goff = gpass;
-      gpass += gb;
-      const int g = P.item_group[i];
-      cur.tile_lo[g] = std::min(cur.tile_lo[g], P.groups[g].item_lo[i]);
-      cur.tile_hi[g] = std::max(cur.tile_hi[g], P.groups[g].item_hi[i]);
-      cur.seg_lo = std::min(cur.seg_lo, P.seg_lo[i]);
-      cur.seg_hi = std::max(cur.seg_hi, P.seg_hi[i]);
-    }
-    close(P.nitem);
-    goff = gmax;
-  }
+  for (size_t gi = 0; gi < P.groups.size(); ++gi) build_tiles(P, (int)gi);
+  goff = build_passes(c, P);
   P.ntot = std::max<int64_t>(off, 64);
   P.gtot = goff;
   P.wtot = woff;
@@ -452,10 +498,82 @@ int count_active(mbefci_ctx* c, Plan& P, const View& v) {
   return h;
 }
 
+// Autotuner: for every active size n of the plan that has no tuned schedule
+// yet, time the contraction kernel over the group's whole work list for each
+// candidate (tile width, tiles per workgroup) on the live plan (guess vectors
+// in slot 0; the kernels' cost does not depend on the values) and keep the
+// fastest.  Results persist in the context and, with opts.tune_cache, in a
+// file.  Runs once per plan, before the iteration graph is captured.
+void autotune(mbefci_ctx* c, Plan& P) {
+  if (c->opts.tile != 0 || P.tuned) return;
+  P.tuned = true;
+  load_tune_cache(c);
+  auto t0 = std::chrono::steady_clock::now();
+  bool changed = false;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+    Group& g = P.groups[gi];
+    if (c->tuned.count(g.n)) {
+      if (g.tn != c->tuned[g.n].first || g.tiles_per_wg != c->tuned[g.n].second) {
+        g.tn = c->tuned[g.n].first;
+        g.tiles_per_wg = c->tuned[g.n].second;
+        changed = true;
+      }
+      continue;
+    }
+    float best = 1e30f;
+    std::pair<int, int> pick{g.tn, g.tiles_per_wg};
+    for (int tn : {32, 64, 128}) {
+      if (tn == 128 && g.n >= 13) continue;
+      for (int tpw : {4, 8, 16, 32}) {
+        g.tn = tn;
+        g.tiles_per_wg = tpw;
+        build_tiles(P, (int)gi);
+        Work* d = arena<Work>(c, "tune_tiles", g.tiles.size());
+        upload(c, d, g.tiles);
+        const int nw = (int)g.tiles.size();
+        launch_sigma_dgemm(g.n, tn, P.d_items, d, nw, P.W, P.V, P.ntot, P.G, P.st, 0, c->stream);
+        HIPCHK(hipEventRecord(e0, c->stream));
+        for (int r = 0; r < 3; ++r)
+          launch_sigma_dgemm(g.n, tn, P.d_items, d, nw, P.W, P.V, P.ntot, P.G, P.st, 0, c->stream);
+        HIPCHK(hipEventRecord(e1, c->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          pick = {tn, tpw};
+        }
+      }
+    }
+    c->tuned[g.n] = pick;
+    g.tn = pick.first;
+    g.tiles_per_wg = pick.second;
+    changed = true;
+  }
+  HIPCHK(hipEventDestroy(e0));
+  HIPCHK(hipEventDestroy(e1));
+  if (changed) {
+    for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+      build_tiles(P, (int)gi);
+      P.groups[gi].d_tiles =
+          arena<Work>(c, "tiles" + std::to_string(gi), P.groups[gi].tiles.size());
+      upload(c, P.groups[gi].d_tiles, P.groups[gi].tiles);
+    }
+    build_passes(c, P);  // item G offsets are unchanged; pass work ranges follow the tiles
+    save_tune_cache(c);
+  }
+  c->ms_tune += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                    .count();
+}
+
 // guess + iterations for the items of view v (hdiag and set-up already done)
 void solve_view(mbefci_ctx* c, Plan& P, const View& v, int* graph_launches) {
   const int g = std::max(1, std::min(c->opts.nguess, 8));
   launch_dav_guess(P.d_items, v.ibase, v.nitem, P.diag, P.V, P.ntot, P.st, g, c->stream);
+  if (v.item < 0) autotune(c, P);
   for (int j = 0; j < g; ++j) add_vector(c, P, v, j);
   const int max_iter = c->opts.max_iter;
   if (v.item < 0 && c->opts.use_graph) {
@@ -534,6 +652,7 @@ void solve_plan(mbefci_ctx* c, Plan& P, mbefci_stats* stats) {
     stats->nbuckets = (int32_t)P.buckets.size();
     stats->graph_launches = graph_launches;
     stats->ms_solve = ms;
+    stats->ms_tune = c->ms_tune;
   }
   if (first_failed >= 0)
     throw Error(MBEFCI_ENOTCONV, "Davidson did not converge for CASCI " +

@@ -62,4 +62,4 @@ def test_null_context_is_rejected(lib):
 def test_struct_layouts_match_header():
     # mbefci_problem: int32, 2 pointers, double, (int32, ptr) x 3, int32
     assert ctypes.sizeof(_lib.Problem) == 4 + 4 + 8 + 8 + 8 + 3 * (8 + 8) + 8
-    assert ctypes.sizeof(_lib.Stats) == 4 * 8 + 4 * 4 + 2 * 8
+    assert ctypes.sizeof(_lib.Stats) == 4 * 8 + 4 * 4 + 3 * 8

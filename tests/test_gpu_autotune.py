@@ -1,0 +1,40 @@
+"""Autotuned sigma schedule (needs an MI355X): the tuner picks a tile width and
+tiles per workgroup per active size, writes its cache file, and the results
+are bitwise identical to a fixed schedule (the contraction order over pairs
+does not depend on the tiling)."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def test_autotune_cache_and_bitwise_results(tmp_path):
+    from paper_1910_03527_amd import Context
+    p = W.problem("hubbard12")
+    h, g = _dev(p.h1), _dev(p.eri)
+    cache = tmp_path / "tune.txt"
+    ref = Context(0, tile=64)
+    r0 = ref.mbe_forward(h, g, p.occ, p.ref, p.exp, p.max_order, want_increments=True)
+    ref.close()
+    c = Context(0, tile=0, tune_cache=str(cache))
+    r1 = c.mbe_forward(h, g, p.occ, p.ref, p.exp, p.max_order, want_increments=True)
+    assert c.last_stats["ms_tune"] > 0.0
+    c.close()
+    assert r0["increments"] == r1["increments"] and r0["e_order"] == r1["e_order"]
+    lines = [l.split() for l in cache.read_text().splitlines() if not l.startswith("#")]
+    assert lines and all(len(l) == 3 and int(l[1]) in (32, 64, 128) for l in lines)
+    # a new context reads the cache and does not time again
+    c2 = Context(0, tile=0, tune_cache=str(cache))
+    r2 = c2.mbe_forward(h, g, p.occ, p.ref, p.exp, p.max_order, want_increments=True)
+    assert c2.last_stats["ms_tune"] < 50.0
+    c2.close()
+    assert r2["increments"] == r1["increments"]
