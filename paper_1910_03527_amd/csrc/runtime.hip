@@ -483,12 +483,16 @@ void add_vector(mbefci_ctx* c, Plan& P, const View& v, int slot) {
   launch_dav_rr(P.d_items, v.ibase, v.nitem, P.part, P.st, slot, c->stream);
 }
 
-void iteration(mbefci_ctx* c, Plan& P, const View& v) {
+// One Davidson iteration is split in two halves so that the convergence test
+// sits between them: step_a forms the residual of the current Ritz vector,
+// decides convergence and builds the next basis vector; step_b applies sigma
+// to it and updates the subspace matrix and Ritz pair.
+void step_a(mbefci_ctx* c, Plan& P, const View& v) {
   launch_dav_iteration(P.d_items, v.ibase, v.nitem, P.d_chunks + v.chunk_lo, v.nchunk, P.V, P.S,
                        P.diag, P.ntot, P.st, P.part, c->opts.conv_tol, c->opts.max_iter,
                        c->opts.max_space, c->stream);
-  add_vector(c, P, v, -1);
 }
+void step_b(mbefci_ctx* c, Plan& P, const View& v) { add_vector(c, P, v, -1); }
 
 int count_active(mbefci_ctx* c, Plan& P, const View& v) {
   launch_count_active(P.st, v.ibase, v.nitem, P.d_count, c->stream);
@@ -576,8 +580,10 @@ void solve_view(mbefci_ctx* c, Plan& P, const View& v, int* graph_launches) {
   if (v.item < 0) autotune(c, P);
   for (int j = 0; j < g; ++j) add_vector(c, P, v, j);
   const int max_iter = c->opts.max_iter;
+  step_a(c, P, v);
   if (v.item < 0 && c->opts.use_graph) {
     const int K = 4;
+    if (count_active(c, P, v) == 0) return;
     if (!P.graph || P.graph_iters != K) {
       if (P.graph) {
         HIPCHK(hipGraphExecDestroy(P.graph));
@@ -585,13 +591,15 @@ void solve_view(mbefci_ctx* c, Plan& P, const View& v, int* graph_launches) {
       }
       hipGraph_t gr;
       HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-      for (int k = 0; k < K; ++k) iteration(c, P, v);
+      for (int k = 0; k < K; ++k) {
+        step_b(c, P, v);
+        step_a(c, P, v);
+      }
       HIPCHK(hipStreamEndCapture(c->stream, &gr));
       HIPCHK(hipGraphInstantiate(&P.graph, gr, nullptr, nullptr, 0));
       HIPCHK(hipGraphDestroy(gr));
       P.graph_iters = K;
     }
-    if (count_active(c, P, v) == 0) return;
     for (int it = 0; it < max_iter + K; it += K) {
       HIPCHK(hipGraphLaunch(P.graph, c->stream));
       if (graph_launches) ++*graph_launches;
@@ -601,13 +609,17 @@ void solve_view(mbefci_ctx* c, Plan& P, const View& v, int* graph_launches) {
     const int K = 4;
     if (count_active(c, P, v) == 0) return;
     for (int it = 0; it < max_iter + K; it += K) {
-      for (int k = 0; k < K; ++k) iteration(c, P, v);
+      for (int k = 0; k < K; ++k) {
+        step_b(c, P, v);
+        step_a(c, P, v);
+      }
       if (count_active(c, P, v) == 0) break;
     }
   } else {
     for (int it = 0; it < max_iter + 1; ++it) {
       if (count_active(c, P, v) == 0) break;
-      iteration(c, P, v);
+      step_b(c, P, v);
+      step_a(c, P, v);
     }
   }
   HIPCHK(hipGetLastError());
