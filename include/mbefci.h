@@ -72,7 +72,9 @@ typedef struct {
                             pair array) stays below this many MiB, so that it is
                             re-read from the on-die cache and its memory is bounded;
                             0 = one pass (default 0) */
-  int32_t pad_;
+  int32_t precond;       /* Davidson correction: 0 = diagonal (theta - H_II)^-1 r,
+                            1 = Olsen-corrected, orthogonal to the Ritz vector
+                            (default 0)                                          */
   int64_t max_workspace; /* workspace cap in bytes, 0 = no cap                       */
   const char* tune_cache;/* autotuner cache file (read/written) or NULL: one line per
                             active size n, "n tile tiles_per_workgroup"          */

@@ -38,7 +38,7 @@ class Opts(ctypes.Structure):
         ("keep_ci", ctypes.c_int32),
         ("validate", ctypes.c_int32),
         ("sigma_pass_mb", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("precond", ctypes.c_int32),
         ("max_workspace", ctypes.c_int64),
         ("tune_cache", ctypes.c_char_p),
     ]

@@ -95,6 +95,7 @@ struct DavState {
   double theta;       // lowest Ritz value (active-space energy without ecore)
   double rnorm;       // residual norm of the last Ritz vector
   double tnorm2;      // squared norm of the correction vector
+  double eps;         // Olsen shift of the correction equation
   double y[kMaxSpace];
   double coef[kMaxSpace + 1];
   double Hs[kMaxSpace * kMaxSpace];

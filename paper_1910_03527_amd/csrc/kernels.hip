@@ -860,6 +860,124 @@ __global__ void __launch_bounds__(256) k_dav_residual(const Item* __restrict__ i
   block_reduce_store<kMaxSpace + 1>(acc, part + (int64_t)wk.begin * kPart);
 }
 
+// Olsen-corrected preconditioner.  With x = V y the Ritz vector and
+// r = S y - theta x its residual, the correction is
+//   t = -(D - theta)^{-1} (r - eps x),  eps = x^T (D-theta)^{-1} r / x^T (D-theta)^{-1} x,
+// the choice that makes t orthogonal to x (Olsen, Jorgensen and Simons'
+// correction of the diagonal-preconditioned update used in FCI codes).
+// Pass 1 stores r and x and reduces |r|^2, x.(D-theta)^{-1} r, x.(D-theta)^{-1} x.
+__device__ inline double guarded_den(double d) {
+  return fabs(d) < 1e-8 ? (d < 0 ? -1e-8 : 1e-8) : d;
+}
+
+__global__ void __launch_bounds__(256) k_dav_residual_olsen(
+    const Item* __restrict__ items, const Work* __restrict__ work, const double* __restrict__ V,
+    const double* __restrict__ Sv, const double* __restrict__ diag, int64_t ntot,
+    const DavState* __restrict__ st, double* __restrict__ Rb, double* __restrict__ Xb,
+    double* part) {
+  const Work wk = work[blockIdx.x];
+  const Item& I = items[wk.item];
+  const DavState& S = st[wk.item];
+  if (S.conv) return;
+  const int m = S.m;
+  const double th = S.theta;
+  double y[kMaxSpace];
+#pragma unroll
+  for (int i = 0; i < kMaxSpace; ++i) y[i] = S.y[i];
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int64_t e0 = (int64_t)(wk.begin - I.chunk0) * kChunk;
+  const int64_t e1 = min(e0 + kChunk, I.ndet);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    double x = 0.0, sx = 0.0;
+#pragma unroll
+    for (int i = 0; i < kMaxSpace; ++i)
+      if (i < m) {
+        x += y[i] * V[(int64_t)i * ntot + I.off + e];
+        sx += y[i] * Sv[(int64_t)i * ntot + I.off + e];
+      }
+    const double r = sx - th * x;
+    const double den = guarded_den(diag[I.off + e] - th);
+    Rb[I.off + e] = r;
+    Xb[I.off + e] = x;
+    acc[0] += r * r;
+    acc[1] += x * r / den;
+    acc[2] += x * x / den;
+  }
+  block_reduce_store<3>(acc, part + (int64_t)wk.begin * kPart);
+}
+
+__global__ void k_dav_reduce1_olsen(const Item* __restrict__ items,
+                                    const double* __restrict__ part, DavState* st, int ibase,
+                                    int nitem, double tol, int max_iter) {
+  int it = blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= nitem) return;
+  it += ibase;
+  const Item& I = items[it];
+  DavState& S = st[it];
+  if (S.conv) return;
+  double rr = 0.0, a = 0.0, b = 0.0;
+  for (int c = 0; c < I.nchunk; ++c) {
+    const double* p = part + (int64_t)(I.chunk0 + c) * kPart;
+    rr += p[0];
+    a += p[1];
+    b += p[2];
+  }
+  S.rnorm = sqrt(rr);
+  S.eps = (b != 0.0) ? a / b : 0.0;
+  if (S.rnorm <= tol || S.m >= I.ndet) {
+    S.conv = 1;
+  } else if (S.iters >= max_iter) {
+    S.conv = 1;
+    S.status = 1;
+  }
+}
+
+// t = -(r - eps x) / (D - theta) into slot m; partial dots V_i . t (i < m)
+__global__ void __launch_bounds__(256) k_dav_precond_olsen(
+    const Item* __restrict__ items, const Work* __restrict__ work, double* V,
+    const double* __restrict__ diag, int64_t ntot, const DavState* __restrict__ st,
+    const double* __restrict__ Rb, const double* __restrict__ Xb, double* part) {
+  const Work wk = work[blockIdx.x];
+  const Item& I = items[wk.item];
+  const DavState& S = st[wk.item];
+  if (S.conv) return;
+  const int m = S.m;
+  const double th = S.theta, eps = S.eps;
+  double acc[kMaxSpace];
+#pragma unroll
+  for (int i = 0; i < kMaxSpace; ++i) acc[i] = 0.0;
+  const int64_t e0 = (int64_t)(wk.begin - I.chunk0) * kChunk;
+  const int64_t e1 = min(e0 + kChunk, I.ndet);
+  double* t_out = V + (int64_t)m * ntot + I.off;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const double den = guarded_den(diag[I.off + e] - th);
+    const double tv = -(Rb[I.off + e] - eps * Xb[I.off + e]) / den;
+    t_out[e] = tv;
+#pragma unroll
+    for (int i = 0; i < kMaxSpace; ++i)
+      if (i < m) acc[i] += V[(int64_t)i * ntot + I.off + e] * tv;
+  }
+  block_reduce_store<kMaxSpace>(acc, part + (int64_t)wk.begin * kPart);
+}
+
+// first Gram-Schmidt coefficients from the partial dots
+__global__ void k_dav_reduce_coef(const Item* __restrict__ items, const double* __restrict__ part,
+                                  DavState* st, int ibase, int nitem) {
+  int it = blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= nitem) return;
+  it += ibase;
+  const Item& I = items[it];
+  DavState& S = st[it];
+  if (S.conv) return;
+  double cf[kMaxSpace];
+  for (int i = 0; i < kMaxSpace; ++i) cf[i] = 0.0;
+  for (int c = 0; c < I.nchunk; ++c) {
+    const double* p = part + (int64_t)(I.chunk0 + c) * kPart;
+    for (int i = 0; i < S.m; ++i) cf[i] += p[i];
+  }
+  for (int i = 0; i < kMaxSpace; ++i) S.coef[i] = cf[i];
+}
+
 // Convergence test and first Gram-Schmidt coefficients.
 __global__ void k_dav_reduce1(const Item* __restrict__ items, const double* __restrict__ part,
                               DavState* st, int ibase, int nitem, double tol, int max_iter) {
@@ -1556,16 +1674,27 @@ void launch_dav_rr(const Item* items, int ibase, int nitem, const double* part, 
 }
 void launch_dav_iteration(const Item* items, int ibase, int nitem, const Work* chunks, int nchunk,
                           double* V, double* Sv, const double* diag, int64_t ntot, DavState* st,
-                          double* part, double tol, int max_iter, int mmax, hipStream_t s) {
+                          double* part, double tol, int max_iter, int mmax, double* Rb,
+                          double* Xb, hipStream_t s) {
   if (nchunk <= 0) return;
   const int nb = nblk(nitem, 64);
   hipLaunchKernelGGL(k_dav_collapse, dim3(nchunk), dim3(256), 0, s, items, chunks, V, Sv, ntot, st,
                      mmax);
   hipLaunchKernelGGL(k_dav_collapse_state, dim3(nb), dim3(64), 0, s, st, ibase, nitem, mmax);
-  hipLaunchKernelGGL(k_dav_residual, dim3(nchunk), dim3(256), 0, s, items, chunks, V, Sv, diag,
-                     ntot, st, part);
-  hipLaunchKernelGGL(k_dav_reduce1, dim3(nb), dim3(64), 0, s, items, part, st, ibase, nitem, tol,
-                     max_iter);
+  if (Rb && Xb) {
+    hipLaunchKernelGGL(k_dav_residual_olsen, dim3(nchunk), dim3(256), 0, s, items, chunks, V, Sv,
+                       diag, ntot, st, Rb, Xb, part);
+    hipLaunchKernelGGL(k_dav_reduce1_olsen, dim3(nb), dim3(64), 0, s, items, part, st, ibase,
+                       nitem, tol, max_iter);
+    hipLaunchKernelGGL(k_dav_precond_olsen, dim3(nchunk), dim3(256), 0, s, items, chunks, V, diag,
+                       ntot, st, Rb, Xb, part);
+    hipLaunchKernelGGL(k_dav_reduce_coef, dim3(nb), dim3(64), 0, s, items, part, st, ibase, nitem);
+  } else {
+    hipLaunchKernelGGL(k_dav_residual, dim3(nchunk), dim3(256), 0, s, items, chunks, V, Sv, diag,
+                       ntot, st, part);
+    hipLaunchKernelGGL(k_dav_reduce1, dim3(nb), dim3(64), 0, s, items, part, st, ibase, nitem, tol,
+                       max_iter);
+  }
   hipLaunchKernelGGL(k_dav_orth, dim3(nchunk), dim3(256), 0, s, items, chunks, V, ntot, st, part);
   hipLaunchKernelGGL(k_dav_reduce2, dim3(nb), dim3(64), 0, s, items, part, st, ibase, nitem);
   hipLaunchKernelGGL(k_dav_orth2, dim3(nchunk), dim3(256), 0, s, items, chunks, V, ntot, st);

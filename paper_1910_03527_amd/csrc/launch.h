@@ -35,7 +35,8 @@ void launch_dav_rr(const Item* items, int ibase, int nitem, const double* part, 
                    int slot, hipStream_t s);
 void launch_dav_iteration(const Item* items, int ibase, int nitem, const Work* chunks, int nchunk,
                           double* V, double* Sv, const double* diag, int64_t ntot, DavState* st,
-                          double* part, double tol, int max_iter, int mmax, hipStream_t s);
+                          double* part, double tol, int max_iter, int mmax, double* Rb,
+                          double* Xb, hipStream_t s);
 void launch_item_energy(const Item* items, const ItemHam* hams, const DavState* st, int nitem,
                         double* f, hipStream_t s);
 void launch_mbe_combine(const MbeSpaces* sp, const BucketDev* buckets, int nbucket,

@@ -98,7 +98,7 @@ struct Plan {
   Work* d_segs = nullptr;
   BucketDev* d_buckets = nullptr;
   double *V = nullptr, *S = nullptr, *diag = nullptr, *G = nullptr, *W = nullptr,
-         *part = nullptr, *f = nullptr, *inc = nullptr, *ci = nullptr;
+         *part = nullptr, *f = nullptr, *inc = nullptr, *ci = nullptr, *R = nullptr, *X = nullptr;
   ItemHam* hams = nullptr;
   DavState* st = nullptr;
   int32_t* tuple_pos = nullptr;
@@ -399,6 +399,10 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
   P.V = arena<double>(c, "V", (size_t)(mmax + 1) * P.ntot, &grown);
   P.S = arena<double>(c, "S", (size_t)mmax * P.ntot, &grown);
   P.diag = arena<double>(c, "diag", P.ntot, &grown);
+  if (c->opts.precond == 1) {
+    P.R = arena<double>(c, "resid", P.ntot, &grown);
+    P.X = arena<double>(c, "ritz", P.ntot, &grown);
+  }
   P.G = arena<double>(c, "G", std::max<int64_t>(P.gtot, 1), &grown);
   P.W = arena<double>(c, "W", std::max<int64_t>(P.wtot, 1), &grown);
   P.part = arena<double>(c, "part", (size_t)std::max(P.nchunk, 1) * kPartStride, &grown);
@@ -488,9 +492,11 @@ void add_vector(mbefci_ctx* c, Plan& P, const View& v, int slot) {
 // decides convergence and builds the next basis vector; step_b applies sigma
 // to it and updates the subspace matrix and Ritz pair.
 void step_a(mbefci_ctx* c, Plan& P, const View& v) {
+  const bool olsen = c->opts.precond == 1;
   launch_dav_iteration(P.d_items, v.ibase, v.nitem, P.d_chunks + v.chunk_lo, v.nchunk, P.V, P.S,
                        P.diag, P.ntot, P.st, P.part, c->opts.conv_tol, c->opts.max_iter,
-                       c->opts.max_space, c->stream);
+                       c->opts.max_space, olsen ? P.R : nullptr, olsen ? P.X : nullptr,
+                       c->stream);
 }
 void step_b(mbefci_ctx* c, Plan& P, const View& v) { add_vector(c, P, v, -1); }
 
@@ -857,6 +863,7 @@ void mbefci_default_opts(mbefci_opts* o) {
   o->keep_ci = 1;
   o->validate = 1;
   o->sigma_pass_mb = 0;
+  o->precond = 0;
   o->max_workspace = 0;
   o->tune_cache = nullptr;
 }
@@ -869,6 +876,7 @@ static int check_opts(const mbefci_opts* o, std::string* why) {
   if (o->mode != MBEFCI_BATCHED && o->mode != MBEFCI_PER_LAUNCH) { *why = "unknown mode"; return MBEFCI_EINVAL; }
   if (o->tile != 0 && o->tile != 32 && o->tile != 64 && o->tile != 128) { *why = "tile must be 0, 32, 64 or 128"; return MBEFCI_EINVAL; }
   if (o->sigma_pass_mb < 0) { *why = "sigma_pass_mb must be >= 0"; return MBEFCI_EINVAL; }
+  if (o->precond != 0 && o->precond != 1) { *why = "precond must be 0 or 1"; return MBEFCI_EINVAL; }
   return MBEFCI_OK;
 }
 
@@ -932,7 +940,7 @@ int mbefci_set_opts(mbefci_ctx* c, const mbefci_opts* o) {
     return rc;
   }
   bool plan_dead = o->max_space != c->opts.max_space || o->tile != c->opts.tile ||
-                   o->sigma_pass_mb != c->opts.sigma_pass_mb;
+                   o->sigma_pass_mb != c->opts.sigma_pass_mb || o->precond != c->opts.precond;
   c->opts = *o;
   if (plan_dead && c->plan) {
     if (c->plan->graph) (void)hipGraphExecDestroy(c->plan->graph);
