@@ -62,6 +62,7 @@ struct Item {
   int32_t pad_;
   const uint32_t* linkA;  // [Na][La]
   const uint32_t* linkB;  // [Nb][Lb]
+  const uint32_t* linkBT; // [Lb][Nb] (link-major copy: coalesced per-lane reads)
   const uint64_t* strA;   // [Na] alpha string bitmasks
   const uint64_t* strB;   // [Nb] beta string bitmasks
   const int32_t* pairA;   // [Na][npair] pair table (see pack_pair_entry)

@@ -86,7 +86,8 @@ __global__ void k_strings(int n, int ne, int64_t N, uint64_t* out) {
 // canonical order (diagonal entries first, then q in I ascending, p not in I
 // ascending).  The sign is (-1)^(number of occupied orbitals strictly between
 // p and q), the parity of a+_p a_q acting on the occupation-number vector.
-__global__ void k_links(int n, int ne, int64_t N, uint32_t* packed, int32_t* abi4) {
+__global__ void k_links(int n, int ne, int64_t N, uint32_t* packed, uint32_t* packedT,
+                        int32_t* abi4) {
   int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= N) return;
   const int L = ne * (n - ne + 1);
@@ -94,7 +95,9 @@ __global__ void k_links(int n, int ne, int64_t N, uint32_t* packed, int32_t* abi
   int idx = 0;
   for (int o = 0; o < n; ++o)
     if (m >> o & 1) {
-      if (packed) packed[I * L + idx] = pack_link((int)I, pair_index(o, o), 1);
+      const uint32_t v = pack_link((int)I, pair_index(o, o), 1);
+      if (packed) packed[I * L + idx] = v;
+      if (packedT) packedT[idx * N + I] = v;
       if (abi4) {
         int32_t* e = abi4 + (I * L + idx) * 4;
         e[0] = o; e[1] = o; e[2] = (int32_t)I; e[3] = 1;
@@ -110,7 +113,9 @@ __global__ void k_links(int n, int ne, int64_t N, uint32_t* packed, int32_t* abi
       uint64_t between = (((uint64_t)1 << hi) - 1) & ~((((uint64_t)1 << lo) << 1) - 1);
       int sign = (__builtin_popcountll(m & between) & 1) ? -1 : 1;
       int64_t J = string_addr(r);
-      if (packed) packed[I * L + idx] = pack_link((int)J, pair_index(p, q), sign);
+      const uint32_t v = pack_link((int)J, pair_index(p, q), sign);
+      if (packed) packed[I * L + idx] = v;
+      if (packedT) packedT[idx * N + I] = v;
       if (abi4) {
         int32_t* e = abi4 + (I * L + idx) * 4;
         e[0] = p; e[1] = q; e[2] = (int32_t)J; e[3] = sign;
@@ -388,6 +393,8 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
   constexpr int NPER = (NP + NSUB - 1) / NSUB;
   constexpr int LDT = TN + 1;            // padded LDS row (doubles)
   constexpr int CMAX = (int)binom_c(NACT, NACT / 2);  // largest string count for NACT
+  constexpr int CPT = (CMAX + 255) / 256;             // c-row doubles per thread
+  constexpr int TPT = (NP * TN + 255) / 256;          // beta-table entries per thread
   __shared__ double Ds[KR * LDT];
   __shared__ int32_t Tb[NP * TN];
   __shared__ double Cr[CMAX];
@@ -412,6 +419,7 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
   const int Kb = Kb0 + col;
   const double keep = Kb < Nb ? 1.0 : 0.0;  // ragged end of the row: zero columns
   const int Kbc = Kb < Nb ? Kb : Nb - 1;
+  const double* __restrict__ ca = c + Kbc;  // alpha source of D+: ca[Ja * Nb]
 
   // W rows of this wave's row blocks, as MFMA A operands: lane l holds
   // W[rb*16 + l%16][ks*4 + l/16] (B operand: lane l holds D+[ks*4 + l/16][l%16])
@@ -425,33 +433,94 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
       wreg[r][ks] = (rb < NRB) ? ldg(W + (rb * 16 + (lane & 15)) * KPAD + ks * 4 + (lane >> 4))
                                : 0.0;
   }
-  // beta pair-table block [pair][TN] and the zero padding rows of D+
-  for (int x = t; x < NP * TN; x += 256) {
-    const int ab = x / TN, cc = x - ab * TN;
-    const int kb = Kb0 + cc < Nb ? Kb0 + cc : Nb - 1;
-    Tb[x] = ldg(pB + ab * Nb + kb);
+  // beta pair-table block [pair][TN] (all loads issued before the LDS
+  // stores) and the zero padding rows of D+
+  {
+    int32_t tv[TPT];
+#pragma unroll
+    for (int i = 0; i < TPT; ++i) {
+      const int x = t + 256 * i;
+      tv[i] = 0;
+      if (x < NP * TN) {
+        const int ab = x / TN, cc = x - ab * TN;
+        const int kb = Kb0 + cc < Nb ? Kb0 + cc : Nb - 1;
+        tv[i] = ldg(pB + ab * Nb + kb);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < TPT; ++i)
+      if (t + 256 * i < NP * TN) Tb[t + 256 * i] = tv[i];
   }
   for (int x = NP * LDT + t; x < KR * LDT; x += 256) Ds[x] = 0.0;
 
+  // Software pipeline over the tiles of the work unit: the alpha pair-table
+  // entries of tile i+1 are loaded while tile i builds D+, and the c row and
+  // alpha-half values of tile i+1 while tile i runs its MFMAs.
+  int32_t ea[NPER];   // alpha pair-table entries of the current tile
+  double ga[NPER];    // c values they address (alpha half of D+)
+  double cr[CPT];     // this thread's share of the c row Ka
+  // The alpha entries are wave-uniform per row (scalar loads): with TN = 32
+  // a wave covers the two rows 2*wave and 2*wave+1 of each row group.
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  auto load_entries = [&](int ka, int32_t (&e)[NPER]) {
+    const int32_t* __restrict__ pa = pA + ka * NP;
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) {
+      if constexpr (TN >= 64) {
+        const int ab = sub + NSUB * i;
+        e[i] = ab < NP ? ldc(pa + ab) : 0;
+      } else {
+        static_assert(TN == 32, "tile width 32, 64 or 128");
+        const int ab0 = 2 * wave_u + NSUB * i;
+        const int32_t e0 = ab0 < NP ? ldc(pa + ab0) : 0;
+        const int32_t e1 = ab0 + 1 < NP ? ldc(pa + ab0 + 1) : 0;
+        e[i] = lane < 32 ? e0 : e1;
+      }
+    }
+  };
+  auto load_values = [&](int ka) {
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) ga[i] = ea[i] ? ldg(ca + ((ea[i] >> 1) - 1) * Nb) : 0.0;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const int x = t + 256 * j;
+      cr[j] = x < Nb ? ldg(c + ka * Nb + x) : 0.0;
+    }
+  };
+  load_entries(wk.begin - blk * Na, ea);
+  load_values(wk.begin - blk * Na);
+
   for (int tile = wk.begin; tile < wk.end; ++tile) {
     const int Ka = tile - blk * Na;              // uniform
-    for (int x = t; x < Nb; x += 256) Cr[x] = ldg(c + Ka * Nb + x);
+    const bool more = tile + 1 < wk.end;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j)
+      if (t + 256 * j < Nb) Cr[t + 256 * j] = cr[j];
+    int32_t en[NPER];
+    if (more) {
+      load_entries(Ka + 1, en);
+    } else {
+#pragma unroll
+      for (int i = 0; i < NPER; ++i) en[i] = 0;
+    }
     __syncthreads();
-    const int32_t* __restrict__ pa = pA + Ka * NP;       // uniform row of the alpha table
-    const double* __restrict__ ca = c + Kbc;             // alpha source: ca[Ja * Nb]
 #pragma unroll
     for (int i = 0; i < NPER; ++i) {
       const int ab = sub + NSUB * i;
       if (ab < NP) {
-        const int32_t ea = ldc(pa + ab);   // uniform: scalar load
         const int32_t eb = Tb[ab * TN + col];
-        const int ja = ea ? (ea >> 1) - 1 : 0, jb = eb ? (eb >> 1) - 1 : 0;
-        const double fa = ea ? ((ea & 1) ? -keep : keep) : 0.0;
+        const int jb = eb ? (eb >> 1) - 1 : 0;
+        const double fa = ea[i] ? ((ea[i] & 1) ? -keep : keep) : 0.0;
         const double fb = eb ? ((eb & 1) ? -keep : keep) : 0.0;
-        Ds[ab * LDT + col] = fa * ldg(ca + ja * Nb) + fb * Cr[jb];
+        Ds[ab * LDT + col] = fa * ga[i] + fb * Cr[jb];
       }
     }
     __syncthreads();
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < NPER; ++i) ea[i] = en[i];
+      load_values(Ka + 1);
+    }
 #pragma unroll
     for (int r = 0; r < RBW; ++r) {
       const int rb = wave + 4 * r;
@@ -482,7 +551,9 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
         }
       }
     }
-    __syncthreads();
+    // No barrier here: the next tile's Cr stores follow this tile's second
+    // barrier (every D+ read of Cr is done), and its D+ stores follow the
+    // next first barrier (every MFMA read of Ds is done).
   }
 }
 
@@ -528,11 +599,12 @@ __global__ void __launch_bounds__(256) k_sigma_gather(const Item* __restrict__ i
     const uint32_t e0 = ldc(la + l);
     acc0 += link_sign(e0) * ldg(Gcol + (int64_t)(link_addr(e0) * np + link_pair(e0)) * Nb);
   }
-  const uint32_t* __restrict__ lb = I.linkB + Kb * Lb;
+  const uint32_t* __restrict__ lb = I.linkBT + Kb;               // link l of Kb: lb[l * Nb]
   const double* __restrict__ Grow = G + (int64_t)Ka * np * Nb;  // G[(Ka * npair + pair) * Nb + Jb]
   l = 0;
   for (; l + 3 < Lb; l += 4) {
-    const uint32_t e0 = ldg(lb + l), e1 = ldg(lb + l + 1), e2 = ldg(lb + l + 2), e3 = ldg(lb + l + 3);
+    const uint32_t e0 = ldg(lb + l * Nb), e1 = ldg(lb + (l + 1) * Nb), e2 = ldg(lb + (l + 2) * Nb),
+                   e3 = ldg(lb + (l + 3) * Nb);
     const double g0 = ldg(Grow + link_pair(e0) * Nb + link_addr(e0));
     const double g1 = ldg(Grow + link_pair(e1) * Nb + link_addr(e1));
     const double g2 = ldg(Grow + link_pair(e2) * Nb + link_addr(e2));
@@ -541,7 +613,7 @@ __global__ void __launch_bounds__(256) k_sigma_gather(const Item* __restrict__ i
     acc1 += link_sign(e1) * g1 + link_sign(e3) * g3;
   }
   for (; l < Lb; ++l) {
-    const uint32_t e0 = ldg(lb + l);
+    const uint32_t e0 = ldg(lb + l * Nb);
     acc0 += link_sign(e0) * ldg(Grow + link_pair(e0) * Nb + link_addr(e0));
   }
   Sarena[(int64_t)vs * ntot + I.off + (int64_t)Ka * Nb + Kb] = acc0 + acc1;
@@ -1573,9 +1645,11 @@ static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 void launch_strings(int n, int ne, int64_t N, uint64_t* out, hipStream_t s) {
   if (N > 0) hipLaunchKernelGGL(k_strings, dim3(nblk(N, 256)), dim3(256), 0, s, n, ne, N, out);
 }
-void launch_links(int n, int ne, int64_t N, uint32_t* packed, int32_t* abi4, hipStream_t s) {
+void launch_links(int n, int ne, int64_t N, uint32_t* packed, uint32_t* packedT, int32_t* abi4,
+                  hipStream_t s) {
   if (N > 0)
-    hipLaunchKernelGGL(k_links, dim3(nblk(N, 128)), dim3(128), 0, s, n, ne, N, packed, abi4);
+    hipLaunchKernelGGL(k_links, dim3(nblk(N, 128)), dim3(128), 0, s, n, ne, N, packed, packedT,
+                       abi4);
 }
 void launch_pair_table(int n, int ne, int64_t N, int32_t* out, int32_t* outT, hipStream_t s) {
   if (N > 0)

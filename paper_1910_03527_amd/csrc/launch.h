@@ -9,7 +9,8 @@
 namespace mbefci {
 
 void launch_strings(int n, int ne, int64_t N, uint64_t* out, hipStream_t s);
-void launch_links(int n, int ne, int64_t N, uint32_t* packed, int32_t* abi4, hipStream_t s);
+void launch_links(int n, int ne, int64_t N, uint32_t* packed, uint32_t* packedT, int32_t* abi4,
+                  hipStream_t s);
 void launch_pair_table(int n, int ne, int64_t N, int32_t* out, int32_t* outT, hipStream_t s);
 void launch_mbe_setup(const MbeSpaces* sp, const BucketDev* buckets, int nbucket, const Item* items,
                       int nitem, const double* h1, const double* eri, double e_const,

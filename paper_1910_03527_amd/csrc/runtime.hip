@@ -54,7 +54,8 @@ struct DevBuf {
 struct StringTab {
   int n = 0, ne = 0, L = 0;
   int64_t N = 0;
-  uint32_t* link = nullptr;
+  uint32_t* link = nullptr;   // [N][L]
+  uint32_t* linkT = nullptr;  // [L][N]
   uint64_t* str = nullptr;
   int32_t* pair = nullptr;
   int32_t* pairT = nullptr;
@@ -182,7 +183,8 @@ const StringTab& string_tab(mbefci_ctx* c, int n, int ne) {
   t.L = ne * (n - ne + 1);
   if (t.N * t.L > 0) {
     HIPCHK(hipMalloc(&t.link, sizeof(uint32_t) * t.N * t.L));
-    launch_links(n, ne, t.N, t.link, nullptr, c->stream);
+    HIPCHK(hipMalloc(&t.linkT, sizeof(uint32_t) * t.N * t.L));
+    launch_links(n, ne, t.N, t.link, t.linkT, nullptr, c->stream);
     HIPCHK(hipGetLastError());
   }
   HIPCHK(hipMalloc(&t.str, sizeof(uint64_t) * std::max<int64_t>(t.N, 1)));
@@ -328,6 +330,7 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
     I.Lb = tb.L;
     I.linkA = ta.link;
     I.linkB = tb.link;
+    I.linkBT = tb.linkT;
     I.strA = ta.str;
     I.strB = tb.str;
     I.pairA = ta.pair;
@@ -915,6 +918,7 @@ void mbefci_destroy(mbefci_ctx* c) {
   if (c->plan && c->plan->graph) (void)hipGraphExecDestroy(c->plan->graph);
   for (auto& kv : c->tabs) {
     if (kv.second.link) (void)hipFree(kv.second.link);
+    if (kv.second.linkT) (void)hipFree(kv.second.linkT);
     if (kv.second.str) (void)hipFree(kv.second.str);
     if (kv.second.pair) (void)hipFree(kv.second.pair);
     if (kv.second.pairT) (void)hipFree(kv.second.pairT);
@@ -981,7 +985,7 @@ int mbefci_link_table(mbefci_ctx* c, int32_t norb, int32_t nelec, int32_t* out, 
     if (norb < 0 || norb > 32 || nelec < 0 || nelec > norb || !out)
       throw Error(MBEFCI_EINVAL, "invalid link-table shape");
     StreamScope sc(c, stream);
-    launch_links(norb, nelec, binom_host(norb, nelec), nullptr, out, c->stream);
+    launch_links(norb, nelec, binom_host(norb, nelec), nullptr, nullptr, out, c->stream);
     HIPCHK(hipGetLastError());
     sc.done();
   });
