@@ -75,6 +75,13 @@ typedef struct {
   int32_t precond;       /* Davidson correction: 0 = diagonal (theta - H_II)^-1 r,
                             1 = Olsen-corrected, orthogonal to the Ritz vector
                             (default 0)                                          */
+  int32_t pspace;        /* P-space size 0..112: the determinants of lowest diagonal
+                            energy whose block H_PP is diagonalised once per CASCI;
+                            it gives the guess and, on that block, the exact
+                            (theta - H_PP)^-1 correction; 0 = unit-vector guesses
+                            (nguess of them) and the diagonal correction only;
+                            ignored with precond = 1 (default 112)              */
+  int32_t pad0_;
   int64_t max_workspace; /* workspace cap in bytes, 0 = no cap                       */
   const char* tune_cache;/* autotuner cache file (read/written) or NULL: one line per
                             active size n, "n tile tiles_per_workgroup"          */

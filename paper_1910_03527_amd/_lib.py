@@ -39,6 +39,8 @@ class Opts(ctypes.Structure):
         ("validate", ctypes.c_int32),
         ("sigma_pass_mb", ctypes.c_int32),
         ("precond", ctypes.c_int32),
+        ("pspace", ctypes.c_int32),
+        ("pad0_", ctypes.c_int32),
         ("max_workspace", ctypes.c_int64),
         ("tune_cache", ctypes.c_char_p),
     ]

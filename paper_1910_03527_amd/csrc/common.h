@@ -18,6 +18,7 @@ constexpr int kMaxPair = kMaxActive * (kMaxActive + 1) / 2;
 constexpr int kMaxOrb = 64;             // orbitals of the whole problem
 constexpr int kMaxSpace = 16;           // Davidson subspace (+1 correction slot)
 constexpr int kBinom = 65;              // binomial table C(n,k), n,k < 65
+constexpr int kMaxPspace = 112;         // P-space (lowest-diagonal determinants) size cap
 
 // packed single-excitation link: bits 0..21 string address J, bits 22..29
 // orbital-pair index pair(p,q) = max(p,q)*(max(p,q)+1)/2 + min(p,q),
@@ -83,6 +84,9 @@ struct ItemHam {
   double heff[kMaxActive * kMaxActive];  // h_eff_tu
   double J[kMaxActive * kMaxActive];     // (tt|uu)
   double K[kMaxActive * kMaxActive];     // (tu|ut)
+  const double* eri;                     // (pq|rs) of the whole problem, [M^4]
+  int32_t M;                             // its orbital count
+  int32_t act[kMaxActive];               // active orbital t -> orbital of the problem
 };
 
 // Per-item Davidson state (device resident).
@@ -92,7 +96,7 @@ struct DavState {
   int32_t iters;      // iterations taken
   int32_t status;     // 0 ok, 1 not converged, 2 breakdown
   int32_t nguess;     // number of guess vectors (slots 0..nguess-1)
-  int32_t pad_;
+  int32_t np;         // P-space size (0: diagonal preconditioner only)
   double theta;       // lowest Ritz value (active-space energy without ecore)
   double rnorm;       // residual norm of the last Ritz vector
   double tnorm2;      // squared norm of the correction vector

@@ -192,7 +192,12 @@ __device__ void build_item_hamiltonian(const ActiveSet& s, int M, const double* 
     if (t < w) s_red[t] += s_red[t + w];
     __syncthreads();
   }
-  if (t == 0) ham->ecore = e_const + s_red[0];
+  if (t == 0) {
+    ham->ecore = e_const + s_red[0];
+    ham->eri = eri;
+    ham->M = M;
+    for (int i = 0; i < kMaxActive; ++i) ham->act[i] = i < n ? s.act[i] : 0;
+  }
   // effective one-electron operator, Coulomb/exchange diagonals
   for (int x = t; x < n * n; x += nt) {
     int tt = x / n, uu = x % n;
@@ -702,6 +707,7 @@ __global__ void k_dav_guess(const Item* __restrict__ items, int ibase,
   if (t == 0) {
     S.m = 0;
     S.nguess = g;
+    S.np = 0;
     S.iters = 0;
     S.status = 0;
     S.rnorm = 0.0;
@@ -1052,7 +1058,8 @@ __global__ void k_dav_reduce_coef(const Item* __restrict__ items, const double* 
 
 // Convergence test and first Gram-Schmidt coefficients.
 __global__ void k_dav_reduce1(const Item* __restrict__ items, const double* __restrict__ part,
-                              DavState* st, int ibase, int nitem, double tol, int max_iter) {
+                              const double* __restrict__ pdots, DavState* st, int ibase,
+                              int nitem, double tol, int max_iter) {
   int it = blockIdx.x * blockDim.x + threadIdx.x;
   if (it >= nitem) return;
   it += ibase;
@@ -1067,6 +1074,8 @@ __global__ void k_dav_reduce1(const Item* __restrict__ items, const double* __re
     rr += p[kMaxSpace];
     for (int i = 0; i < S.m; ++i) cf[i] += p[i];
   }
+  if (pdots && S.np > 0)  // the P-space correction changed t on the P block
+    for (int i = 0; i < S.m; ++i) cf[i] += pdots[(int64_t)it * kMaxSpace + i];
   S.rnorm = sqrt(rr);
   for (int i = 0; i < kMaxSpace; ++i) S.coef[i] = cf[i];
   if (S.rnorm <= tol || S.m >= I.ndet) {
@@ -1172,6 +1181,497 @@ __global__ void k_dav_grow(DavState* st, int ibase, int nitem) {
   i += ibase;
   DavState& S = st[i];
   if (!S.conv) S.m += 1;
+}
+
+// ------------------------------------------------------------- P-space
+// Davidson with a P-space: the np = min(kMaxPspace-ish cap, ndet) determinants
+// of lowest diagonal energy (ties: lower address) span a block H_PP of H that
+// is diagonalised exactly once per CASCI, H_PP = U diag(lambda) U^T.  It
+// supplies (i) the guess, the lowest eigenvector of H_PP plus the
+// lowest-diagonal unit vector orthogonalised against it (so every spin and
+// spatial symmetry sector of the determinant basis stays in the subspace),
+// and (ii) the preconditioner: the correction t = (theta - H)^-1 r is
+// approximated by (theta - H_PP)^-1 r on the P block and by the diagonal
+// (theta - H_II)^-1 r elsewhere.  The converged eigenpair does not depend on
+// either choice, only the number of iterations does.
+
+// Orderable 64-bit key of a double (ascending unsigned order = ascending
+// value; -0 and +0 share the key of +0).
+__device__ inline uint64_t order_key(double x) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x == 0.0 ? 0.0 : x);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+// Selection of the np lowest (diagonal, address) keys of one item, by radix
+// select over the 96-bit key (order_key(H_II) << 32 | address) in 8-bit
+// digits (12 histogram passes), then a rank sort of the np survivors.
+// One 256-thread block per item; pidx[item][k] receives the addresses in
+// ascending key order.
+__global__ void __launch_bounds__(256) k_pspace_select(const Item* __restrict__ items, int ibase,
+                                                       const double* __restrict__ diag,
+                                                       int32_t* __restrict__ pidx, int pmax) {
+  const int it = ibase + blockIdx.x;
+  const Item& I = items[it];
+  const int64_t nd = I.ndet;
+  const int np = (int)(nd < pmax ? nd : pmax);
+  const double* __restrict__ d = diag + I.off;
+  const int t = threadIdx.x;
+  __shared__ uint32_t hist[256];
+  __shared__ uint64_t pre_hi;
+  __shared__ uint32_t pre_lo;
+  __shared__ int64_t need;
+  __shared__ uint32_t ncol;
+  __shared__ uint64_t khi[kMaxPspace];
+  __shared__ uint32_t klo[kMaxPspace];
+  if (t == 0) { pre_hi = 0; pre_lo = 0; need = np; ncol = 0; }
+  __syncthreads();
+  if (np < nd) {
+    // digits 0..7: the value key from the top; digits 8..11: the address
+    for (int dg = 0; dg < 12; ++dg) {
+      hist[t] = 0;
+      __syncthreads();
+      const uint64_t ph = pre_hi;
+      const uint32_t pl = pre_lo;
+      for (int64_t K = t; K < nd; K += 256) {
+        const uint64_t kh = order_key(d[K]);
+        const uint32_t kl = (uint32_t)K;
+        bool match;
+        int b;
+        if (dg < 8) {
+          const int sh = 56 - 8 * dg;
+          match = dg == 0 || (kh >> (sh + 8)) == (ph >> (sh + 8));
+          b = (int)((kh >> sh) & 0xFF);
+        } else {
+          const int sh = 24 - 8 * (dg - 8);
+          match = kh == ph && (dg == 8 || (kl >> (sh + 8)) == (pl >> (sh + 8)));
+          b = (int)((kl >> sh) & 0xFF);
+        }
+        if (match) atomicAdd(&hist[b], 1u);
+      }
+      __syncthreads();
+      if (t == 0) {
+        int64_t k = need, cum = 0;
+        int b = 0;
+        for (; b < 255; ++b) {
+          if (cum + hist[b] >= k) break;
+          cum += hist[b];
+        }
+        need = k - cum;
+        if (dg < 8) pre_hi |= (uint64_t)b << (56 - 8 * dg);
+        else pre_lo |= (uint32_t)b << (24 - 8 * (dg - 8));
+      }
+      __syncthreads();
+    }
+  } else if (t == 0) {
+    pre_hi = ~0ull;
+    pre_lo = ~0u;
+  }
+  __syncthreads();
+  // collect every key <= the np-th smallest (exactly np of them)
+  const uint64_t ph = pre_hi;
+  const uint32_t pl = pre_lo;
+  for (int64_t K = t; K < nd; K += 256) {
+    const uint64_t kh = order_key(d[K]);
+    const uint32_t kl = (uint32_t)K;
+    if (kh < ph || (kh == ph && kl <= pl)) {
+      const uint32_t slot = atomicAdd(&ncol, 1u);
+      if (slot < (uint32_t)kMaxPspace) { khi[slot] = kh; klo[slot] = kl; }
+    }
+  }
+  __syncthreads();
+  // rank sort (keys are distinct)
+  if (t < np) {
+    const uint64_t kh = khi[t];
+    const uint32_t kl = klo[t];
+    int rank = 0;
+    for (int j = 0; j < np; ++j)
+      rank += (khi[j] < kh || (khi[j] == kh && klo[j] < kl)) ? 1 : 0;
+    pidx[(int64_t)it * kMaxPspace + rank] = (int32_t)kl;
+  }
+}
+
+// Matrix element <I|H - E_core|J> between two different determinants of the
+// active space (Slater-Condon rules; strings are bit masks over the active
+// orbitals, alpha string before beta string, each in ascending order).
+__device__ inline int between_parity(uint64_t s, int p, int q) {
+  const int lo = p < q ? p : q, hi = p < q ? q : p;
+  const uint64_t m = (((uint64_t)1 << hi) - 1) & ~((((uint64_t)1 << lo) << 1) - 1);
+  return __builtin_popcountll(s & m) & 1;
+}
+__device__ double sc_offdiag(const ItemHam& H, uint64_t ia, uint64_t ib, uint64_t ja,
+                             uint64_t jb) {
+  const uint64_t xa = ia ^ ja, xb = ib ^ jb;
+  const int da = __builtin_popcountll(xa) >> 1, db = __builtin_popcountll(xb) >> 1;
+  if (da + db > 2) return 0.0;
+  const double* __restrict__ eri = H.eri;
+  const int M = H.M;
+  auto g = [&](int p, int q, int r, int s) -> double {
+    return ldg(eri + (((int64_t)H.act[p] * M + H.act[q]) * M + H.act[r]) * M + H.act[s]);
+  };
+  if (da + db == 1) {
+    // one excitation q -> p in the string of spin sigma
+    const uint64_t is = da ? ia : ib, js = da ? ja : jb, jo = da ? jb : ja;
+    const int p = __builtin_ctzll(is & ~js), q = __builtin_ctzll(js & ~is);
+    double v = H.heff[p * kMaxActive + q];
+    for (uint64_t x = js; x; x &= x - 1) {
+      const int r = __builtin_ctzll(x);
+      v += g(p, q, r, r) - g(p, r, r, q);   // r = q contributes zero
+    }
+    for (uint64_t x = jo; x; x &= x - 1) {
+      const int r = __builtin_ctzll(x);
+      v += g(p, q, r, r);
+    }
+    return between_parity(js, p, q) ? -v : v;
+  }
+  if (da == 1 && db == 1) {
+    const int p = __builtin_ctzll(ia & ~ja), q = __builtin_ctzll(ja & ~ia);
+    const int r = __builtin_ctzll(ib & ~jb), s = __builtin_ctzll(jb & ~ib);
+    const double v = g(p, q, r, s);
+    return (between_parity(ja, p, q) ^ between_parity(jb, r, s)) ? -v : v;
+  }
+  // two excitations in one string: holes q1 < q2, particles p1 < p2;
+  // I = E_p1q1 E_p2q2 J (up to the sign), element (p1 q1|p2 q2) - (p1 q2|p2 q1)
+  const uint64_t is = da ? ia : ib, js = da ? ja : jb;
+  uint64_t pp = is & ~js, hh = js & ~is;
+  const int p1 = __builtin_ctzll(pp), p2 = 63 - __builtin_clzll(pp);
+  const int q1 = __builtin_ctzll(hh), q2 = 63 - __builtin_clzll(hh);
+  const uint64_t k = (js & ~((uint64_t)1 << q2)) | ((uint64_t)1 << p2);
+  const int par = between_parity(js, p2, q2) ^ between_parity(k, p1, q1);
+  const double v = g(p1, q1, p2, q2) - g(p1, q2, p2, q1);
+  return par ? -v : v;
+}
+
+// One 512-thread block per item: build H_PP (packed lower triangle in LDS)
+// and reduce it to tridiagonal form by Householder reflections,
+// H_PP = Q T Q^T (T: diagonal d, off-diagonal e; Q accumulated explicitly).
+// The lowest eigenvalue of T comes from multisection on Sturm counts (every
+// thread evaluates one point per round), its eigenvector from inverse
+// iteration; the guess is Q z.  The P-space is used when it holds the whole
+// CASCI (ndet <= pmax: the guess is then the exact ground state) or when the
+// CASCI is large enough for the reduction to pay off (ndet >=
+// kPspaceMinRatio * pmax); other CASCIs get the two lowest-diagonal unit
+// vectors and the diagonal correction.
+constexpr int kPspaceMinRatio = 32;
+constexpr int kPspaceThreads = 512;
+
+// Solve (theta - T) z = y for symmetric tridiagonal T (diagonal d, off-
+// diagonal e) by an LDL^T sweep without pivoting, pivots kept at |p| >= floor
+// (1e-8 for the correction, like the diagonal one; a tiny relative floor for
+// inverse iteration).  In the Davidson iteration theta never exceeds the
+// lowest eigenvalue of T, so theta - T is negative semidefinite and the sweep
+// is stable.  z may alias y.
+__device__ inline double floored(double p, double floor) {
+  return fabs(p) < floor ? (p < 0 ? -floor : floor) : p;
+}
+__device__ inline void tridiag_shift_solve(const double* d, const double* e, int n, double theta,
+                                           const double* y, double* z, double* piv,
+                                           double floor) {
+  double p = floored(theta - d[0], floor);
+  piv[0] = p;
+  z[0] = y[0];
+  for (int i = 1; i < n; ++i) {
+    const double l = -e[i - 1] / p;           // multiplier of the off-diagonal (-e)
+    p = floored((theta - d[i]) + l * e[i - 1], floor);
+    piv[i] = p;
+    z[i] = y[i] - l * z[i - 1];
+  }
+  z[n - 1] = z[n - 1] / piv[n - 1];
+  for (int i = n - 2; i >= 0; --i) z[i] = (z[i] + e[i] * z[i + 1]) / piv[i];
+}
+
+__device__ inline int sturm_count(const double* d, const double* e, int n, double x) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (q == 0.0) q = -1e-300;
+  cnt += q < 0.0;
+  for (int i = 1; i < n; ++i) {
+    q = (d[i] - x) - e[i - 1] * e[i - 1] / q;
+    if (q == 0.0) q = -1e-300;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+__global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
+    const Item* __restrict__ items, int ibase, const ItemHam* __restrict__ hams,
+    const double* __restrict__ diag, const int32_t* __restrict__ pidx, double* __restrict__ pQ,
+    double* __restrict__ pT, double* V, int64_t ntot, DavState* st, int pmax) {
+  constexpr int PM = kMaxPspace;
+  constexpr int NT = kPspaceThreads;
+  __shared__ double A[PM * (PM + 1) / 2];
+  __shared__ double Q[PM * PM];
+  __shared__ uint64_t sa[PM], sb[PM];
+  __shared__ double vv[PM], pw[PM], dd[PM], ee[PM], beta[PM], zz[PM], piv[PM];
+  __shared__ double red[NT / 64];
+  __shared__ double lo_hi[2];
+  __shared__ double nrm2;
+  const int it = ibase + blockIdx.x;
+  const Item& I = items[it];
+  DavState& S = st[it];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t nd = I.ndet;
+  const int32_t* __restrict__ idx = pidx + (int64_t)it * PM;
+  if (nd == 1) {  // nothing to solve: the single determinant
+    if (t == 0) {
+      V[I.off] = 1.0;
+      S.m = 1; S.nguess = 1; S.np = 0; S.iters = 0; S.status = 0; S.rnorm = 0.0; S.conv = 1;
+      S.theta = diag[I.off];
+    }
+    return;
+  }
+  if (nd > pmax && nd < (int64_t)kPspaceMinRatio * pmax) {
+    // unit vectors on the two lowest diagonal determinants (idx is sorted)
+    if (t < 2) V[(int64_t)t * ntot + I.off + idx[t]] = 1.0;
+    if (t == 0) {
+      S.m = 0; S.nguess = 2; S.np = 0; S.iters = 0; S.status = 0; S.rnorm = 0.0; S.conv = 0;
+      S.theta = 0.0;
+    }
+    return;
+  }
+  // fixed-order block sum of one value per thread
+  auto block_sum = [&](double x) -> double {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    __syncthreads();
+    if (lane == 0) red[wv] = x;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s += red[w];
+    return s;
+  };
+  const int n = (int)(nd < pmax ? nd : pmax);
+  const ItemHam& H = hams[I.ham];
+  for (int k = t; k < n; k += NT) {
+    const int e = idx[k];  // an address of this item: 0 <= e < ndet
+    sa[k] = I.strA[e / I.Nb];
+    sb[k] = I.strB[e % I.Nb];
+  }
+  __syncthreads();
+  auto L = [](int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; };
+  for (int i = t; i < n; i += NT)   // row i of the packed lower triangle
+    for (int j = 0; j <= i; ++j)
+      A[i * (i + 1) / 2 + j] =
+          (i == j) ? diag[I.off + idx[i]] : sc_offdiag(H, sa[i], sb[i], sa[j], sb[j]);
+  __syncthreads();
+
+  // ---- Householder reduction: step k annihilates A[k+2.., k]
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    double x = 0.0;
+    if (t < m) {
+      x = A[L(k + 1 + t, k)];
+      vv[t] = x;
+    }
+    const double sig = block_sum(x * x);  // (includes a barrier)
+    const double x0 = vv[0];
+    const double sg = sqrt(sig);
+    const double alpha = x0 >= 0.0 ? -sg : sg;
+    const double bt = sig > 0.0 ? 1.0 / (sig - x0 * alpha) : 0.0;
+    __syncthreads();
+    if (t == 0) {
+      vv[0] = x0 - alpha;
+      ee[k] = sig > 0.0 ? alpha : x0;
+      beta[k] = bt;
+    }
+    __syncthreads();
+    if (bt != 0.0) {
+      // p = beta B v, four threads per row of the trailing block B
+      {
+        const int row = t >> 2, part = t & 3;
+        double acc = 0.0;
+        if (row < m)
+          for (int j = part; j < m; j += 4) acc += A[L(k + 1 + row, k + 1 + j)] * vv[j];
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        if (row < m && part == 0) pw[row] = bt * acc;
+      }
+      __syncthreads();
+      const double Kc = 0.5 * bt * block_sum(t < m ? pw[t] * vv[t] : 0.0);
+      __syncthreads();
+      if (t < m) pw[t] -= Kc * vv[t];   // w = p - K v
+      __syncthreads();
+      // B -= v w^T + w v^T (lower triangle), rows strided by 64, columns by 8
+      for (int i = t >> 3; i < m; i += NT / 8)
+        for (int j = t & 7; j <= i; j += 8)
+          A[L(k + 1 + i, k + 1 + j)] -= vv[i] * pw[j] + pw[i] * vv[j];
+    }
+    // keep v in column k below the diagonal (A[k+1+i, k] = v_i)
+    if (t < m) A[L(k + 1 + t, k)] = vv[t];
+    __syncthreads();
+  }
+  for (int i = t; i < n; i += NT) {
+    dd[i] = A[L(i, i)];
+    if (i == n - 2) ee[i] = A[L(n - 1, n - 2)];
+  }
+  if (t == 0 && n >= 1) ee[n - 1] = 0.0;
+  // ---- Q = H_0 H_1 ... H_{n-3}, accumulated backwards from the identity
+  for (int x = t; x < n * n; x += NT) Q[x] = (x / n == x % n) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int k = n - 3; k >= 0; --k) {
+    const int m = n - k - 1;
+    const double bt = beta[k];
+    if (bt == 0.0) continue;  // uniform
+    // s_j = sum_i v_i Q[k+1+i][j] for columns j > k (columns <= k are still
+    // those of the identity there); four threads per column
+    {
+      const int col = k + 1 + (t >> 2), part = t & 3;
+      double acc = 0.0;
+      if (col < n)
+        for (int i = part; i < m; i += 4) acc += A[L(k + 1 + i, k)] * Q[(k + 1 + i) * n + col];
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      if (col < n && part == 0) pw[col - k - 1] = bt * acc;
+    }
+    __syncthreads();
+    for (int x = t; x < m * m; x += NT) {
+      const int i = x / m, j = x % m;
+      Q[(k + 1 + i) * n + (k + 1 + j)] -= A[L(k + 1 + i, k)] * pw[j];
+    }
+    __syncthreads();
+  }
+  // ---- lowest eigenvalue of T: multisection on [lo, hi] (Gershgorin)
+  if (t == 0) {
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < n; ++i) {
+      const double rr = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < n ? fabs(ee[i]) : 0.0);
+      lo = fmin(lo, dd[i] - rr);
+      hi = fmax(hi, dd[i] + rr);
+    }
+    lo_hi[0] = lo;
+    lo_hi[1] = hi;
+  }
+  __syncthreads();
+  for (int round = 0; round < 8; ++round) {
+    const double lo = lo_hi[0], hi = lo_hi[1];
+    const double x = lo + (hi - lo) * (double)(t + 1) / (double)NT;
+    const int c = sturm_count(dd, ee, n, x);
+    // the first point with at least one eigenvalue below it
+    __syncthreads();
+    if (c >= 1 && (t == 0 || sturm_count(dd, ee, n, lo + (hi - lo) * (double)t / (double)NT) == 0)) {
+      lo_hi[0] = lo + (hi - lo) * (double)t / (double)NT;
+      lo_hi[1] = x;
+    }
+    __syncthreads();
+  }
+  const double lam0 = 0.5 * (lo_hi[0] + lo_hi[1]);
+  // ---- eigenvector of T for lam0: inverse iteration, (lam0 - T) z = z, with
+  // pivots floored at 1e-15 of the spectrum's scale
+  if (t == 0) {
+    double scale = 0.0;
+    for (int i = 0; i < n; ++i) scale = fmax(scale, fabs(dd[i]) + 2.0 * fabs(ee[i]));
+    const double floor = 1e-15 * fmax(scale, 1e-300);
+    for (int i = 0; i < n; ++i) zz[i] = 1.0;
+    for (int rep = 0; rep < 3; ++rep) {
+      tridiag_shift_solve(dd, ee, n, lam0, zz, zz, piv, floor);
+      double s2 = 0.0;
+      for (int i = 0; i < n; ++i) s2 += zz[i] * zz[i];
+      const double inv = 1.0 / sqrt(s2);
+      for (int i = 0; i < n; ++i) zz[i] *= inv;
+    }
+  }
+  __syncthreads();
+  // ---- outputs: Q (row = P position), T, the guess vectors
+  double* __restrict__ Qo = pQ + (int64_t)it * PM * PM;
+  for (int x = t; x < n * n; x += NT) Qo[(x / n) * PM + (x % n)] = Q[x];
+  double* __restrict__ To = pT + (int64_t)it * 2 * PM;
+  for (int i = t; i < n; i += NT) {
+    To[i] = dd[i];
+    To[PM + i] = ee[i];
+  }
+  // u = Q z (row k: P position k)
+  if (t < n) {
+    double u = 0.0;
+    for (int j = 0; j < n; ++j) u += Q[t * n + j] * zz[j];
+    vv[t] = u;
+  }
+  __syncthreads();
+  const double u0 = vv[0];
+  if (t == 0) {
+    double n2 = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const double w = (k == 0 ? 1.0 : 0.0) - u0 * vv[k];
+      n2 += w * w;
+    }
+    nrm2 = n2;
+  }
+  __syncthreads();
+  const bool two = nrm2 > 1e-12;
+  const double inv = two ? 1.0 / sqrt(nrm2) : 0.0;
+  double* __restrict__ v0 = V + I.off;
+  double* __restrict__ v1 = V + ntot + I.off;
+  for (int k = t; k < n; k += NT) {
+    const int e = idx[k];
+    v0[e] = vv[k];
+    if (two) v1[e] = ((k == 0 ? 1.0 : 0.0) - u0 * vv[k]) * inv;
+  }
+  if (t == 0) {
+    S.m = 0;
+    S.nguess = two ? 2 : 1;
+    S.np = n;
+    S.iters = 0;
+    S.status = 0;
+    S.rnorm = 0.0;
+    S.conv = 0;
+    S.theta = 0.0;
+  }
+}
+
+// P-space correction, run after k_dav_residual: on the P block replace the
+// diagonal correction by t_P = Q (theta - T)^-1 Q^T r_P = (theta - H_PP)^-1 r_P,
+// and store the change of the Gram-Schmidt dots V_i . t (i < m) in
+// pdots[item] for k_dav_reduce1.
+__global__ void __launch_bounds__(256) k_pspace_correct(const Item* __restrict__ items, int ibase,
+                                                        const int32_t* __restrict__ pidx,
+                                                        const double* __restrict__ pQ,
+                                                        const double* __restrict__ pT, double* V,
+                                                        const double* __restrict__ Sv,
+                                                        int64_t ntot,
+                                                        const DavState* __restrict__ st,
+                                                        double* __restrict__ pdots) {
+  constexpr int PM = kMaxPspace;
+  const int it = ibase + blockIdx.x;
+  const Item& I = items[it];
+  const DavState& S = st[it];
+  if (S.conv || S.np == 0) return;
+  const int np = S.np, m = S.m, t = threadIdx.x;
+  const double th = S.theta;
+  __shared__ double r[PM], z[PM], dd[PM], ee[PM], piv[PM];
+  const int32_t* __restrict__ idx = pidx + (int64_t)it * PM;
+  const double* __restrict__ Qi = pQ + (int64_t)it * PM * PM;
+  double tnew = 0.0, told = 0.0;
+  int e = 0;
+  if (t < np) {
+    e = idx[t];
+    double rv = 0.0;
+    for (int i = 0; i < m; ++i)
+      rv += S.y[i] * (Sv[(int64_t)i * ntot + I.off + e] - th * V[(int64_t)i * ntot + I.off + e]);
+    r[t] = rv;
+    told = V[(int64_t)m * ntot + I.off + e];
+    dd[t] = pT[(int64_t)it * 2 * PM + t];
+    ee[t] = pT[(int64_t)it * 2 * PM + PM + t];
+  }
+  __syncthreads();
+  if (t < np) {
+    double zj = 0.0;
+    for (int k = 0; k < np; ++k) zj += Qi[k * PM + t] * r[k];
+    z[t] = zj;
+  }
+  __syncthreads();
+  if (t == 0) tridiag_shift_solve(dd, ee, np, th, z, z, piv, 1e-8);
+  __syncthreads();
+  double acc[kMaxSpace];
+#pragma unroll
+  for (int i = 0; i < kMaxSpace; ++i) acc[i] = 0.0;
+  if (t < np) {
+    for (int j = 0; j < np; ++j) tnew += Qi[t * PM + j] * z[j];
+    V[(int64_t)m * ntot + I.off + e] = tnew;
+    const double dl = tnew - told;
+#pragma unroll
+    for (int i = 0; i < kMaxSpace; ++i)
+      if (i < m) acc[i] = V[(int64_t)i * ntot + I.off + e] * dl;
+  }
+  block_reduce_store<kMaxSpace>(acc, pdots + (int64_t)it * kMaxSpace);
 }
 
 // ------------------------------------------------------------------- RDMs
@@ -1746,10 +2246,17 @@ void launch_dav_rr(const Item* items, int ibase, int nitem, const double* part, 
                    int slot, hipStream_t s) {
   hipLaunchKernelGGL(k_dav_rr, dim3(nitem), dim3(64), 0, s, items, ibase, part, st, slot);
 }
+void launch_pspace_setup(const Item* items, int ibase, int nitem, const ItemHam* hams,
+                         const double* diag, int32_t* pidx, double* pQ, double* pT, double* V,
+                         int64_t ntot, DavState* st, int pmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_pspace_select, dim3(nitem), dim3(256), 0, s, items, ibase, diag, pidx, pmax);
+  hipLaunchKernelGGL(k_pspace_eigen, dim3(nitem), dim3(kPspaceThreads), 0, s, items, ibase, hams,
+                     diag, pidx, pQ, pT, V, ntot, st, pmax);
+}
 void launch_dav_iteration(const Item* items, int ibase, int nitem, const Work* chunks, int nchunk,
                           double* V, double* Sv, const double* diag, int64_t ntot, DavState* st,
                           double* part, double tol, int max_iter, int mmax, double* Rb,
-                          double* Xb, hipStream_t s) {
+                          double* Xb, const PspaceArgs* ps, hipStream_t s) {
   if (nchunk <= 0) return;
   const int nb = nblk(nitem, 64);
   hipLaunchKernelGGL(k_dav_collapse, dim3(nchunk), dim3(256), 0, s, items, chunks, V, Sv, ntot, st,
@@ -1766,8 +2273,11 @@ void launch_dav_iteration(const Item* items, int ibase, int nitem, const Work* c
   } else {
     hipLaunchKernelGGL(k_dav_residual, dim3(nchunk), dim3(256), 0, s, items, chunks, V, Sv, diag,
                        ntot, st, part);
-    hipLaunchKernelGGL(k_dav_reduce1, dim3(nb), dim3(64), 0, s, items, part, st, ibase, nitem, tol,
-                       max_iter);
+    if (ps)
+      hipLaunchKernelGGL(k_pspace_correct, dim3(nitem), dim3(256), 0, s, items, ibase, ps->pidx,
+                         ps->pQ, ps->pT, V, Sv, ntot, st, ps->pdots);
+    hipLaunchKernelGGL(k_dav_reduce1, dim3(nb), dim3(64), 0, s, items, part,
+                       ps ? ps->pdots : nullptr, st, ibase, nitem, tol, max_iter);
   }
   hipLaunchKernelGGL(k_dav_orth, dim3(nchunk), dim3(256), 0, s, items, chunks, V, ntot, st, part);
   hipLaunchKernelGGL(k_dav_reduce2, dim3(nb), dim3(64), 0, s, items, part, st, ibase, nitem);

@@ -34,10 +34,23 @@ void launch_dav_dots(const Item* items, const Work* chunks, int nchunk, const do
                      hipStream_t s);
 void launch_dav_rr(const Item* items, int ibase, int nitem, const double* part, DavState* st,
                    int slot, hipStream_t s);
+// P-space arrays of a plan: pidx [item][kMaxPspace] determinant addresses,
+// pQ [item][kMaxPspace^2] orthogonal factor of H_PP = Q T Q^T (row = P
+// position), pT [item][2][kMaxPspace] diagonal and off-diagonal of T, pdots
+// [item][kMaxSpace] Gram-Schmidt dot corrections.
+struct PspaceArgs {
+  const int32_t* pidx;
+  const double* pQ;
+  const double* pT;
+  double* pdots;
+};
+void launch_pspace_setup(const Item* items, int ibase, int nitem, const ItemHam* hams,
+                         const double* diag, int32_t* pidx, double* pQ, double* pT, double* V,
+                         int64_t ntot, DavState* st, int pmax, hipStream_t s);
 void launch_dav_iteration(const Item* items, int ibase, int nitem, const Work* chunks, int nchunk,
                           double* V, double* Sv, const double* diag, int64_t ntot, DavState* st,
                           double* part, double tol, int max_iter, int mmax, double* Rb,
-                          double* Xb, hipStream_t s);
+                          double* Xb, const PspaceArgs* ps, hipStream_t s);
 void launch_item_energy(const Item* items, const ItemHam* hams, const DavState* st, int nitem,
                         double* f, hipStream_t s);
 void launch_mbe_combine(const MbeSpaces* sp, const BucketDev* buckets, int nbucket,

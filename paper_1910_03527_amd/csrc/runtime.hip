@@ -100,6 +100,10 @@ struct Plan {
   BucketDev* d_buckets = nullptr;
   double *V = nullptr, *S = nullptr, *diag = nullptr, *G = nullptr, *W = nullptr,
          *part = nullptr, *f = nullptr, *inc = nullptr, *ci = nullptr, *R = nullptr, *X = nullptr;
+  // P-space (lowest-diagonal block of H): addresses, eigenvectors, eigenvalues,
+  // Gram-Schmidt dot corrections; null when the P-space is off
+  int32_t* pidx = nullptr;
+  double *pQ = nullptr, *pT = nullptr, *pdots = nullptr;
   ItemHam* hams = nullptr;
   DavState* st = nullptr;
   int32_t* tuple_pos = nullptr;
@@ -300,6 +304,8 @@ int64_t build_passes(mbefci_ctx* c, Plan& P) {
 
 // items must have n, na, nb filled; computes every derived field, work lists
 // and allocates the arenas.
+bool use_pspace(const mbefci_ctx* c) { return c->opts.pspace > 0 && c->opts.precond == 0; }
+
 void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
   const int mmax = c->opts.max_space;
   P.nitem = (int)P.items.size();
@@ -402,6 +408,12 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
   P.V = arena<double>(c, "V", (size_t)(mmax + 1) * P.ntot, &grown);
   P.S = arena<double>(c, "S", (size_t)mmax * P.ntot, &grown);
   P.diag = arena<double>(c, "diag", P.ntot, &grown);
+  if (use_pspace(c)) {
+    P.pidx = arena<int32_t>(c, "pidx", (size_t)P.nitem * kMaxPspace, &grown);
+    P.pQ = arena<double>(c, "pQ", (size_t)P.nitem * kMaxPspace * kMaxPspace, &grown);
+    P.pT = arena<double>(c, "pT", (size_t)P.nitem * 2 * kMaxPspace, &grown);
+    P.pdots = arena<double>(c, "pdots", (size_t)P.nitem * kMaxSpace, &grown);
+  }
   if (c->opts.precond == 1) {
     P.R = arena<double>(c, "resid", P.ntot, &grown);
     P.X = arena<double>(c, "ritz", P.ntot, &grown);
@@ -496,10 +508,11 @@ void add_vector(mbefci_ctx* c, Plan& P, const View& v, int slot) {
 // to it and updates the subspace matrix and Ritz pair.
 void step_a(mbefci_ctx* c, Plan& P, const View& v) {
   const bool olsen = c->opts.precond == 1;
+  const PspaceArgs ps{P.pidx, P.pQ, P.pT, P.pdots};
   launch_dav_iteration(P.d_items, v.ibase, v.nitem, P.d_chunks + v.chunk_lo, v.nchunk, P.V, P.S,
                        P.diag, P.ntot, P.st, P.part, c->opts.conv_tol, c->opts.max_iter,
                        c->opts.max_space, olsen ? P.R : nullptr, olsen ? P.X : nullptr,
-                       c->stream);
+                       P.pidx ? &ps : nullptr, c->stream);
 }
 void step_b(mbefci_ctx* c, Plan& P, const View& v) { add_vector(c, P, v, -1); }
 
@@ -521,6 +534,7 @@ void autotune(mbefci_ctx* c, Plan& P) {
   if (c->opts.tile != 0 || P.tuned) return;
   P.tuned = true;
   load_tune_cache(c);
+  HIPCHK(hipStreamSynchronize(c->stream));  // the clock covers the tuner only
   auto t0 = std::chrono::steady_clock::now();
   bool changed = false;
   hipEvent_t e0, e1;
@@ -584,8 +598,14 @@ void autotune(mbefci_ctx* c, Plan& P) {
 
 // guess + iterations for the items of view v (hdiag and set-up already done)
 void solve_view(mbefci_ctx* c, Plan& P, const View& v, int* graph_launches) {
-  const int g = std::max(1, std::min(c->opts.nguess, 8));
-  launch_dav_guess(P.d_items, v.ibase, v.nitem, P.diag, P.V, P.ntot, P.st, g, c->stream);
+  int g = std::max(1, std::min(c->opts.nguess, 8));
+  if (P.pidx) {
+    launch_pspace_setup(P.d_items, v.ibase, v.nitem, P.hams, P.diag, P.pidx, P.pQ, P.pT, P.V,
+                        P.ntot, P.st, c->opts.pspace, c->stream);
+    g = 2;  // the P-space eigenvector and the orthogonalised lowest-diagonal vector
+  } else {
+    launch_dav_guess(P.d_items, v.ibase, v.nitem, P.diag, P.V, P.ntot, P.st, g, c->stream);
+  }
   if (v.item < 0) autotune(c, P);
   for (int j = 0; j < g; ++j) add_vector(c, P, v, j);
   const int max_iter = c->opts.max_iter;
@@ -635,7 +655,7 @@ void solve_view(mbefci_ctx* c, Plan& P, const View& v, int* graph_launches) {
 }
 
 void solve_plan(mbefci_ctx* c, Plan& P, mbefci_stats* stats) {
-  const int g = std::max(1, std::min(c->opts.nguess, 8));
+  const int g = P.pidx ? 2 : std::max(1, std::min(c->opts.nguess, 8));
   HIPCHK(hipEventRecord(c->t0, c->stream));
   launch_hdiag(P.d_items, P.d_blocks, P.nblock, P.hams, P.diag, c->stream);
   launch_fill(P.V, (int64_t)g * P.ntot, 0.0, c->stream);
@@ -867,6 +887,7 @@ void mbefci_default_opts(mbefci_opts* o) {
   o->validate = 1;
   o->sigma_pass_mb = 0;
   o->precond = 0;
+  o->pspace = kMaxPspace;
   o->max_workspace = 0;
   o->tune_cache = nullptr;
 }
@@ -880,6 +901,7 @@ static int check_opts(const mbefci_opts* o, std::string* why) {
   if (o->tile != 0 && o->tile != 32 && o->tile != 64 && o->tile != 128) { *why = "tile must be 0, 32, 64 or 128"; return MBEFCI_EINVAL; }
   if (o->sigma_pass_mb < 0) { *why = "sigma_pass_mb must be >= 0"; return MBEFCI_EINVAL; }
   if (o->precond != 0 && o->precond != 1) { *why = "precond must be 0 or 1"; return MBEFCI_EINVAL; }
+  if (o->pspace < 0 || o->pspace > kMaxPspace) { *why = "pspace must be in 0..112"; return MBEFCI_EINVAL; }
   return MBEFCI_OK;
 }
 
@@ -944,7 +966,8 @@ int mbefci_set_opts(mbefci_ctx* c, const mbefci_opts* o) {
     return rc;
   }
   bool plan_dead = o->max_space != c->opts.max_space || o->tile != c->opts.tile ||
-                   o->sigma_pass_mb != c->opts.sigma_pass_mb || o->precond != c->opts.precond;
+                   o->sigma_pass_mb != c->opts.sigma_pass_mb || o->precond != c->opts.precond ||
+                   o->pspace != c->opts.pspace;
   c->opts = *o;
   if (plan_dead && c->plan) {
     if (c->plan->graph) (void)hipGraphExecDestroy(c->plan->graph);

@@ -1,0 +1,127 @@
+"""P-space Davidson (needs an MI355X).
+
+The lowest-diagonal block H_PP of every CASCI is built on the device from
+Slater-Condon rules and diagonalised once; it gives the guess vector and,
+on its block, the correction (theta - H_PP)^-1 r.
+
+* When the P-space holds every determinant (N_det <= 112), its lowest
+  eigenvector is the exact ground state: the solver must stop at the first
+  residual test (0 iterations) with the oracle's energy.  Any wrong element
+  of H_PP (a sign, a missed exchange term, a wrong excitation class) leaves a
+  residual far above the 1e-6 tolerance, so this pins the device
+  Slater-Condon rules for singles, same-spin doubles and alpha-beta doubles.
+* With a partial P-space the energies must equal those of the unit-vector
+  guess with the diagonal correction (pspace = 0) to 1e-9 E_h, with no more
+  sigma evaluations.  (Very small P-spaces, a few determinants, can steer the
+  solver to an excited root of a symmetric Hamiltonian: for the 8-orbital
+  test matrix below P = 3..7 does, which a CPU model of the same iteration
+  reproduces; the sizes tested are 1, 64 and the default 112.)
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fci
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1910_03527_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+WHOLE = [(2, 1, 1), (3, 1, 2), (4, 2, 2), (5, 2, 2), (5, 2, 3), (5, 1, 4), (6, 1, 1), (6, 1, 2),
+         (6, 2, 1), (7, 1, 1), (8, 1, 1)]
+
+
+@pytest.mark.parametrize("n,na,nb", WHOLE)
+def test_whole_space_pspace_is_exact(ctx, n, na, nb):
+    _log("pspace whole", n, na, nb)
+    h, g = W.synthetic(n, 700 + 10 * n + na)
+    a = fci.string_masks(range(n), na)
+    b = fci.string_masks(range(n), nb)
+    assert len(a) * len(b) <= 112
+    exp = fci.lowest(fci.hamiltonian(h, g, 0.25, a, b))
+    got = ctx.casci([_dev(h)], [_dev(g)], na, nb, [0.25])[0]
+    st = ctx.last_stats
+    assert abs(got - exp) < 1e-9, (got, exp)
+    if len(a) * len(b) > 1:
+        assert st["max_iters"] == 0, st
+        assert st["sigma_calls"] <= 2, st
+
+
+def test_whole_space_pspace_degenerate_hubbard(ctx):
+    """Hubbard MOs (many equal diagonal energies and vanishing integrals)."""
+    _log("pspace hubbard6 (3,3) in a 5-orbital window")
+    h1, g = W.hubbard_mo(5, 1.0, 2.5)
+    a = fci.string_masks(range(5), 2)
+    exp = fci.lowest(fci.hamiltonian(h1, g, 0.0, a, a))
+    got = ctx.casci([_dev(h1)], [_dev(g)], 2, 2)[0]
+    assert abs(got - exp) < 1e-9
+    assert ctx.last_stats["max_iters"] == 0
+
+
+@pytest.mark.parametrize("pspace", [1, 64, 112])
+def test_partial_pspace_matches_diagonal(ctx, pspace):
+    _log("pspace partial", pspace)
+    from paper_1910_03527_amd import Context
+    h, g = W.synthetic(8, 808)
+    ref = Context(0, pspace=0)
+    try:
+        e0 = ref.casci([_dev(h)], [_dev(g)], 4, 4)[0]
+        s0 = ref.last_stats["sigma_calls"]
+    finally:
+        ref.close()
+    ctx.set_opts(pspace=pspace)
+    try:
+        e1 = ctx.casci([_dev(h)], [_dev(g)], 4, 4)[0]
+        s1 = ctx.last_stats["sigma_calls"]
+    finally:
+        ctx.set_opts(pspace=112)
+    assert abs(e1 - e0) < 1e-9
+    if pspace >= 64:
+        assert s1 <= s0, (s1, s0)
+
+
+def test_mbe_pspace_matches_diagonal(ctx):
+    _log("pspace mbe hubbard12")
+    from paper_1910_03527_amd import Context
+    p = W.problem("hubbard12")
+
+    def run(c):
+        r = c.mbe_forward(_dev(p.h1), _dev(p.eri), p.occ, p.ref, p.exp, p.max_order, p.e_const,
+                          want_increments=True)
+        return r, c.last_stats
+
+    ref = Context(0, pspace=0)
+    try:
+        r0, s0 = run(ref)
+    finally:
+        ref.close()
+    r1, s1 = run(ctx)
+    assert np.max(np.abs(np.array(r1["increments"]) - np.array(r0["increments"]))) < 1e-9
+    assert abs(r1["e_total"] - r0["e_total"]) < 1e-9
+    assert s1["sigma_calls"] < s0["sigma_calls"], (s1, s0)
+
+
+def test_pspace_option_range():
+    from paper_1910_03527_amd import Context, MbefciError
+    with pytest.raises(MbefciError):
+        Context(0, pspace=113)
