@@ -708,6 +708,7 @@ __global__ void k_dav_guess(const Item* __restrict__ items, int ibase,
     S.m = 0;
     S.nguess = g;
     S.np = 0;
+    S.onepass = 0;
     S.iters = 0;
     S.status = 0;
     S.rnorm = 0.0;
@@ -892,7 +893,8 @@ __global__ void k_dav_collapse_state(DavState* st, int ibase, int nitem, int mma
 }
 
 // Residual r = S y - theta V y, preconditioned t = r / (theta - H_II) into
-// slot m; partial sums of |r|^2 (index kMaxSpace) and V_i . t (i < m).
+// slot m; partial sums of V_i . t (i < m), |r|^2 (index kMaxSpace) and |t|^2
+// (index kMaxSpace + 1).
 __global__ void __launch_bounds__(256) k_dav_residual(const Item* __restrict__ items,
                                                       const Work* __restrict__ work, double* V,
                                                       const double* __restrict__ Sv,
@@ -909,9 +911,9 @@ __global__ void __launch_bounds__(256) k_dav_residual(const Item* __restrict__ i
   double y[kMaxSpace];
 #pragma unroll
   for (int i = 0; i < kMaxSpace; ++i) y[i] = S.y[i];
-  double acc[kMaxSpace + 1];
+  double acc[kMaxSpace + 2];
 #pragma unroll
-  for (int i = 0; i <= kMaxSpace; ++i) acc[i] = 0.0;
+  for (int i = 0; i <= kMaxSpace + 1; ++i) acc[i] = 0.0;
   const int64_t e0 = (int64_t)(wk.begin - I.chunk0) * kChunk;
   const int64_t e1 = min(e0 + kChunk, I.ndet);
   double* t_out = V + (int64_t)m * ntot + I.off;
@@ -931,11 +933,12 @@ __global__ void __launch_bounds__(256) k_dav_residual(const Item* __restrict__ i
     if (fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
     const double tv = r / den;
     t_out[e] = tv;
+    acc[kMaxSpace + 1] += tv * tv;
 #pragma unroll
     for (int i = 0; i < kMaxSpace; ++i)
       if (i < m) acc[i] += v[i] * tv;
   }
-  block_reduce_store<kMaxSpace + 1>(acc, part + (int64_t)wk.begin * kPart);
+  block_reduce_store<kMaxSpace + 2>(acc, part + (int64_t)wk.begin * kPart);
 }
 
 // Olsen-corrected preconditioner.  With x = V y the Ritz vector and
@@ -1054,6 +1057,7 @@ __global__ void k_dav_reduce_coef(const Item* __restrict__ items, const double* 
     for (int i = 0; i < S.m; ++i) cf[i] += p[i];
   }
   for (int i = 0; i < kMaxSpace; ++i) S.coef[i] = cf[i];
+  S.onepass = 0;
 }
 
 // Convergence test and first Gram-Schmidt coefficients.
@@ -1066,18 +1070,28 @@ __global__ void k_dav_reduce1(const Item* __restrict__ items, const double* __re
   const Item& I = items[it];
   DavState& S = st[it];
   if (S.conv) return;
-  double rr = 0.0;
+  double rr = 0.0, tt = 0.0;
   double cf[kMaxSpace];
   for (int i = 0; i < kMaxSpace; ++i) cf[i] = 0.0;
   for (int c = 0; c < I.nchunk; ++c) {
     const double* p = part + (int64_t)(I.chunk0 + c) * kPart;
     rr += p[kMaxSpace];
+    tt += p[kMaxSpace + 1];
     for (int i = 0; i < S.m; ++i) cf[i] += p[i];
   }
-  if (pdots && S.np > 0)  // the P-space correction changed t on the P block
-    for (int i = 0; i < S.m; ++i) cf[i] += pdots[(int64_t)it * kMaxSpace + i];
+  if (pdots && S.np > 0) {  // the P-space correction changed t on the P block
+    const double* pd = pdots + (int64_t)it * (kMaxSpace + 1);
+    for (int i = 0; i < S.m; ++i) cf[i] += pd[i];
+    tt += pd[kMaxSpace];
+  }
   S.rnorm = sqrt(rr);
   for (int i = 0; i < kMaxSpace; ++i) S.coef[i] = cf[i];
+  // one Gram-Schmidt pass suffices when it keeps at least half of |t|^2
+  // (the Daniel-Gragg-Kaufman-Stewart criterion); |t - V c|^2 = |t|^2 - |c|^2
+  double n1 = tt;
+  for (int i = 0; i < S.m; ++i) n1 -= cf[i] * cf[i];
+  S.onepass = (n1 >= 0.5 * tt && n1 > 1e-28) ? 1 : 0;
+  S.tnorm2 = n1;
   if (S.rnorm <= tol || S.m >= I.ndet) {
     S.conv = 1;
   } else if (S.iters >= max_iter) {
@@ -1087,6 +1101,7 @@ __global__ void k_dav_reduce1(const Item* __restrict__ items, const double* __re
 }
 
 // t -= sum_i coef_i V_i ; partial sums of V_i . t and |t|^2 (second pass).
+// Items whose first pass suffices (onepass) are normalised here instead.
 __global__ void __launch_bounds__(256) k_dav_orth(const Item* __restrict__ items,
                                                   const Work* __restrict__ work, double* V,
                                                   int64_t ntot, const DavState* __restrict__ st,
@@ -1099,6 +1114,20 @@ __global__ void __launch_bounds__(256) k_dav_orth(const Item* __restrict__ items
   double cf[kMaxSpace];
 #pragma unroll
   for (int i = 0; i < kMaxSpace; ++i) cf[i] = S.coef[i];
+  if (S.onepass) {
+    const double inv = 1.0 / sqrt(S.tnorm2);
+    const int64_t e0 = (int64_t)(wk.begin - I.chunk0) * kChunk;
+    const int64_t e1 = min(e0 + kChunk, I.ndet);
+    double* t = V + (int64_t)m * ntot + I.off;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+      double tv = t[e];
+#pragma unroll
+      for (int i = 0; i < kMaxSpace; ++i)
+        if (i < m) tv -= cf[i] * V[(int64_t)i * ntot + I.off + e];
+      t[e] = tv * inv;
+    }
+    return;
+  }
   double acc[kMaxSpace + 1];
 #pragma unroll
   for (int i = 0; i <= kMaxSpace; ++i) acc[i] = 0.0;
@@ -1132,7 +1161,7 @@ __global__ void k_dav_reduce2(const Item* __restrict__ items, const double* __re
   it += ibase;
   const Item& I = items[it];
   DavState& S = st[it];
-  if (S.conv) return;
+  if (S.conv || S.onepass) return;
   double tt = 0.0;
   double cf[kMaxSpace];
   for (int i = 0; i < kMaxSpace; ++i) cf[i] = 0.0;
@@ -1158,7 +1187,7 @@ __global__ void __launch_bounds__(256) k_dav_orth2(const Item* __restrict__ item
   const Work wk = work[blockIdx.x];
   const Item& I = items[wk.item];
   const DavState& S = st[wk.item];
-  if (S.conv) return;
+  if (S.conv || S.onepass) return;
   const int m = S.m;
   double cf[kMaxSpace];
 #pragma unroll
@@ -1415,6 +1444,7 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
     if (t == 0) {
       V[I.off] = 1.0;
       S.m = 1; S.nguess = 1; S.np = 0; S.iters = 0; S.status = 0; S.rnorm = 0.0; S.conv = 1;
+      S.onepass = 0;
       S.theta = diag[I.off];
     }
     return;
@@ -1424,6 +1454,7 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
     if (t < 2) V[(int64_t)t * ntot + I.off + idx[t]] = 1.0;
     if (t == 0) {
       S.m = 0; S.nguess = 2; S.np = 0; S.iters = 0; S.status = 0; S.rnorm = 0.0; S.conv = 0;
+      S.onepass = 0;
       S.theta = 0.0;
     }
     return;
@@ -1609,6 +1640,7 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
     S.m = 0;
     S.nguess = two ? 2 : 1;
     S.np = n;
+    S.onepass = 0;
     S.iters = 0;
     S.status = 0;
     S.rnorm = 0.0;
@@ -1619,8 +1651,8 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
 
 // P-space correction, run after k_dav_residual: on the P block replace the
 // diagonal correction by t_P = Q (theta - T)^-1 Q^T r_P = (theta - H_PP)^-1 r_P,
-// and store the change of the Gram-Schmidt dots V_i . t (i < m) in
-// pdots[item] for k_dav_reduce1.
+// and store the change of the Gram-Schmidt dots V_i . t (i < m) and of |t|^2
+// in pdots[item][0..kMaxSpace] for k_dav_reduce1.
 __global__ void __launch_bounds__(256) k_pspace_correct(const Item* __restrict__ items, int ibase,
                                                         const int32_t* __restrict__ pidx,
                                                         const double* __restrict__ pQ,
@@ -1660,9 +1692,9 @@ __global__ void __launch_bounds__(256) k_pspace_correct(const Item* __restrict__
   __syncthreads();
   if (t == 0) tridiag_shift_solve(dd, ee, np, th, z, z, piv, 1e-8);
   __syncthreads();
-  double acc[kMaxSpace];
+  double acc[kMaxSpace + 1];
 #pragma unroll
-  for (int i = 0; i < kMaxSpace; ++i) acc[i] = 0.0;
+  for (int i = 0; i <= kMaxSpace; ++i) acc[i] = 0.0;
   if (t < np) {
     for (int j = 0; j < np; ++j) tnew += Qi[t * PM + j] * z[j];
     V[(int64_t)m * ntot + I.off + e] = tnew;
@@ -1670,8 +1702,9 @@ __global__ void __launch_bounds__(256) k_pspace_correct(const Item* __restrict__
 #pragma unroll
     for (int i = 0; i < kMaxSpace; ++i)
       if (i < m) acc[i] = V[(int64_t)i * ntot + I.off + e] * dl;
+    acc[kMaxSpace] = tnew * tnew - told * told;
   }
-  block_reduce_store<kMaxSpace>(acc, pdots + (int64_t)it * kMaxSpace);
+  block_reduce_store<kMaxSpace + 1>(acc, pdots + (int64_t)it * (kMaxSpace + 1));
 }
 
 // ------------------------------------------------------------------- RDMs

@@ -412,7 +412,7 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
     P.pidx = arena<int32_t>(c, "pidx", (size_t)P.nitem * kMaxPspace, &grown);
     P.pQ = arena<double>(c, "pQ", (size_t)P.nitem * kMaxPspace * kMaxPspace, &grown);
     P.pT = arena<double>(c, "pT", (size_t)P.nitem * 2 * kMaxPspace, &grown);
-    P.pdots = arena<double>(c, "pdots", (size_t)P.nitem * kMaxSpace, &grown);
+    P.pdots = arena<double>(c, "pdots", (size_t)P.nitem * (kMaxSpace + 1), &grown);
   }
   if (c->opts.precond == 1) {
     P.R = arena<double>(c, "resid", P.ntot, &grown);
