@@ -33,24 +33,42 @@ HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E
 FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix
 
 
+def kernel_source_sha(kernel_name):
+    """SHA-256 of the source a kernel is compiled from: its own function text
+    in kernels.hip (the template for sigma_dgemm<...>) plus common.h.  A
+    counter record stays valid while this hash is unchanged."""
+    import hashlib
+    import re
+    here = os.path.dirname(os.path.abspath(__file__))
+    csrc = os.path.join(here, "paper_1910_03527_amd", "csrc")
+    fn = "k_" + kernel_name.split("<")[0]
+    with open(os.path.join(csrc, "kernels.hip")) as fh:
+        text = fh.read()
+    m = re.search(r"\n(template <[^>]*>\n)?__global__ void (__launch_bounds__\([^)]*\) )?" +
+                  re.escape(fn) + r"\(", text)
+    if not m:
+        return None
+    end = text.index("\n}\n", m.start()) + 3
+    with open(os.path.join(csrc, "common.h")) as fh:
+        common = fh.read()
+    return hashlib.sha256((text[m.start():end] + common).encode()).hexdigest()
+
+
 def _traffic(kernel_name, workload):
     """HBM bytes per launch of `kernel_name` from the committed rocprofv3
-    counter record, or None when the record is missing or the kernel source
+    counter record, or None when the record is missing or the kernel's source
     changed since the counters were taken."""
-    import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     rec = os.path.join(here, "profiles", "traffic.json")
-    src = os.path.join(here, "paper_1910_03527_amd", "csrc", "kernels.hip")
     try:
         with open(rec) as fh:
             data = json.load(fh)
-        with open(src, "rb") as fh:
-            sha = hashlib.sha256(fh.read()).hexdigest()
     except OSError:
         return None
+    sha = kernel_source_sha(kernel_name)
     for r in data.get("records", []):
         if r.get("kernel") == kernel_name and r.get("workload") == workload and \
-                r.get("kernels_hip_sha256") == sha:
+                sha is not None and r.get("kernel_source_sha256") == sha:
             return r["hbm_bytes_per_launch"]
     return None
 
