@@ -60,7 +60,10 @@ typedef struct {
   double conv_tol;       /* Davidson residual 2-norm tolerance (default 1e-6)       */
   int32_t max_iter;      /* Davidson iterations per CASCI (default 200)              */
   int32_t max_space;     /* subspace size before restart, 2..16 (default 16)        */
-  int32_t nguess;        /* lowest-diagonal unit guess vectors, 1..8 (default 2)    */
+  int32_t nguess;        /* lowest-diagonal unit guess vectors, 1..8, below
+                            max_space - 1 (default 2); every solve also starts
+                            from one dense vector with weight in every symmetry
+                            sector, orthogonalised against the others          */
   int32_t mode;          /* MBEFCI_BATCHED (default) or MBEFCI_PER_LAUNCH            */
   int32_t use_graph;     /* batched mode: replay captured iterations (default 1)     */
   int32_t tile;          /* sigma tile width 32/64/128; 0 = autotuned schedule: the
@@ -75,12 +78,15 @@ typedef struct {
   int32_t precond;       /* Davidson correction: 0 = diagonal (theta - H_II)^-1 r,
                             1 = Olsen-corrected, orthogonal to the Ritz vector
                             (default 0)                                          */
-  int32_t pspace;        /* P-space size 0..112: the determinants of lowest diagonal
-                            energy whose block H_PP is diagonalised once per CASCI;
-                            it gives the guess and, on that block, the exact
-                            (theta - H_PP)^-1 correction; 0 = unit-vector guesses
-                            (nguess of them) and the diagonal correction only;
-                            ignored with precond = 1 (default 112)              */
+  int32_t pspace;        /* P-space size 0..112 for CASCIs of more than 112
+                            determinants: the determinants of lowest diagonal
+                            energy whose block H_PP is diagonalised once per
+                            CASCI; it gives the guess and, on that block, the
+                            exact (theta - H_PP)^-1 correction; 0 = unit-vector
+                            guesses and the diagonal correction only.  CASCIs
+                            of at most 112 determinants are always solved from
+                            their whole-space block.  Ignored with precond = 1
+                            (default 112)                                     */
   int32_t pad0_;
   int64_t max_workspace; /* workspace cap in bytes, 0 = no cap                       */
   const char* tune_cache;/* autotuner cache file (read/written) or NULL: one line per
@@ -186,6 +192,39 @@ int mbefci_mbe_forward(mbefci_ctx* ctx, const mbefci_problem* prob, double* e_re
  * (symmetric) and d_eri device [M^4] (8-fold symmetrised); both overwritten. */
 int mbefci_mbe_backward(mbefci_ctx* ctx, const double* grad_out, double* d_h1, double* d_eri,
                         void* hip_stream);
+
+/* ---- screened expansion ---------------------------------------------------
+ * The order-by-order driver of the paper's production runs (the tuple
+ * screening described with Eq. 4).  Order 1 holds every expansion orbital;
+ * a tuple of order k+1 is computed iff one of its order-k sub-tuples S was
+ * computed with |Delta eps_S| > T_tup(S), where (Eq. 4)
+ *   T_tup = 0                                 if M_tup <  m_init,
+ *   T_tup = t_init * a^(M_tup - m_init)       otherwise,
+ * and M_tup = max(occupied MOs, virtual MOs) of S.  With an empty reference
+ * space (Eq. 3) tuples of only occupied or only virtual MOs have vanishing
+ * increments by construction: they are not computed, and every mixed pair is
+ * (order 2 is the first order).  Increments follow Eq. 2 over the computed
+ * sub-tuples (a sub-tuple never computed contributes 0).  Outputs (host):
+ * e_ref, e_order [max_order] (0 for orders with no tuple), e_total,
+ * n_order [max_order] (tuples computed per order).  The computed tuples and
+ * their increments stay on ctx for mbefci_screened_tuples; the call drops the
+ * cached plan of mbefci_mbe_forward (no backward follows a screened call).
+ * Errors: EINVAL for t_init < 0, a < 1, m_init < 0 or a bad problem. */
+typedef struct {
+  double t_init;          /* T_init in E_h (the paper: 1e-10)                         */
+  double a;               /* relaxation factor a >= 1 (the paper: 5.0, or 2.5)        */
+  int32_t m_init;         /* M_init (the paper: 3)                                    */
+  int32_t pad_;
+} mbefci_screen;
+int mbefci_mbe_screened(mbefci_ctx* ctx, const mbefci_problem* prob, const mbefci_screen* scr,
+                        double* e_ref, double* e_order, double* e_total, int64_t* n_order,
+                        mbefci_stats* stats, void* hip_stream);
+/* The tuples computed at `order` (1..max_order) by the last screened call on
+ * ctx, in lexicographic order of the sorted orbital lists: tuples host
+ * [count][order] orbital indices (or NULL), increments host [count] Delta eps
+ * (or NULL).  Returns count, or a negative error code. */
+int64_t mbefci_screened_tuples(mbefci_ctx* ctx, int32_t order, int32_t* tuples,
+                               double* increments);
 
 /* ---- measurement ----------------------------------------------------------
  * Re-times the sigma = Hc kernels of the last mbefci_casci / mbefci_mbe_forward

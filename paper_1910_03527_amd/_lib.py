@@ -22,7 +22,8 @@ EXPORTS = (
     "mbefci_default_opts", "mbefci_create", "mbefci_destroy", "mbefci_last_error",
     "mbefci_set_opts", "mbefci_num_strings", "mbefci_num_links", "mbefci_strings",
     "mbefci_link_table", "mbefci_num_tuples", "mbefci_hdiag", "mbefci_sigma", "mbefci_casci",
-    "mbefci_casci_rdm", "mbefci_mbe_forward", "mbefci_mbe_backward", "mbefci_time_kernels",
+    "mbefci_casci_rdm", "mbefci_mbe_forward", "mbefci_mbe_backward", "mbefci_mbe_screened",
+    "mbefci_screened_tuples", "mbefci_time_kernels",
 )
 
 
@@ -59,6 +60,15 @@ class Problem(ctypes.Structure):
         ("nexp", ctypes.c_int32),
         ("exp", ctypes.POINTER(ctypes.c_int32)),
         ("max_order", ctypes.c_int32),
+    ]
+
+
+class Screen(ctypes.Structure):
+    _fields_ = [
+        ("t_init", ctypes.c_double),
+        ("a", ctypes.c_double),
+        ("m_init", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
     ]
 
 
@@ -147,6 +157,13 @@ def load():
     L.mbefci_mbe_forward.restype = ctypes.c_int
     L.mbefci_mbe_backward.argtypes = [vp, ctypes.POINTER(dbl), vp, vp, vp]
     L.mbefci_mbe_backward.restype = ctypes.c_int
+    L.mbefci_mbe_screened.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(Screen),
+                                      ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                      ctypes.POINTER(dbl), ctypes.POINTER(i64),
+                                      ctypes.POINTER(Stats), vp]
+    L.mbefci_mbe_screened.restype = ctypes.c_int
+    L.mbefci_screened_tuples.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+    L.mbefci_screened_tuples.restype = i64
     L.mbefci_time_kernels.argtypes = [vp, i32, ctypes.POINTER(KernelTime), i32,
                                       ctypes.POINTER(i32)]
     L.mbefci_time_kernels.restype = ctypes.c_int

@@ -4,6 +4,7 @@ from __future__ import annotations
 import ctypes
 import math
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -216,6 +217,45 @@ class Context:
         if want_increments:
             out["increments"] = list(inc)[:nt]
             out["energies"] = list(fen)[:nt]
+        return out
+
+    def mbe_screened(self, h1, eri, occ, ref, exp, max_order: int, t_init: float = 1e-10,
+                     m_init: int = 3, a: float = 5.0, e_const: float = 0.0,
+                     want_tuples: bool = False):
+        """Screened order-by-order expansion (mbefci_mbe_screened).  Returns
+        dict(e_ref, e_order [k], e_total, n_order [k]) and, with want_tuples,
+        per_order: list over orders of (tuples int32 [n][order], increments)."""
+        M = h1.shape[0]
+        _dev_f64(h1, (M, M), "h1")
+        _dev_f64(eri, (M, M, M, M), "eri")
+        occ_a, ref_a, exp_a = _i32(occ), _i32(ref), _i32(exp)
+        pb = _lib.Problem(M, h1.data_ptr(), eri.data_ptr(), float(e_const), len(occ), occ_a,
+                          len(ref), ref_a, len(exp), exp_a, int(max_order))
+        sc = _lib.Screen(float(t_init), float(a), int(m_init), 0)
+        e_ref = ctypes.c_double()
+        e_tot = ctypes.c_double()
+        e_ord = (ctypes.c_double * max(1, max_order))()
+        n_ord = (ctypes.c_int64 * max(1, max_order))()
+        st = _lib.Stats()
+        self._check(self._L.mbefci_mbe_screened(self._h, ctypes.byref(pb), ctypes.byref(sc),
+                                                ctypes.byref(e_ref), e_ord, ctypes.byref(e_tot),
+                                                n_ord, ctypes.byref(st), self._stream()))
+        self.last_stats = st.as_dict()
+        self._fwd = None
+        out = {"e_ref": e_ref.value, "e_order": list(e_ord)[:max_order], "e_total": e_tot.value,
+               "n_order": list(n_ord)[:max_order]}
+        if want_tuples:
+            per = []
+            for k in range(1, max_order + 1):
+                n = int(n_ord[k - 1])
+                tu = (ctypes.c_int32 * max(1, n * k))()
+                inc = (ctypes.c_double * max(1, n))()
+                got = self._L.mbefci_screened_tuples(self._h, k, tu, inc)
+                if got < 0:
+                    self._check(int(got))
+                arr = np.frombuffer(tu, dtype=np.int32, count=n * k).reshape(n, k).copy()
+                per.append((arr, list(inc)[:n]))
+            out["per_order"] = per
         return out
 
     def time_kernels(self, reps: int = 5):

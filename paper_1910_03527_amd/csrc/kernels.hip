@@ -652,8 +652,19 @@ __global__ void k_fill(double* p, int64_t n, double v) {
   for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
+// Dense guess vector: r_K = +-1/sqrt(ndet) with the sign taken from the top
+// bit of a multiplicative hash of the address K.  It has no symmetry, so it
+// carries weight in every spin and spatial symmetry sector of the
+// determinant basis: with it in the first subspace the solver cannot be
+// confined to a sector without the ground state (a closed-shell determinant,
+// for example, is a pure singlet and never reaches a triplet ground state).
+__device__ inline double hash_sign(int64_t K) {
+  return (((uint64_t)K * 0x9E3779B97F4A7C15ull) >> 63) ? 1.0 : -1.0;
+}
+
 // Guess: the `nguess` lowest diagonal determinants (ties: lower address) as
-// unit vectors in slots 0..g-1.  One block per item.
+// unit vectors in slots 0..g-1, and the dense vector orthogonalised against
+// them in slot g.  One block per item.
 __global__ void k_dav_guess(const Item* __restrict__ items, int ibase,
                             const double* __restrict__ diag, double* V, int64_t ntot, DavState* st,
                             int nguess) {
@@ -682,6 +693,7 @@ __global__ void k_dav_guess(const Item* __restrict__ items, int ibase,
   __shared__ int rth[256];
   int g = nguess < G ? nguess : G;
   if (g > I.ndet) g = (int)I.ndet;
+  __shared__ int64_t chosen[G];
   int head = 0;
   for (int k = 0; k < g; ++k) {
     rv[t] = head < G ? bv[head] : 1e300;
@@ -701,12 +713,26 @@ __global__ void k_dav_guess(const Item* __restrict__ items, int ibase,
       __syncthreads();
     }
     if (t == rth[0]) ++head;
-    if (t == 0) V[(int64_t)k * ntot + I.off + ri[0]] = 1.0;
+    if (t == 0) {
+      V[(int64_t)k * ntot + I.off + ri[0]] = 1.0;
+      chosen[k] = ri[0];
+    }
     __syncthreads();
+  }
+  // dense vector minus its components on the chosen unit vectors
+  const bool dense = I.ndet > g;
+  if (dense) {
+    const double sc = 1.0 / sqrt((double)(I.ndet - g));
+    double* __restrict__ vr = V + (int64_t)g * ntot + I.off;
+    for (int64_t K = t; K < I.ndet; K += blockDim.x) {
+      bool hit = false;
+      for (int j = 0; j < g; ++j) hit |= chosen[j] == K;
+      vr[K] = hit ? 0.0 : hash_sign(K) * sc;
+    }
   }
   if (t == 0) {
     S.m = 0;
-    S.nguess = g;
+    S.nguess = g + (dense ? 1 : 0);
     S.np = 0;
     S.onepass = 0;
     S.iters = 0;
@@ -1242,7 +1268,9 @@ __global__ void __launch_bounds__(256) k_pspace_select(const Item* __restrict__ 
   const int it = ibase + blockIdx.x;
   const Item& I = items[it];
   const int64_t nd = I.ndet;
-  const int np = (int)(nd < pmax ? nd : pmax);
+  // small CASCIs: every determinant; larger ones: pmax (at least the two
+  // lowest, used as unit guesses when the P-space is not used)
+  const int np = nd <= kMaxPspace ? (int)nd : (pmax > 2 ? pmax : 2);
   const double* __restrict__ d = diag + I.off;
   const int t = threadIdx.x;
   __shared__ uint32_t hist[256];
@@ -1375,11 +1403,12 @@ __device__ double sc_offdiag(const ItemHam& H, uint64_t ia, uint64_t ib, uint64_
 // H_PP = Q T Q^T (T: diagonal d, off-diagonal e; Q accumulated explicitly).
 // The lowest eigenvalue of T comes from multisection on Sturm counts (every
 // thread evaluates one point per round), its eigenvector from inverse
-// iteration; the guess is Q z.  The P-space is used when it holds the whole
-// CASCI (ndet <= pmax: the guess is then the exact ground state) or when the
-// CASCI is large enough for the reduction to pay off (ndet >=
-// kPspaceMinRatio * pmax); other CASCIs get the two lowest-diagonal unit
-// vectors and the diagonal correction.
+// iteration; the guess is Q z.  A CASCI of at most kMaxPspace determinants
+// is always solved from its whole-space block (the guess is then the exact
+// ground state, whatever pmax); larger ones use a P-space of pmax
+// determinants when they are large enough for the reduction to pay off
+// (ndet >= kPspaceMinRatio * pmax), else the two lowest-diagonal unit
+// vectors and the diagonal correction.  The dense vector is always added.
 constexpr int kPspaceMinRatio = 32;
 constexpr int kPspaceThreads = 512;
 
@@ -1449,11 +1478,16 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
     }
     return;
   }
-  if (nd > pmax && nd < (int64_t)kPspaceMinRatio * pmax) {
-    // unit vectors on the two lowest diagonal determinants (idx is sorted)
+  if (nd > kMaxPspace && (pmax == 0 || nd < (int64_t)kPspaceMinRatio * pmax)) {
+    // unit vectors on the two lowest diagonal determinants (idx is sorted),
+    // the dense vector without those two components in slot 2
+    const int i0 = idx[0], i1 = idx[1];
+    const double sc = 1.0 / sqrt((double)(nd - 2));
+    double* __restrict__ vr = V + 2 * ntot + I.off;
+    for (int64_t K = t; K < nd; K += NT) vr[K] = (K == i0 || K == i1) ? 0.0 : hash_sign(K) * sc;
     if (t < 2) V[(int64_t)t * ntot + I.off + idx[t]] = 1.0;
     if (t == 0) {
-      S.m = 0; S.nguess = 2; S.np = 0; S.iters = 0; S.status = 0; S.rnorm = 0.0; S.conv = 0;
+      S.m = 0; S.nguess = 3; S.np = 0; S.iters = 0; S.status = 0; S.rnorm = 0.0; S.conv = 0;
       S.onepass = 0;
       S.theta = 0.0;
     }
@@ -1471,7 +1505,7 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
     for (int w = 0; w < NT / 64; ++w) s += red[w];
     return s;
   };
-  const int n = (int)(nd < pmax ? nd : pmax);
+  const int n = nd <= kMaxPspace ? (int)nd : pmax;
   const ItemHam& H = hams[I.ham];
   for (int k = t; k < n; k += NT) {
     const int e = idx[k];  // an address of this item: 0 <= e < ndet
@@ -1636,9 +1670,36 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
     v0[e] = vv[k];
     if (two) v1[e] = ((k == 0 ? 1.0 : 0.0) - u0 * vv[k]) * inv;
   }
+  // dense vector r = sign/sqrt(ndet) minus its components on the guesses
+  // above (both live on the P block): r - c0 u - c1 e', |.|^2 = 1 - c0^2 - c1^2
+  const int slot_r = two ? 2 : 1;
+  if (t == 0) {
+    const double rs = 1.0 / sqrt((double)nd);
+    double c0 = 0.0, c1 = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const double rk = hash_sign(idx[k]) * rs;
+      c0 += vv[k] * rk;
+      if (two) c1 += ((k == 0 ? 1.0 : 0.0) - u0 * vv[k]) * inv * rk;
+    }
+    zz[0] = c0;
+    zz[1] = c1;
+    zz[2] = 1.0 - c0 * c0 - c1 * c1;
+  }
+  __syncthreads();
+  const bool dense = nd > n && zz[2] > 1e-6;
+  if (dense) {
+    const double rs = 1.0 / sqrt((double)nd), rn = 1.0 / sqrt(zz[2]);
+    double* __restrict__ vr = V + (int64_t)slot_r * ntot + I.off;
+    for (int64_t K = t; K < nd; K += NT) vr[K] = hash_sign(K) * rs * rn;
+    __syncthreads();   // the P-block entries below overwrite the dense pass
+    for (int k = t; k < n; k += NT) {
+      const double ek = two ? ((k == 0 ? 1.0 : 0.0) - u0 * vv[k]) * inv : 0.0;
+      vr[idx[k]] = (hash_sign(idx[k]) * rs - zz[0] * vv[k] - zz[1] * ek) * rn;
+    }
+  }
   if (t == 0) {
     S.m = 0;
-    S.nguess = two ? 2 : 1;
+    S.nguess = (two ? 2 : 1) + (dense ? 1 : 0);
     S.np = n;
     S.onepass = 0;
     S.iters = 0;
@@ -2172,6 +2233,87 @@ __global__ void k_mbe_total(const double* f, const double* e_order, int k, doubl
   }
 }
 
+// ------------------------------------------------------- screened expansion
+// Set-up from explicit tuples: item i holds the tuple with orbital mask
+// masks[i] (bit p = expansion orbital p of the problem; 0 = the reference
+// CASCI of R alone).  A = R u T, F = O \ A frozen, the rest deleted.
+__global__ void k_mbe_setup_list(MbeSpaces sp, const uint64_t* __restrict__ masks,
+                                 const Item* __restrict__ items, const double* __restrict__ h1,
+                                 const double* __restrict__ eri, double e_const, ItemHam* hams,
+                                 double* warena) {
+  const int it = blockIdx.x;
+  __shared__ ActiveSet s;
+  if (threadIdx.x == 0) {
+    const uint64_t m = masks[it];
+    uint64_t a = m;
+    for (int i = 0; i < sp.nR; ++i) a |= (uint64_t)1 << sp.R[i];
+    int nt = 0;
+    for (uint64_t x = a; x; x &= x - 1) s.act[nt++] = __builtin_ctzll(x);  // ascending
+    s.n = nt;
+    s.nf = 0;
+    int na = 0;
+    for (int i = 0; i < sp.nO; ++i) {
+      const int o = sp.O[i];
+      if (a >> o & 1) ++na;
+      else s.frz[s.nf++] = o;
+    }
+    s.na = na;
+  }
+  __syncthreads();
+  const Item& I = items[it];
+  build_item_hamiltonian(s, sp.M, h1, eri, e_const, I.na + I.nb, &hams[I.ham],
+                         I.ndet > 1 ? warena + I.woff : nullptr, I.kpad);
+}
+
+// Computed tuples of the lower orders, each order's masks in ascending
+// numeric order with their increments.
+struct ScreenLevels {
+  const uint64_t* mask[kMaxActive + 1];
+  const double* inc[kMaxActive + 1];
+  int64_t n[kMaxActive + 1];
+};
+
+// Eq. 2 over the computed sub-tuples: for tuple i of order k,
+// Delta eps = (f_i - E_ref) - sum over its proper non-empty sub-tuples U that
+// were computed of Delta eps_U (binary search in U's order; sub-tuples in
+// ascending subset order, so the sum has a fixed order).
+__global__ void k_screen_increments(const uint64_t* __restrict__ masks, int64_t n, int k,
+                                    const double* __restrict__ f, const double* __restrict__ e_ref,
+                                    ScreenLevels lv, double* __restrict__ inc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t m = masks[i];
+  int bit[kMaxActive];
+  int nb = 0;
+  for (uint64_t x = m; x; x &= x - 1) bit[nb++] = __builtin_ctzll(x);
+  double d = f[i] - e_ref[0];
+  const uint32_t full = (1u << k) - 1u;
+  for (uint32_t sub = 1; sub < full; ++sub) {
+    uint64_t u = 0;
+    for (int b = 0; b < k; ++b)
+      if (sub >> b & 1) u |= (uint64_t)1 << bit[b];
+    const int o = __builtin_popcount(sub);
+    const uint64_t* __restrict__ arr = lv.mask[o];
+    int64_t lo = 0, hi = lv.n[o];
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (arr[mid] < u) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < lv.n[o] && arr[lo] == u) d -= lv.inc[o][lo];
+  }
+  inc[i] = d;
+}
+
+// E^(k) = sum of the order-k increments, in index order (one thread).
+__global__ void k_screen_order_sum(const double* __restrict__ inc, int64_t n, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double e = 0.0;
+    for (int64_t i = 0; i < n; ++i) e += inc[i];
+    out[0] = e;
+  }
+}
+
 // ================================================================ launchers
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
@@ -2419,5 +2561,25 @@ void launch_casci_rdm_out(const Item* items, int it, int n, const double* rdmp,
   int b = nblk(n4, 256);
   if (b > 4096) b = 4096;
   hipLaunchKernelGGL(k_casci_rdm_out, dim3(b), dim3(256), 0, s, items, it, rdmp, roff, rdm1, rdm2);
+}
+void launch_mbe_setup_list(const MbeSpaces* sp, const uint64_t* masks, const Item* items, int nitem,
+                           const double* h1, const double* eri, double e_const, ItemHam* hams,
+                           double* warena, hipStream_t s) {
+  hipLaunchKernelGGL(k_mbe_setup_list, dim3(nitem), dim3(256), 0, s, *sp, masks, items, h1, eri,
+                     e_const, hams, warena);
+}
+void launch_screen_increments(const uint64_t* masks, int64_t n, int k, const double* f,
+                              const double* e_ref, const ScreenArrays& lower, double* inc,
+                              double* order_sum, hipStream_t s) {
+  ScreenLevels lv{};
+  for (int o = 0; o <= kMaxActive; ++o) {
+    lv.mask[o] = lower.mask[o];
+    lv.inc[o] = lower.inc[o];
+    lv.n[o] = lower.n[o];
+  }
+  if (n > 0)
+    hipLaunchKernelGGL(k_screen_increments, dim3(nblk(n, 128)), dim3(128), 0, s, masks, n, k, f,
+                       e_ref, lv, inc);
+  hipLaunchKernelGGL(k_screen_order_sum, dim3(1), dim3(64), 0, s, inc, n, order_sum);
 }
 }  // namespace mbefci

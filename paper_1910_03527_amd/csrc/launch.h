@@ -88,4 +88,17 @@ void launch_casci_rdm_out(const Item* items, int it, int n, const double* rdmp,
 constexpr int kChunkElems = 4096;   // elements per Davidson reduction chunk
 constexpr int kPartStride = kMaxSpace + 2;
 
+// screened expansion: the computed tuples of every order (masks ascending)
+struct ScreenArrays {
+  const uint64_t* mask[kMaxActive + 1];
+  const double* inc[kMaxActive + 1];
+  int64_t n[kMaxActive + 1];
+};
+void launch_mbe_setup_list(const MbeSpaces* sp, const uint64_t* masks, const Item* items, int nitem,
+                           const double* h1, const double* eri, double e_const, ItemHam* hams,
+                           double* warena, hipStream_t s);
+void launch_screen_increments(const uint64_t* masks, int64_t n, int k, const double* f,
+                              const double* e_ref, const ScreenArrays& lower, double* inc,
+                              double* order_sum, hipStream_t s);
 }  // namespace mbefci
+

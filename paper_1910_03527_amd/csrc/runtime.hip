@@ -141,6 +141,10 @@ struct mbefci_ctx {
   double ms_tune = 0.0;
   bool have_forward = false;
   std::vector<double> host_scratch;
+  // last screened expansion: computed tuples (masks, ascending) and their
+  // increments, per order
+  std::vector<std::vector<uint64_t>> scr_masks;
+  std::vector<std::vector<double>> scr_inc;
 };
 
 namespace {
@@ -304,7 +308,9 @@ int64_t build_passes(mbefci_ctx* c, Plan& P) {
 
 // items must have n, na, nb filled; computes every derived field, work lists
 // and allocates the arenas.
-bool use_pspace(const mbefci_ctx* c) { return c->opts.pspace > 0 && c->opts.precond == 0; }
+// The P-space machinery also solves every CASCI of at most kMaxPspace
+// determinants exactly, so it runs whenever the diagonal correction is used.
+bool use_pspace(const mbefci_ctx* c) { return c->opts.precond == 0; }
 
 void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
   const int mmax = c->opts.max_space;
@@ -602,9 +608,10 @@ void solve_view(mbefci_ctx* c, Plan& P, const View& v, int* graph_launches) {
   if (P.pidx) {
     launch_pspace_setup(P.d_items, v.ibase, v.nitem, P.hams, P.diag, P.pidx, P.pQ, P.pT, P.V,
                         P.ntot, P.st, c->opts.pspace, c->stream);
-    g = 2;  // the P-space eigenvector and the orthogonalised lowest-diagonal vector
+    g = 3;  // P-space eigenvector, orthogonalised lowest-diagonal vector, dense vector
   } else {
     launch_dav_guess(P.d_items, v.ibase, v.nitem, P.diag, P.V, P.ntot, P.st, g, c->stream);
+    g += 1;  // the dense vector
   }
   if (v.item < 0) autotune(c, P);
   for (int j = 0; j < g; ++j) add_vector(c, P, v, j);
@@ -655,7 +662,7 @@ void solve_view(mbefci_ctx* c, Plan& P, const View& v, int* graph_launches) {
 }
 
 void solve_plan(mbefci_ctx* c, Plan& P, mbefci_stats* stats) {
-  const int g = P.pidx ? 2 : std::max(1, std::min(c->opts.nguess, 8));
+  const int g = P.pidx ? 3 : std::max(1, std::min(c->opts.nguess, 8)) + 1;
   HIPCHK(hipEventRecord(c->t0, c->stream));
   launch_hdiag(P.d_items, P.d_blocks, P.nblock, P.hams, P.diag, c->stream);
   launch_fill(P.V, (int64_t)g * P.ntot, 0.0, c->stream);
@@ -748,6 +755,55 @@ struct StreamScope {  // order the library stream after the caller's and back
     HIPCHK(hipStreamWaitEvent(user, c->ev_out, 0));
   }
 };
+
+// Host checks of an expansion problem; role[o] = 1 for R, 2 for X; occ[o] = 1
+// for the occupied orbitals of the reference determinant.
+void parse_problem(const mbefci_problem* pb, std::vector<int>& role, std::vector<int>& occ) {
+  const int M = pb->norb;
+  if (M < 1 || M > kMaxOrb) throw Error(MBEFCI_EINVAL, "norb must be in 1..64");
+  if (!pb->h1 || !pb->eri) throw Error(MBEFCI_EINVAL, "null integrals");
+  if (pb->nocc < 0 || pb->nref < 0 || pb->nexp < 0 || pb->nocc > M || pb->nref > M ||
+      pb->nexp > M)
+    throw Error(MBEFCI_EINVAL, "orbital-set sizes out of range");
+  if (pb->max_order < 0 || pb->max_order > pb->nexp)
+    throw Error(MBEFCI_EINVAL, "max_order must be in 0..nexp");
+  role.assign(M, 0);
+  occ.assign(M, 0);
+  for (int i = 0; i < pb->nocc; ++i) {
+    int o = pb->occ[i];
+    if (o < 0 || o >= M || occ[o]) throw Error(MBEFCI_EINVAL, "bad occupied orbital list");
+    occ[o] = 1;
+  }
+  for (int i = 0; i < pb->nref; ++i) {
+    int o = pb->ref[i];
+    if (o < 0 || o >= M || role[o]) throw Error(MBEFCI_EINVAL, "bad reference space");
+    role[o] = 1;
+  }
+  for (int i = 0; i < pb->nexp; ++i) {
+    int o = pb->exp[i];
+    if (o < 0 || o >= M || role[o])
+      throw Error(MBEFCI_EINVAL, "expansion space must be distinct and disjoint from R");
+    role[o] = 2;
+  }
+  if (pb->nref + pb->max_order > 14)
+    throw Error(MBEFCI_EUNSUPPORTED, "|R| + max_order exceeds the compiled 14 active orbitals");
+}
+
+MbeSpaces make_spaces(int M, const std::vector<int>& role, const std::vector<int>& occ) {
+  MbeSpaces sp;
+  std::memset(&sp, 0, sizeof(sp));
+  sp.M = M;
+  for (int o = 0; o < M; ++o) {
+    if (role[o] == 1) sp.R[sp.nR++] = o;
+    if (role[o] == 2) {
+      if (occ[o]) sp.Xo[sp.nXo++] = o;
+      else sp.Xv[sp.nXv++] = o;
+    }
+    if (occ[o]) sp.O[sp.nO++] = o;
+    if (role[o] == 1 && occ[o]) ++sp.nocc_ref;
+  }
+  return sp;
+}
 
 template <class F>
 int guarded(mbefci_ctx* c, F&& f) {
@@ -896,7 +952,7 @@ static int check_opts(const mbefci_opts* o, std::string* why) {
   if (!(o->conv_tol > 0)) { *why = "conv_tol must be positive"; return MBEFCI_EINVAL; }
   if (o->max_iter < 1) { *why = "max_iter must be >= 1"; return MBEFCI_EINVAL; }
   if (o->max_space < 2 || o->max_space > kMaxSpace) { *why = "max_space must be in 2..16"; return MBEFCI_EINVAL; }
-  if (o->nguess < 1 || o->nguess > 8 || o->nguess >= o->max_space) { *why = "nguess must be in 1..8 and below max_space"; return MBEFCI_EINVAL; }
+  if (o->nguess < 1 || o->nguess > 8 || o->nguess + 1 >= o->max_space) { *why = "nguess must be in 1..8 and below max_space - 1"; return MBEFCI_EINVAL; }
   if (o->mode != MBEFCI_BATCHED && o->mode != MBEFCI_PER_LAUNCH) { *why = "unknown mode"; return MBEFCI_EINVAL; }
   if (o->tile != 0 && o->tile != 32 && o->tile != 64 && o->tile != 128) { *why = "tile must be 0, 32, 64 or 128"; return MBEFCI_EINVAL; }
   if (o->sigma_pass_mb < 0) { *why = "sigma_pass_mb must be >= 0"; return MBEFCI_EINVAL; }
@@ -1117,32 +1173,8 @@ int mbefci_mbe_forward(mbefci_ctx* c, const mbefci_problem* pb, double* e_ref, d
     if (!pb || !e_ref || !e_total || (pb->max_order > 0 && !e_order))
       throw Error(MBEFCI_EINVAL, "null argument");
     const int M = pb->norb;
-    if (M < 1 || M > kMaxOrb) throw Error(MBEFCI_EINVAL, "norb must be in 1..64");
-    if (!pb->h1 || !pb->eri) throw Error(MBEFCI_EINVAL, "null integrals");
-    if (pb->nocc < 0 || pb->nref < 0 || pb->nexp < 0 || pb->nocc > M || pb->nref > M ||
-        pb->nexp > M)
-      throw Error(MBEFCI_EINVAL, "orbital-set sizes out of range");
-    if (pb->max_order < 0 || pb->max_order > pb->nexp)
-      throw Error(MBEFCI_EINVAL, "max_order must be in 0..nexp");
-    std::vector<int> role(M, 0), occ(M, 0);
-    for (int i = 0; i < pb->nocc; ++i) {
-      int o = pb->occ[i];
-      if (o < 0 || o >= M || occ[o]) throw Error(MBEFCI_EINVAL, "bad occupied orbital list");
-      occ[o] = 1;
-    }
-    for (int i = 0; i < pb->nref; ++i) {
-      int o = pb->ref[i];
-      if (o < 0 || o >= M || role[o]) throw Error(MBEFCI_EINVAL, "bad reference space");
-      role[o] = 1;
-    }
-    for (int i = 0; i < pb->nexp; ++i) {
-      int o = pb->exp[i];
-      if (o < 0 || o >= M || role[o])
-        throw Error(MBEFCI_EINVAL, "expansion space must be distinct and disjoint from R");
-      role[o] = 2;
-    }
-    if (pb->nref + pb->max_order > 14)
-      throw Error(MBEFCI_EUNSUPPORTED, "|R| + max_order exceeds the compiled 14 active orbitals");
+    std::vector<int> role, occ;
+    parse_problem(pb, role, occ);
     StreamScope sc(c, stream);
     check_integrals(c, M, pb->h1, pb->eri);
 
@@ -1272,6 +1304,185 @@ int mbefci_mbe_forward(mbefci_ctx* c, const mbefci_problem* pb, double* e_ref, d
     if (stats) *stats = st;
     sc.done();
   });
+}
+
+int mbefci_mbe_screened(mbefci_ctx* c, const mbefci_problem* pb, const mbefci_screen* scr,
+                        double* e_ref, double* e_order, double* e_total, int64_t* n_order,
+                        mbefci_stats* stats, void* stream) {
+  return guarded(c, [&] {
+    auto t_start = std::chrono::steady_clock::now();
+    if (!pb || !scr || !e_ref || !e_total || (pb->max_order > 0 && (!e_order || !n_order)))
+      throw Error(MBEFCI_EINVAL, "null argument");
+    std::vector<int> role, occ;
+    parse_problem(pb, role, occ);
+    if (!(scr->t_init >= 0.0) || !std::isfinite(scr->t_init) || !(scr->a >= 1.0) ||
+        !std::isfinite(scr->a) || scr->m_init < 0)
+      throw Error(MBEFCI_EINVAL, "screening needs t_init >= 0, a >= 1 and m_init >= 0");
+    const int M = pb->norb, K = pb->max_order;
+    StreamScope sc(c, stream);
+    check_integrals(c, M, pb->h1, pb->eri);
+    // every order gets a plan of its own; the cached expansion plan is dropped
+    if (c->plan && c->plan->graph) HIPCHK(hipGraphExecDestroy(c->plan->graph));
+    c->plan.reset();
+    c->have_forward = false;
+    const MbeSpaces sp = make_spaces(M, role, occ);
+    std::vector<int> xs;
+    uint64_t occx = 0;
+    for (int o = 0; o < M; ++o)
+      if (role[o] == 2) {
+        xs.push_back(o);
+        if (occ[o]) occx |= (uint64_t)1 << o;
+      }
+    const bool vacuum = sp.nR == 0;
+    // Eq. 3: with no reference space, tuples of only occupied or only virtual
+    // MOs have vanishing increments by construction; they are not computed
+    auto structural = [&](uint64_t m) {
+      if (!vacuum) return false;
+      const int o = __builtin_popcountll(m & occx);
+      return o == 0 || o == __builtin_popcountll(m);
+    };
+    // Eq. 4
+    auto threshold = [&](uint64_t m) {
+      const int o = __builtin_popcountll(m & occx), v = __builtin_popcountll(m) - o;
+      const int mt = std::max(o, v);
+      return mt < scr->m_init ? 0.0 : scr->t_init * std::pow(scr->a, (double)(mt - scr->m_init));
+    };
+    c->scr_masks.assign(K + 1, {});
+    c->scr_inc.assign(K + 1, {});
+    for (int k = 0; k < K; ++k) n_order[k] = 0;
+    ScreenArrays lower{};
+    double* d_eref = arena<double>(c, "scr_eref", 1);
+    double* d_eord = arena<double>(c, "scr_eord", std::max(K, 1));
+    double* d_tot = arena<double>(c, "scr_tot", 2);
+    launch_fill(d_eord, std::max(K, 1), 0.0, c->stream);
+    // first level: order 1, or with no reference space the mixed pairs
+    int k = 1;
+    std::vector<uint64_t> level;
+    for (int p : xs)
+      if (!structural((uint64_t)1 << p)) level.push_back((uint64_t)1 << p);
+    if (level.empty() && vacuum) {
+      k = 2;
+      for (size_t i = 0; i < xs.size(); ++i)
+        for (size_t j = i + 1; j < xs.size(); ++j) {
+          const uint64_t m = ((uint64_t)1 << xs[i]) | ((uint64_t)1 << xs[j]);
+          if (!structural(m)) level.push_back(m);
+        }
+    }
+    mbefci_stats tot{};
+    tot.first_failed = -1;
+    bool first = true;
+    for (;;) {
+      const bool run = k <= K && !level.empty();
+      if (!run && !first) break;
+      std::sort(level.begin(), level.end());
+      level.erase(std::unique(level.begin(), level.end()), level.end());
+      std::vector<uint64_t> masks;
+      if (first) masks.push_back(0);  // the reference CASCI (E_ref)
+      if (run) masks.insert(masks.end(), level.begin(), level.end());
+      if (c->plan && c->plan->graph) HIPCHK(hipGraphExecDestroy(c->plan->graph));
+      c->plan.reset(new Plan());
+      Plan& P = *c->plan;
+      P.norb = M;
+      P.sp = sp;
+      for (uint64_t m : masks) {
+        Item I{};
+        I.n = sp.nR + __builtin_popcountll(m);
+        I.na = I.nb = sp.nocc_ref + __builtin_popcountll(m & occx);
+        P.items.push_back(I);
+      }
+      finalize_plan(c, P, c->opts.nguess);
+      uint64_t* d_masks = arena<uint64_t>(c, "scr_items", masks.size());
+      upload(c, d_masks, masks);
+      launch_mbe_setup_list(&P.sp, d_masks, P.d_items, P.nitem, pb->h1, pb->eri, pb->e_const,
+                            P.hams, P.W, c->stream);
+      HIPCHK(hipGetLastError());
+      mbefci_stats st{};
+      solve_plan(c, P, &st);
+      tot.ntuples += st.ntuples - (first ? 1 : 0);
+      tot.nsingle += st.nsingle;
+      tot.sigma_calls += st.sigma_calls;
+      tot.ndet_total += st.ndet_total;
+      tot.max_iters = std::max(tot.max_iters, st.max_iters);
+      tot.nbuckets += st.nbuckets;
+      tot.graph_launches += st.graph_launches;
+      tot.ms_solve += st.ms_solve;
+      launch_item_energy(P.d_items, P.hams, P.st, P.nitem, P.f, c->stream);
+      if (first) {
+        HIPCHK(hipMemcpyAsync(d_eref, P.f, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        first = false;
+      }
+      if (!run) break;
+      const int off = masks[0] == 0 ? 1 : 0;
+      const int64_t n = (int64_t)level.size();
+      uint64_t* dm = arena<uint64_t>(c, "scr_mask" + std::to_string(k), n);
+      double* di = arena<double>(c, "scr_inc" + std::to_string(k), n);
+      upload(c, dm, level);
+      launch_screen_increments(dm, n, k, P.f + off, d_eref, lower, di, d_eord + (k - 1),
+                               c->stream);
+      HIPCHK(hipGetLastError());
+      lower.mask[k] = dm;
+      lower.inc[k] = di;
+      lower.n[k] = n;
+      std::vector<double> inc(n);
+      HIPCHK(hipMemcpyAsync(inc.data(), di, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      n_order[k - 1] = n;
+      c->scr_masks[k] = level;
+      c->scr_inc[k] = inc;
+      if (k == K) break;
+      // spawn order k+1: children of every tuple whose increment exceeds its
+      // threshold
+      std::vector<uint64_t> next;
+      for (int64_t i = 0; i < n; ++i) {
+        if (!(std::fabs(inc[i]) > threshold(level[i]))) continue;
+        for (int p : xs) {
+          if (level[i] >> p & 1) continue;
+          const uint64_t child = level[i] | ((uint64_t)1 << p);
+          if (!structural(child)) next.push_back(child);
+        }
+      }
+      level.swap(next);
+      ++k;
+    }
+    launch_mbe_total(d_eref, d_eord, K, d_tot, c->stream);
+    double tt[2];
+    std::vector<double> eo(std::max(K, 1));
+    HIPCHK(hipMemcpyAsync(tt, d_tot, 16, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(eo.data(), d_eord, eo.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *e_ref = tt[0];
+    *e_total = tt[1];
+    for (int i = 0; i < K; ++i) e_order[i] = eo[i];
+    tot.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                             t_start).count();
+    tot.ms_tune = c->ms_tune;
+    if (stats) *stats = tot;
+    sc.done();
+  });
+}
+
+int64_t mbefci_screened_tuples(mbefci_ctx* c, int32_t order, int32_t* tuples,
+                               double* increments) {
+  if (!c) return MBEFCI_EINVAL;
+  if (order < 1 || order >= (int32_t)c->scr_masks.size()) {
+    c->err = "order out of range of the last screened expansion";
+    return MBEFCI_EINVAL;
+  }
+  const auto& ms = c->scr_masks[order];
+  const auto& inc = c->scr_inc[order];
+  // lexicographic order of the sorted orbital lists
+  std::vector<std::vector<int32_t>> lists(ms.size());
+  for (size_t i = 0; i < ms.size(); ++i)
+    for (uint64_t x = ms[i]; x; x &= x - 1) lists[i].push_back(__builtin_ctzll(x));
+  std::vector<size_t> perm(ms.size());
+  for (size_t i = 0; i < perm.size(); ++i) perm[i] = i;
+  std::sort(perm.begin(), perm.end(), [&](size_t a, size_t b) { return lists[a] < lists[b]; });
+  for (size_t r = 0; r < perm.size(); ++r) {
+    if (tuples)
+      std::copy(lists[perm[r]].begin(), lists[perm[r]].end(), tuples + (int64_t)r * order);
+    if (increments) increments[r] = inc[perm[r]];
+  }
+  return (int64_t)ms.size();
 }
 
 int mbefci_mbe_backward(mbefci_ctx* c, const double* grad_out, double* d_h1, double* d_eri,

@@ -51,15 +51,42 @@ def test_default_options(lib):
     lib.mbefci_default_opts(ctypes.byref(o))
     assert o.conv_tol == 1e-6 and o.max_space == 16 and o.nguess == 2
     assert o.mode == _lib.BATCHED and o.keep_ci == 1 and o.validate == 1
+    assert o.precond == 0 and o.pspace == 112
 
 
 def test_null_context_is_rejected(lib):
     assert lib.mbefci_mbe_forward(None, None, None, None, None, None, None, None, None) == _lib.EINVAL
     assert lib.mbefci_strings(None, 4, 2, None, None) == _lib.EINVAL
+    assert lib.mbefci_mbe_screened(None, None, None, None, None, None, None, None, None) == \
+        _lib.EINVAL
+    assert lib.mbefci_screened_tuples(None, 1, None, None) == _lib.EINVAL
     assert lib.mbefci_last_error(None) == b"null context"
 
 
-def test_struct_layouts_match_header():
-    # mbefci_problem: int32, 2 pointers, double, (int32, ptr) x 3, int32
-    assert ctypes.sizeof(_lib.Problem) == 4 + 4 + 8 + 8 + 8 + 3 * (8 + 8) + 8
-    assert ctypes.sizeof(_lib.Stats) == 4 * 8 + 4 * 4 + 3 * 8
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes layouts equal the C compiler's layout of include/mbefci.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"mbefci_opts": _lib.Opts, "mbefci_problem": _lib.Problem,
+               "mbefci_stats": _lib.Stats, "mbefci_screen": _lib.Screen,
+               "mbefci_kernel_time": _lib.KernelTime}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mbefci.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append('  return 0;\n}')
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

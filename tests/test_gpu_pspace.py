@@ -11,8 +11,9 @@ on its block, the correction (theta - H_PP)^-1 r.
   residual far above the 1e-6 tolerance, so this pins the device
   Slater-Condon rules for singles, same-spin doubles and alpha-beta doubles.
 * With a partial P-space the energies must equal those of the unit-vector
-  guess with the diagonal correction (pspace = 0) to 1e-9 E_h, with no more
-  sigma evaluations.  (Very small P-spaces, a few determinants, can steer the
+  guess with the diagonal correction (pspace = 0; CASCIs of at most 112
+  determinants are solved from their whole space either way) to 1e-9 E_h,
+  with no more sigma evaluations.  (Very small P-spaces, a few determinants, can steer the
   solver to an excited root of a symmetric Hamiltonian: for the 8-orbital
   test matrix below P = 3..7 does, which a CPU model of the same iteration
   reproduces; the sizes tested are 1, 64 and the default 112.)
@@ -64,7 +65,7 @@ def test_whole_space_pspace_is_exact(ctx, n, na, nb):
     assert abs(got - exp) < 1e-9, (got, exp)
     if len(a) * len(b) > 1:
         assert st["max_iters"] == 0, st
-        assert st["sigma_calls"] <= 2, st
+        assert st["sigma_calls"] <= 3, st
 
 
 def test_whole_space_pspace_degenerate_hubbard(ctx):
@@ -101,9 +102,12 @@ def test_partial_pspace_matches_diagonal(ctx, pspace):
 
 
 def test_mbe_pspace_matches_diagonal(ctx):
-    _log("pspace mbe hubbard12")
+    """Hubbard-16 expansion (CASCIs of 1,225 to 63,504 determinants, most of
+    them large enough for the P-space): same increments as without it, fewer
+    sigma evaluations."""
+    _log("pspace mbe hubbard16")
     from paper_1910_03527_amd import Context
-    p = W.problem("hubbard12")
+    p = W.problem("hubbard16")
 
     def run(c):
         r = c.mbe_forward(_dev(p.h1), _dev(p.eri), p.occ, p.ref, p.exp, p.max_order, p.e_const,
@@ -118,7 +122,7 @@ def test_mbe_pspace_matches_diagonal(ctx):
     r1, s1 = run(ctx)
     assert np.max(np.abs(np.array(r1["increments"]) - np.array(r0["increments"]))) < 1e-9
     assert abs(r1["e_total"] - r0["e_total"]) < 1e-9
-    assert s1["sigma_calls"] < s0["sigma_calls"], (s1, s0)
+    assert s1["sigma_calls"] < 0.95 * s0["sigma_calls"], (s1, s0)
 
 
 def test_pspace_option_range():
