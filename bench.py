@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--per-launch-steps", type=int, default=1)
     ap.add_argument("--reps", type=int, default=5, help="kernel re-timing repetitions")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-screened", action="store_true",
+                    help="skip the screened-expansion measurement")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--sigma-pass-mb", type=int, default=0)
     ap.add_argument("--tune-cache", default=None,
@@ -254,6 +256,42 @@ def main():
                 "traffic": _traffic(dom["name"], args.workload),
                 "ms_per_launch": dom["ms_per_launch"], "launches_per_sweep": dom["launches"],
                 "algorithmic_bytes": dom["bytes"]}
+    # the screened order-by-order driver (Eq. 4 thresholds with the paper's
+    # parameters) on the vacuum-reference Hubbard-16 expansion, in a context
+    # of its own (it replaces the context's cached plan)
+    screened = None
+    if not args.no_screened:
+        sp = W.problem("hubbard16_vacuum")
+        sctx = Context(0, tune_cache=args.tune_cache)
+        try:
+            h2 = torch.as_tensor(sp.h1, device=dev)
+            g2 = torch.as_tensor(sp.eri, device=dev)
+            scr = dict(t_init=1e-10, m_init=3, a=5.0)
+
+            def run_screened():
+                return sctx.mbe_screened(h2, g2, sp.occ, sp.ref, sp.exp, sp.max_order, **scr)
+
+            run_screened()   # tunes the contraction for the new sizes, builds tables
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rs = run_screened()
+            torch.cuda.synchronize()
+            ms_s = (time.perf_counter() - t0) * 1e3
+            ss = dict(sctx.last_stats)
+            full = sctx.mbe_forward(h2, g2, sp.occ, sp.ref, sp.exp, sp.max_order)
+            nfull = int(sctx.last_stats["ntuples"])
+            screened = {"workload": f"hubbard16_vacuum-mbe{sp.max_order}-screened",
+                        "value": round(ss["ntuples"] / (ms_s / 1e3), 2),
+                        "unit": "CASCI solves/s", "ms_per_expansion": round(ms_s, 3),
+                        "t_init": scr["t_init"], "m_init": scr["m_init"], "a": scr["a"],
+                        "ncasci": int(ss["ntuples"]), "ncasci_unscreened": nfull - 1,
+                        "n_order": rs["n_order"], "e_total": rs["e_total"],
+                        "e_total_unscreened": full["e_total"],
+                        "screening_error": rs["e_total"] - full["e_total"],
+                        "sigma_calls": ss["sigma_calls"], "max_iters": ss["max_iters"]}
+        finally:
+            sctx.close()
+
     sig_ms = sum(k["ms_per_launch"] * k["launches"] for k in kt)
     sig_bytes = sum(k["bytes"] * k["launches"] for k in kt)
     sig_flops = sum(k["flops"] * k["launches"] for k in kt)
@@ -289,6 +327,7 @@ def main():
         "kernels": [{k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in k.items()}
                     for k in kt],
         "roofline": roof,
+        "screened": screened,
     }
     if cb is not None:
         tl = list(itertools.chain.from_iterable(

@@ -140,6 +140,10 @@ def problem(name: str, instance: int = 0) -> Problem:
         return _hubbard_problem(name, 16, 4.0, list(range(5, 11)), 4)
     if name == "hubbard12":
         return _hubbard_problem(name, 12, 3.0, [], 6)
+    if name == "hubbard16_vacuum":
+        # the paper's Type-3 setting: empty reference space, every MO in X;
+        # order-by-order with screening (orders 2..8)
+        return _hubbard_problem(name, 16, 4.0, [], 8)
     if name == "synthetic40":
         h, g = synthetic(40, 0)
         occ = list(range(6))
