@@ -17,6 +17,9 @@ What it computes, in the paper's order and notation (arXiv:1910.03527):
   (sum over all proper sub-tuples), the order sums E^(n) and the total of
   Eq. 1 (Eq. 3 for an empty reference space), plus the Moebius closed form as
   an independent second evaluation.
+* ``screen`` -- the screened order-by-order expansion: the thresholds of
+  Eq. 4, child spawning from the computed parent tuples, and Eq. 2 over the
+  computed sub-tuples.
 * ``rdm``  -- full-space spin-summed 1- and 2-RDMs by applying every operator
   string a+ a+ a a to every determinant; gradients dE/dh and dE/d(pq|rs) of
   f(T) and, through the adjoint of the Eq. 2 recursion, of E_MBE; central
