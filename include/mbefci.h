@@ -193,6 +193,20 @@ int mbefci_mbe_forward(mbefci_ctx* ctx, const mbefci_problem* prob, double* e_re
 int mbefci_mbe_backward(mbefci_ctx* ctx, const double* grad_out, double* d_h1, double* d_eri,
                         void* hip_stream);
 
+/* ---- partitions -------------------------------------------------------------
+ * The paper's three partitions of the M orbitals into a reference space R
+ * and an expansion space X (the discussion before Eq. 3), given the occupied
+ * orbitals O of the reference determinant:
+ *   MBEFCI_TYPE1: X = O (expansion over occupied MOs), R = the virtual MOs;
+ *   MBEFCI_TYPE2: R = O, X = the virtual MOs;
+ *   MBEFCI_TYPE3: R empty (vacuum reference), X = all M orbitals.
+ * Host only, no ctx.  ref / exp: host [M] buffers; *nref, *nexp receive the
+ * sizes; both lists ascending.  EINVAL for an unknown type, M outside 1..64 or
+ * a bad occupied list. */
+enum { MBEFCI_TYPE1 = 1, MBEFCI_TYPE2 = 2, MBEFCI_TYPE3 = 3 };
+int mbefci_partition(int32_t type, int32_t norb, int32_t nocc, const int32_t* occ, int32_t* ref,
+                     int32_t* nref, int32_t* exp, int32_t* nexp);
+
 /* ---- screened expansion ---------------------------------------------------
  * The order-by-order driver of the paper's production runs (the tuple
  * screening described with Eq. 4).  Order 1 holds every expansion orbital;

@@ -14,6 +14,8 @@ Names mirror the C ABI without the ``mbefci_`` prefix:
 * ``Context.casci``                            (batch of same-shape CASCIs)
 * ``Context.casci_rdm``                        (their 1- and 2-RDMs)
 * ``Context.mbe_forward``, ``Context.mbe_backward``  (Eq. 1 / Eq. 2)
+* ``Context.mbe_screened``  (order-by-order expansion with the Eq. 4 screening)
+* ``partition``  (the Type-1/2/3 reference/expansion partitions)
 * ``MBEEnergy``  -- ``torch.autograd.Function`` over forward/backward.
 """
 from __future__ import annotations
@@ -27,4 +29,8 @@ from .binding import (  # noqa: F401
     num_links,
     num_strings,
     num_tuples,
+    partition,
+    TYPE1,
+    TYPE2,
+    TYPE3,
 )

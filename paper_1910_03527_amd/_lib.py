@@ -23,7 +23,7 @@ EXPORTS = (
     "mbefci_set_opts", "mbefci_num_strings", "mbefci_num_links", "mbefci_strings",
     "mbefci_link_table", "mbefci_num_tuples", "mbefci_hdiag", "mbefci_sigma", "mbefci_casci",
     "mbefci_casci_rdm", "mbefci_mbe_forward", "mbefci_mbe_backward", "mbefci_mbe_screened",
-    "mbefci_screened_tuples", "mbefci_time_kernels",
+    "mbefci_screened_tuples", "mbefci_partition", "mbefci_time_kernels",
 )
 
 
@@ -164,6 +164,9 @@ def load():
     L.mbefci_mbe_screened.restype = ctypes.c_int
     L.mbefci_screened_tuples.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
     L.mbefci_screened_tuples.restype = i64
+    pi32 = ctypes.POINTER(i32)
+    L.mbefci_partition.argtypes = [i32, i32, i32, pi32, pi32, pi32, pi32, pi32]
+    L.mbefci_partition.restype = ctypes.c_int
     L.mbefci_time_kernels.argtypes = [vp, i32, ctypes.POINTER(KernelTime), i32,
                                       ctypes.POINTER(i32)]
     L.mbefci_time_kernels.restype = ctypes.c_int

@@ -10,6 +10,8 @@ import torch
 from . import _lib
 from ._lib import BATCHED, PER_LAUNCH, MbefciError  # noqa: F401
 
+TYPE1, TYPE2, TYPE3 = 1, 2, 3   # reference/expansion partitions (mbefci_partition)
+
 
 def num_strings(norb: int, nelec: int) -> int:
     return int(_lib.load().mbefci_num_strings(norb, nelec))
@@ -39,6 +41,20 @@ def _i32(xs):
     xs = [int(x) for x in xs]
     arr = (ctypes.c_int32 * max(1, len(xs)))(*xs)
     return arr
+
+
+def partition(kind: int, norb: int, occ):
+    """(ref, exp) of the paper's Type-1/2/3 partition (mbefci_partition)."""
+    L = _lib.load()
+    occ_a = _i32(occ)
+    ref = (ctypes.c_int32 * norb)()
+    exp = (ctypes.c_int32 * norb)()
+    nr, nx = ctypes.c_int32(), ctypes.c_int32()
+    rc = L.mbefci_partition(int(kind), int(norb), len(occ), occ_a, ref, ctypes.byref(nr), exp,
+                            ctypes.byref(nx))
+    if rc != 0:
+        raise MbefciError(rc, "mbefci_partition failed")
+    return list(ref)[:nr.value], list(exp)[:nx.value]
 
 
 class Context:

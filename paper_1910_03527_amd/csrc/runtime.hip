@@ -1306,6 +1306,29 @@ int mbefci_mbe_forward(mbefci_ctx* c, const mbefci_problem* pb, double* e_ref, d
   });
 }
 
+int mbefci_partition(int32_t type, int32_t norb, int32_t nocc, const int32_t* occ, int32_t* ref,
+                     int32_t* nref, int32_t* exp, int32_t* nexp) {
+  if (type < MBEFCI_TYPE1 || type > MBEFCI_TYPE3 || norb < 1 || norb > kMaxOrb || nocc < 0 ||
+      nocc > norb || (nocc > 0 && !occ) || !ref || !nref || !exp || !nexp)
+    return MBEFCI_EINVAL;
+  std::vector<int> is_occ(norb, 0);
+  for (int i = 0; i < nocc; ++i) {
+    if (occ[i] < 0 || occ[i] >= norb || is_occ[occ[i]]) return MBEFCI_EINVAL;
+    is_occ[occ[i]] = 1;
+  }
+  int nr = 0, nx = 0;
+  for (int p = 0; p < norb; ++p) {
+    bool in_ref = false;
+    if (type == MBEFCI_TYPE1) in_ref = !is_occ[p];
+    if (type == MBEFCI_TYPE2) in_ref = is_occ[p] != 0;
+    if (in_ref) ref[nr++] = p;
+    else exp[nx++] = p;
+  }
+  *nref = nr;
+  *nexp = nx;
+  return MBEFCI_OK;
+}
+
 int mbefci_mbe_screened(mbefci_ctx* c, const mbefci_problem* pb, const mbefci_screen* scr,
                         double* e_ref, double* e_order, double* e_total, int64_t* n_order,
                         mbefci_stats* stats, void* stream) {
