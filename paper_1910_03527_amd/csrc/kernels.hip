@@ -533,13 +533,32 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
       double4_t acc[NCB];
 #pragma unroll
       for (int cb2 = 0; cb2 < NCB; ++cb2) acc[cb2] = (double4_t){0.0, 0.0, 0.0, 0.0};
+      // B operands double-buffered in registers: the LDS reads of k-step
+      // ks+1 are issued before the MFMAs of k-step ks
+      double bq[2][NCB];
+      const double* bbase = Ds + (lane >> 4) * LDT + (lane & 15);
+#pragma unroll
+      for (int cb2 = 0; cb2 < NCB; ++cb2) bq[0][cb2] = bbase[cb2 * 16];
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        const double* brow = Ds + (ks * 4 + (lane >> 4)) * LDT + (lane & 15);
+        if (ks + 1 < KS) {
+#pragma unroll
+          for (int cb2 = 0; cb2 < NCB; ++cb2)
+            bq[(ks + 1) & 1][cb2] = bbase[(ks + 1) * 4 * LDT + cb2 * 16];
+        }
 #pragma unroll
         for (int cb2 = 0; cb2 < NCB; ++cb2)
-          acc[cb2] = __builtin_amdgcn_mfma_f64_16x16x4f64(wreg[r][ks], brow[cb2 * 16], acc[cb2],
+          acc[cb2] = __builtin_amdgcn_mfma_f64_16x16x4f64(wreg[r][ks], bq[ks & 1][cb2], acc[cb2],
                                                           0, 0, 0);
+      }
+      // instruction order for the scheduler: the first B reads, then per
+      // k-step the next step's B reads (0x100: LDS read) ahead of this
+      // step's MFMAs (0x008)
+      __builtin_amdgcn_sched_group_barrier(0x100, NCB, 0);
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        if (ks + 1 < KS) __builtin_amdgcn_sched_group_barrier(0x100, NCB, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, NCB, 0);
       }
       double* __restrict__ Grow = G + (int64_t)Ka * NP * Nb;
 #pragma unroll
