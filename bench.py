@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-screened", action="store_true",
                     help="skip the screened-expansion measurement")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the timings of the other workload configurations")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--sigma-pass-mb", type=int, default=0)
     ap.add_argument("--tune-cache", default=None,
@@ -292,9 +294,74 @@ def main():
         finally:
             sctx.close()
 
+    # the other workload configurations, each warm, in contexts of their own
+    configs = None
+    if not args.no_configs:
+        configs = {}
+        for name in ("hubbard8", "synthetic40", "hubbard12"):
+            cp = W.problem(name)
+            cctx = Context(0, tune_cache=args.tune_cache)
+            try:
+                ch = torch.as_tensor(cp.h1, device=dev)
+                cg = torch.as_tensor(cp.eri, device=dev)
+                grad = name == "hubbard12"
+
+                def run_cfg():
+                    r = cctx.mbe_forward(ch, cg, cp.occ, cp.ref, cp.exp, cp.max_order, cp.e_const)
+                    if grad:
+                        cctx.mbe_backward([1.0] * (1 + cp.max_order))
+                    return r
+
+                run_cfg()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rc = run_cfg()
+                torch.cuda.synchronize()
+                mc = (time.perf_counter() - t0) * 1e3
+                sc = dict(cctx.last_stats)
+                configs[name] = {"value": round(sc["ntuples"] / (mc / 1e3), 2),
+                                 "unit": "CASCI solves/s", "ms": round(mc, 3),
+                                 "step": "forward + backward" if grad else "forward",
+                                 "ncasci": int(sc["ntuples"]), "max_order": cp.max_order,
+                                 "sigma_calls": sc["sigma_calls"], "e_total": rc["e_total"]}
+            finally:
+                cctx.close()
+        # 8 x CAS(14e,14o): one batched solve plus the RDMs, and the sigma
+        # kernels of that batch re-timed
+        probs = [W.problem("cas14", i) for i in range(8)]
+        cctx = Context(0, tune_cache=args.tune_cache)
+        try:
+            hs = [torch.as_tensor(q.h1, device=dev) for q in probs]
+            gs = [torch.as_tensor(q.eri, device=dev) for q in probs]
+            cctx.casci(hs, gs, 7, 7)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ec = cctx.casci(hs, gs, 7, 7)
+            cctx.casci_rdm()
+            torch.cuda.synchronize()
+            mc = (time.perf_counter() - t0) * 1e3
+            sc = dict(cctx.last_stats)
+            kc = cctx.time_kernels(2)
+            configs["cas14x8"] = {
+                "value": round(8 / (mc / 1e3), 3), "unit": "CASCI solves/s", "ms": round(mc, 1),
+                "step": "forward + RDMs", "ndet_each": 11778624,
+                "sigma_calls": sc["sigma_calls"], "max_iters": sc["max_iters"],
+                "energies": ec,
+                "kernels": [{"name": k["name"], "ms_per_launch": round(k["ms_per_launch"], 4),
+                             "tflops": round(k["flops"] / (k["ms_per_launch"] * 1e-3) / 1e12, 3),
+                             "gbps": round(k["bytes"] / (k["ms_per_launch"] * 1e-3) / 1e9, 1)}
+                            for k in kc]}
+        finally:
+            cctx.close()
+
     sig_ms = sum(k["ms_per_launch"] * k["launches"] for k in kt)
     sig_bytes = sum(k["bytes"] * k["launches"] for k in kt)
     sig_flops = sum(k["flops"] * k["launches"] for k in kt)
+    # measured HBM traffic (rocprofv3 records) of the sigma kernels that have one
+    meas = [(k, _traffic(k["name"], args.workload)) for k in kt]
+    meas = [(k, tr) for k, tr in meas if tr is not None]
+    meas_ms = sum(k["ms_per_launch"] * k["launches"] for k, _ in meas)
+    meas_bytes = sum(tr * k["launches"] for k, tr in meas)
 
     out = {
         "metric": METRIC,
@@ -323,11 +390,18 @@ def main():
         "sigma_build": {"ms_per_sweep": round(sig_ms, 4),
                         "gbps_algorithmic": round(sig_bytes / (sig_ms * 1e-3) / 1e9, 1),
                         "frac_hbm": round(sig_bytes / (sig_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                        "tflops_mfma": round(sig_flops / (sig_ms * 1e-3) / 1e12, 3)},
+                        "tflops_mfma": round(sig_flops / (sig_ms * 1e-3) / 1e12, 3),
+                        "gbps_hbm_measured": (round(meas_bytes / (meas_ms * 1e-3) / 1e9, 1)
+                                              if meas else None),
+                        "frac_hbm_measured": (round(meas_bytes / (meas_ms * 1e-3) / 1e9
+                                                    / HBM_PEAK_GBPS, 4) if meas else None),
+                        "measured_kernels": [k["name"] for k, _ in meas],
+                        "measured_share_of_sweep": (round(meas_ms / sig_ms, 4) if meas else None)},
         "kernels": [{k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in k.items()}
                     for k in kt],
         "roofline": roof,
         "screened": screened,
+        "configs": configs,
     }
     if cb is not None:
         tl = list(itertools.chain.from_iterable(
