@@ -426,13 +426,17 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
   const int Kbc = Kb < Nb ? Kb : Nb - 1;
   const double* __restrict__ ca = c + Kbc;  // alpha source of D+: ca[Ja * Nb]
 
+  // Row blocks rb = wrot + 4r of this wave.  When the 16-row blocks of G do
+  // not come in multiples of four some waves have one block fewer; rotating
+  // the assignment by workgroup spreads those idle slots over the SIMDs.
+  const int wrot = (wave + (int)blockIdx.x) & 3;
   // W rows of this wave's row blocks, as MFMA A operands: lane l holds
   // W[rb*16 + l%16][ks*4 + l/16] (B operand: lane l holds D+[ks*4 + l/16][l%16])
   double wreg[RBW][KS];
   const double* __restrict__ W = warena + I.woff;
 #pragma unroll
   for (int r = 0; r < RBW; ++r) {
-    const int rb = wave + 4 * r;
+    const int rb = wrot + 4 * r;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
       wreg[r][ks] = (rb < NRB) ? ldg(W + (rb * 16 + (lane & 15)) * KPAD + ks * 4 + (lane >> 4))
@@ -528,7 +532,7 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
     }
 #pragma unroll
     for (int r = 0; r < RBW; ++r) {
-      const int rb = wave + 4 * r;
+      const int rb = wrot + 4 * r;
       if (rb >= NRB) continue;
       double4_t acc[NCB];
 #pragma unroll
