@@ -61,9 +61,11 @@ typedef struct {
   int32_t max_iter;      /* Davidson iterations per CASCI (default 200)              */
   int32_t max_space;     /* subspace size before restart, 2..16 (default 16)        */
   int32_t nguess;        /* lowest-diagonal unit guess vectors, 1..8, below
-                            max_space - 1 (default 2); every solve also starts
-                            from one dense vector with weight in every symmetry
-                            sector, orthogonalised against the others          */
+                            max_space - 1 (default 1), for CASCIs that use
+                            neither their whole space nor a P-space; every
+                            solve also starts from one dense vector with
+                            weight in every symmetry sector, orthogonalised
+                            against the other guesses                       */
   int32_t mode;          /* MBEFCI_BATCHED (default) or MBEFCI_PER_LAUNCH            */
   int32_t use_graph;     /* batched mode: replay captured iterations (default 1)     */
   int32_t tile;          /* sigma tile width 32/64/128; 0 = autotuned schedule: the

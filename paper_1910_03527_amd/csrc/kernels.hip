@@ -1291,9 +1291,9 @@ __global__ void __launch_bounds__(256) k_pspace_select(const Item* __restrict__ 
   const int it = ibase + blockIdx.x;
   const Item& I = items[it];
   const int64_t nd = I.ndet;
-  // small CASCIs: every determinant; larger ones: pmax (at least the two
-  // lowest, used as unit guesses when the P-space is not used)
-  const int np = nd <= kMaxPspace ? (int)nd : (pmax > 2 ? pmax : 2);
+  // small CASCIs: every determinant; larger ones: pmax (at least the eight
+  // lowest, the unit guesses when the P-space is not used)
+  const int np = nd <= kMaxPspace ? (int)nd : (pmax > 8 ? pmax : 8);
   const double* __restrict__ d = diag + I.off;
   const int t = threadIdx.x;
   __shared__ uint32_t hist[256];
@@ -1476,7 +1476,7 @@ __device__ inline int sturm_count(const double* d, const double* e, int n, doubl
 __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
     const Item* __restrict__ items, int ibase, const ItemHam* __restrict__ hams,
     const double* __restrict__ diag, const int32_t* __restrict__ pidx, double* __restrict__ pQ,
-    double* __restrict__ pT, double* V, int64_t ntot, DavState* st, int pmax) {
+    double* __restrict__ pT, double* V, int64_t ntot, DavState* st, int pmax, int nunit) {
   constexpr int PM = kMaxPspace;
   constexpr int NT = kPspaceThreads;
   __shared__ double A[PM * (PM + 1) / 2];
@@ -1502,15 +1502,19 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
     return;
   }
   if (nd > kMaxPspace && (pmax == 0 || nd < (int64_t)kPspaceMinRatio * pmax)) {
-    // unit vectors on the two lowest diagonal determinants (idx is sorted),
-    // the dense vector without those two components in slot 2
-    const int i0 = idx[0], i1 = idx[1];
-    const double sc = 1.0 / sqrt((double)(nd - 2));
-    double* __restrict__ vr = V + 2 * ntot + I.off;
-    for (int64_t K = t; K < nd; K += NT) vr[K] = (K == i0 || K == i1) ? 0.0 : hash_sign(K) * sc;
-    if (t < 2) V[(int64_t)t * ntot + I.off + idx[t]] = 1.0;
+    // unit vectors on the g lowest diagonal determinants (idx is sorted), the
+    // dense vector without those components in slot g
+    const int g = nunit;
+    const double sc = 1.0 / sqrt((double)(nd - g));
+    double* __restrict__ vr = V + (int64_t)g * ntot + I.off;
+    for (int64_t K = t; K < nd; K += NT) {
+      bool hit = false;
+      for (int j = 0; j < g; ++j) hit |= idx[j] == K;
+      vr[K] = hit ? 0.0 : hash_sign(K) * sc;
+    }
+    if (t < g) V[(int64_t)t * ntot + I.off + idx[t]] = 1.0;
     if (t == 0) {
-      S.m = 0; S.nguess = 3; S.np = 0; S.iters = 0; S.status = 0; S.rnorm = 0.0; S.conv = 0;
+      S.m = 0; S.nguess = g + 1; S.np = 0; S.iters = 0; S.status = 0; S.rnorm = 0.0; S.conv = 0;
       S.onepass = 0;
       S.theta = 0.0;
     }
@@ -1674,55 +1678,31 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
     vv[t] = u;
   }
   __syncthreads();
-  const double u0 = vv[0];
-  if (t == 0) {
-    double n2 = 0.0;
-    for (int k = 0; k < n; ++k) {
-      const double w = (k == 0 ? 1.0 : 0.0) - u0 * vv[k];
-      n2 += w * w;
-    }
-    nrm2 = n2;
-  }
-  __syncthreads();
-  const bool two = nrm2 > 1e-12;
-  const double inv = two ? 1.0 / sqrt(nrm2) : 0.0;
+  // guess 0: the P-space eigenvector u; guess 1: the dense vector
+  // r = sign/sqrt(ndet) minus its component on u (u lives on the P block),
+  // |r - c u|^2 = 1 - c^2
   double* __restrict__ v0 = V + I.off;
-  double* __restrict__ v1 = V + ntot + I.off;
-  for (int k = t; k < n; k += NT) {
-    const int e = idx[k];
-    v0[e] = vv[k];
-    if (two) v1[e] = ((k == 0 ? 1.0 : 0.0) - u0 * vv[k]) * inv;
-  }
-  // dense vector r = sign/sqrt(ndet) minus its components on the guesses
-  // above (both live on the P block): r - c0 u - c1 e', |.|^2 = 1 - c0^2 - c1^2
-  const int slot_r = two ? 2 : 1;
+  for (int k = t; k < n; k += NT) v0[idx[k]] = vv[k];
   if (t == 0) {
     const double rs = 1.0 / sqrt((double)nd);
-    double c0 = 0.0, c1 = 0.0;
-    for (int k = 0; k < n; ++k) {
-      const double rk = hash_sign(idx[k]) * rs;
-      c0 += vv[k] * rk;
-      if (two) c1 += ((k == 0 ? 1.0 : 0.0) - u0 * vv[k]) * inv * rk;
-    }
+    double c0 = 0.0;
+    for (int k = 0; k < n; ++k) c0 += vv[k] * hash_sign(idx[k]) * rs;
     zz[0] = c0;
-    zz[1] = c1;
-    zz[2] = 1.0 - c0 * c0 - c1 * c1;
+    zz[2] = 1.0 - c0 * c0;
   }
   __syncthreads();
   const bool dense = nd > n && zz[2] > 1e-6;
   if (dense) {
     const double rs = 1.0 / sqrt((double)nd), rn = 1.0 / sqrt(zz[2]);
-    double* __restrict__ vr = V + (int64_t)slot_r * ntot + I.off;
+    double* __restrict__ vr = V + ntot + I.off;
     for (int64_t K = t; K < nd; K += NT) vr[K] = hash_sign(K) * rs * rn;
     __syncthreads();   // the P-block entries below overwrite the dense pass
-    for (int k = t; k < n; k += NT) {
-      const double ek = two ? ((k == 0 ? 1.0 : 0.0) - u0 * vv[k]) * inv : 0.0;
-      vr[idx[k]] = (hash_sign(idx[k]) * rs - zz[0] * vv[k] - zz[1] * ek) * rn;
-    }
+    for (int k = t; k < n; k += NT)
+      vr[idx[k]] = (hash_sign(idx[k]) * rs - zz[0] * vv[k]) * rn;
   }
   if (t == 0) {
     S.m = 0;
-    S.nguess = (two ? 2 : 1) + (dense ? 1 : 0);
+    S.nguess = 1 + (dense ? 1 : 0);
     S.np = n;
     S.onepass = 0;
     S.iters = 0;
@@ -2446,10 +2426,10 @@ void launch_dav_rr(const Item* items, int ibase, int nitem, const double* part, 
 }
 void launch_pspace_setup(const Item* items, int ibase, int nitem, const ItemHam* hams,
                          const double* diag, int32_t* pidx, double* pQ, double* pT, double* V,
-                         int64_t ntot, DavState* st, int pmax, hipStream_t s) {
+                         int64_t ntot, DavState* st, int pmax, int nunit, hipStream_t s) {
   hipLaunchKernelGGL(k_pspace_select, dim3(nitem), dim3(256), 0, s, items, ibase, diag, pidx, pmax);
   hipLaunchKernelGGL(k_pspace_eigen, dim3(nitem), dim3(kPspaceThreads), 0, s, items, ibase, hams,
-                     diag, pidx, pQ, pT, V, ntot, st, pmax);
+                     diag, pidx, pQ, pT, V, ntot, st, pmax, nunit);
 }
 void launch_dav_iteration(const Item* items, int ibase, int nitem, const Work* chunks, int nchunk,
                           double* V, double* Sv, const double* diag, int64_t ntot, DavState* st,

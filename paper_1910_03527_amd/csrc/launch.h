@@ -46,7 +46,7 @@ struct PspaceArgs {
 };
 void launch_pspace_setup(const Item* items, int ibase, int nitem, const ItemHam* hams,
                          const double* diag, int32_t* pidx, double* pQ, double* pT, double* V,
-                         int64_t ntot, DavState* st, int pmax, hipStream_t s);
+                         int64_t ntot, DavState* st, int pmax, int nunit, hipStream_t s);
 void launch_dav_iteration(const Item* items, int ibase, int nitem, const Work* chunks, int nchunk,
                           double* V, double* Sv, const double* diag, int64_t ntot, DavState* st,
                           double* part, double tol, int max_iter, int mmax, double* Rb,

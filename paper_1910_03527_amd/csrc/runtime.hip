@@ -607,8 +607,8 @@ void solve_view(mbefci_ctx* c, Plan& P, const View& v, int* graph_launches) {
   int g = std::max(1, std::min(c->opts.nguess, 8));
   if (P.pidx) {
     launch_pspace_setup(P.d_items, v.ibase, v.nitem, P.hams, P.diag, P.pidx, P.pQ, P.pT, P.V,
-                        P.ntot, P.st, c->opts.pspace, c->stream);
-    g = 3;  // P-space eigenvector, orthogonalised lowest-diagonal vector, dense vector
+                        P.ntot, P.st, c->opts.pspace, g, c->stream);
+    g += 1;  // unit vectors (or the P-space eigenvector) and the dense vector
   } else {
     launch_dav_guess(P.d_items, v.ibase, v.nitem, P.diag, P.V, P.ntot, P.st, g, c->stream);
     g += 1;  // the dense vector
@@ -662,7 +662,7 @@ void solve_view(mbefci_ctx* c, Plan& P, const View& v, int* graph_launches) {
 }
 
 void solve_plan(mbefci_ctx* c, Plan& P, mbefci_stats* stats) {
-  const int g = P.pidx ? 3 : std::max(1, std::min(c->opts.nguess, 8)) + 1;
+  const int g = std::max(1, std::min(c->opts.nguess, 8)) + 1;
   HIPCHK(hipEventRecord(c->t0, c->stream));
   launch_hdiag(P.d_items, P.d_blocks, P.nblock, P.hams, P.diag, c->stream);
   launch_fill(P.V, (int64_t)g * P.ntot, 0.0, c->stream);
@@ -935,7 +935,7 @@ void mbefci_default_opts(mbefci_opts* o) {
   o->conv_tol = 1e-6;
   o->max_iter = 200;
   o->max_space = 16;
-  o->nguess = 2;
+  o->nguess = 1;
   o->mode = MBEFCI_BATCHED;
   o->use_graph = 1;
   o->tile = 0;

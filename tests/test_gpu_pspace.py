@@ -65,7 +65,7 @@ def test_whole_space_pspace_is_exact(ctx, n, na, nb):
     assert abs(got - exp) < 1e-9, (got, exp)
     if len(a) * len(b) > 1:
         assert st["max_iters"] == 0, st
-        assert st["sigma_calls"] <= 3, st
+        assert st["sigma_calls"] <= 2, st
 
 
 def test_whole_space_pspace_degenerate_hubbard(ctx):
