@@ -1430,7 +1430,7 @@ __device__ double sc_offdiag(const ItemHam& H, uint64_t ia, uint64_t ib, uint64_
 // is always solved from its whole-space block (the guess is then the exact
 // ground state, whatever pmax); larger ones use a P-space of pmax
 // determinants when they are large enough for the reduction to pay off
-// (ndet >= kPspaceMinRatio * pmax), else the two lowest-diagonal unit
+// (ndet >= kPspaceMinRatio * pmax), else `nunit` lowest-diagonal unit
 // vectors and the diagonal correction.  The dense vector is always added.
 constexpr int kPspaceMinRatio = 32;
 constexpr int kPspaceThreads = 512;
