@@ -80,15 +80,16 @@ typedef struct {
   int32_t precond;       /* Davidson correction: 0 = diagonal (theta - H_II)^-1 r,
                             1 = Olsen-corrected, orthogonal to the Ritz vector
                             (default 0)                                          */
-  int32_t pspace;        /* P-space size 0..112 for CASCIs of more than 112
-                            determinants: the determinants of lowest diagonal
-                            energy whose block H_PP is diagonalised once per
-                            CASCI; it gives the guess and, on that block, the
-                            exact (theta - H_PP)^-1 correction; 0 = unit-vector
-                            guesses and the diagonal correction only.  CASCIs
-                            of at most 112 determinants are always solved from
-                            their whole-space block.  Ignored with precond = 1
-                            (default 112)                                     */
+  int32_t pspace;        /* P-space size 0..112 for CASCIs of at least
+                            8 x pspace determinants: the determinants of lowest
+                            diagonal energy whose block H_PP is diagonalised
+                            once per CASCI; it gives the guess and, on that
+                            block, the exact (theta - H_PP)^-1 correction;
+                            0 = unit-vector guesses and the diagonal correction
+                            only (also used between 113 and 8 x pspace
+                            determinants).  CASCIs of at most 112 determinants
+                            are always solved from their whole-space block.
+                            Ignored with precond = 1 (default 112)            */
   int32_t pad0_;
   int64_t max_workspace; /* workspace cap in bytes, 0 = no cap                       */
   const char* tune_cache;/* autotuner cache file (read/written) or NULL: one line per

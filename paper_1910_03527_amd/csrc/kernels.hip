@@ -1432,7 +1432,7 @@ __device__ double sc_offdiag(const ItemHam& H, uint64_t ia, uint64_t ib, uint64_
 // determinants when they are large enough for the reduction to pay off
 // (ndet >= kPspaceMinRatio * pmax), else `nunit` lowest-diagonal unit
 // vectors and the diagonal correction.  The dense vector is always added.
-constexpr int kPspaceMinRatio = 32;
+constexpr int kPspaceMinRatio = 8;
 constexpr int kPspaceThreads = 512;
 
 // Solve (theta - T) z = y for symmetric tridiagonal T (diagonal d, off-
