@@ -90,7 +90,10 @@ typedef struct {
                             determinants).  CASCIs of at most 112 determinants
                             are always solved from their whole-space block.
                             Ignored with precond = 1 (default 112)            */
-  int32_t pad0_;
+  int32_t screen_batch;  /* most CASCIs per solve batch of mbefci_mbe_screened
+                            (an order with more tuples, or more than 2^25
+                            determinants, is solved in several batches);
+                            0 = 65536 (default 0)                            */
   int64_t max_workspace; /* workspace cap in bytes, 0 = no cap                       */
   const char* tune_cache;/* autotuner cache file (read/written) or NULL: one line per
                             active size n, "n tile tiles_per_workgroup"          */

@@ -41,7 +41,7 @@ class Opts(ctypes.Structure):
         ("sigma_pass_mb", ctypes.c_int32),
         ("precond", ctypes.c_int32),
         ("pspace", ctypes.c_int32),
-        ("pad0_", ctypes.c_int32),
+        ("screen_batch", ctypes.c_int32),
         ("max_workspace", ctypes.c_int64),
         ("tune_cache", ctypes.c_char_p),
     ]

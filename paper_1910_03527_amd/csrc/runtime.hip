@@ -149,6 +149,14 @@ struct mbefci_ctx {
 
 namespace {
 
+// Bounds of one solve batch of the screened expansion: an order with more
+// tuples (or determinants) is solved in several batches.  The item bound is
+// the default of opts.screen_batch.  2^16 items keep the
+// per-item P-space blocks at 6.6 GB; 2^25 determinants keep the Davidson
+// vectors at 9 GB and G at most 28 GB (14 active orbitals).
+constexpr int64_t kScreenChunkItems = (int64_t)1 << 16;
+constexpr int64_t kScreenChunkDets = (int64_t)1 << 25;
+
 // ------------------------------------------------------------ device memory
 template <class T>
 T* arena(mbefci_ctx* c, const std::string& name, size_t count, bool* grown = nullptr) {
@@ -958,6 +966,7 @@ static int check_opts(const mbefci_opts* o, std::string* why) {
   if (o->sigma_pass_mb < 0) { *why = "sigma_pass_mb must be >= 0"; return MBEFCI_EINVAL; }
   if (o->precond != 0 && o->precond != 1) { *why = "precond must be 0 or 1"; return MBEFCI_EINVAL; }
   if (o->pspace < 0 || o->pspace > kMaxPspace) { *why = "pspace must be in 0..112"; return MBEFCI_EINVAL; }
+  if (o->screen_batch < 0) { *why = "screen_batch must be >= 0"; return MBEFCI_EINVAL; }
   return MBEFCI_OK;
 }
 
@@ -1370,6 +1379,14 @@ int mbefci_mbe_screened(mbefci_ctx* c, const mbefci_problem* pb, const mbefci_sc
       const int mt = std::max(o, v);
       return mt < scr->m_init ? 0.0 : scr->t_init * std::pow(scr->a, (double)(mt - scr->m_init));
     };
+    // determinants of the CASCI of tuple m: C(n, na)^2
+    auto tuple_dets = [&](uint64_t m) {
+      const int n = sp.nR + __builtin_popcountll(m);
+      const int na = sp.nocc_ref + __builtin_popcountll(m & occx);
+      int64_t b = 1;
+      for (int i = 1; i <= na; ++i) b = b * (n - na + i) / i;
+      return b * b;
+    };
     c->scr_masks.assign(K + 1, {});
     c->scr_inc.assign(K + 1, {});
     for (int k = 0; k < K; ++k) n_order[k] = 0;
@@ -1399,49 +1416,67 @@ int mbefci_mbe_screened(mbefci_ctx* c, const mbefci_problem* pb, const mbefci_sc
       if (!run && !first) break;
       std::sort(level.begin(), level.end());
       level.erase(std::unique(level.begin(), level.end()), level.end());
-      std::vector<uint64_t> masks;
-      if (first) masks.push_back(0);  // the reference CASCI (E_ref)
-      if (run) masks.insert(masks.end(), level.begin(), level.end());
-      if (c->plan && c->plan->graph) HIPCHK(hipGraphExecDestroy(c->plan->graph));
-      c->plan.reset(new Plan());
-      Plan& P = *c->plan;
-      P.norb = M;
-      P.sp = sp;
-      for (uint64_t m : masks) {
-        Item I{};
-        I.n = sp.nR + __builtin_popcountll(m);
-        I.na = I.nb = sp.nocc_ref + __builtin_popcountll(m & occx);
-        P.items.push_back(I);
-      }
-      finalize_plan(c, P, c->opts.nguess);
-      uint64_t* d_masks = arena<uint64_t>(c, "scr_items", masks.size());
-      upload(c, d_masks, masks);
-      launch_mbe_setup_list(&P.sp, d_masks, P.d_items, P.nitem, pb->h1, pb->eri, pb->e_const,
-                            P.hams, P.W, c->stream);
-      HIPCHK(hipGetLastError());
-      mbefci_stats st{};
-      solve_plan(c, P, &st);
-      tot.ntuples += st.ntuples - (first ? 1 : 0);
-      tot.nsingle += st.nsingle;
-      tot.sigma_calls += st.sigma_calls;
-      tot.ndet_total += st.ndet_total;
-      tot.max_iters = std::max(tot.max_iters, st.max_iters);
-      tot.nbuckets += st.nbuckets;
-      tot.graph_launches += st.graph_launches;
-      tot.ms_solve += st.ms_solve;
-      launch_item_energy(P.d_items, P.hams, P.st, P.nitem, P.f, c->stream);
-      if (first) {
-        HIPCHK(hipMemcpyAsync(d_eref, P.f, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        first = false;
-      }
+      // the order's tuples are solved in chunks of bounded size (items and
+      // determinants), so that an order of any width fits the device; their
+      // energies f(T) land in one order-wide array
+      const int64_t n = run ? (int64_t)level.size() : 0;
+      double* d_f = arena<double>(c, "scr_f", std::max<int64_t>(n, 1));
+      int64_t lo = 0;
+      do {
+        std::vector<uint64_t> masks;
+        const bool with_ref = first;
+        if (with_ref) masks.push_back(0);  // the reference CASCI (E_ref)
+        const int64_t max_items = c->opts.screen_batch > 0 ? c->opts.screen_batch
+                                                           : kScreenChunkItems;
+        int64_t hi = lo, dets = 0;
+        while (hi < n && (hi == lo || ((int64_t)masks.size() < max_items &&
+                                       dets + tuple_dets(level[hi]) <= kScreenChunkDets))) {
+          dets += tuple_dets(level[hi]);
+          masks.push_back(level[hi++]);
+        }
+        if (c->plan && c->plan->graph) HIPCHK(hipGraphExecDestroy(c->plan->graph));
+        c->plan.reset(new Plan());
+        Plan& P = *c->plan;
+        P.norb = M;
+        P.sp = sp;
+        for (uint64_t m : masks) {
+          Item I{};
+          I.n = sp.nR + __builtin_popcountll(m);
+          I.na = I.nb = sp.nocc_ref + __builtin_popcountll(m & occx);
+          P.items.push_back(I);
+        }
+        finalize_plan(c, P, c->opts.nguess);
+        uint64_t* d_masks = arena<uint64_t>(c, "scr_items", masks.size());
+        upload(c, d_masks, masks);
+        launch_mbe_setup_list(&P.sp, d_masks, P.d_items, P.nitem, pb->h1, pb->eri, pb->e_const,
+                              P.hams, P.W, c->stream);
+        HIPCHK(hipGetLastError());
+        mbefci_stats st{};
+        solve_plan(c, P, &st);
+        tot.ntuples += st.ntuples - (with_ref ? 1 : 0);
+        tot.nsingle += st.nsingle;
+        tot.sigma_calls += st.sigma_calls;
+        tot.ndet_total += st.ndet_total;
+        tot.max_iters = std::max(tot.max_iters, st.max_iters);
+        tot.nbuckets += st.nbuckets;
+        tot.graph_launches += st.graph_launches;
+        tot.ms_solve += st.ms_solve;
+        launch_item_energy(P.d_items, P.hams, P.st, P.nitem, P.f, c->stream);
+        const int off = with_ref ? 1 : 0;
+        if (with_ref) {
+          HIPCHK(hipMemcpyAsync(d_eref, P.f, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+          first = false;
+        }
+        if (hi > lo)
+          HIPCHK(hipMemcpyAsync(d_f + lo, P.f + off, (hi - lo) * sizeof(double),
+                                hipMemcpyDeviceToDevice, c->stream));
+        lo = hi;
+      } while (lo < n);
       if (!run) break;
-      const int off = masks[0] == 0 ? 1 : 0;
-      const int64_t n = (int64_t)level.size();
       uint64_t* dm = arena<uint64_t>(c, "scr_mask" + std::to_string(k), n);
       double* di = arena<double>(c, "scr_inc" + std::to_string(k), n);
       upload(c, dm, level);
-      launch_screen_increments(dm, n, k, P.f + off, d_eref, lower, di, d_eord + (k - 1),
-                               c->stream);
+      launch_screen_increments(dm, n, k, d_f, d_eref, lower, di, d_eord + (k - 1), c->stream);
       HIPCHK(hipGetLastError());
       lower.mask[k] = dm;
       lower.inc[k] = di;

@@ -22,6 +22,17 @@ Workloads (all FP64, chemist-order integrals, 0-based orbital indices):
 * ``cas14``      -- 8 synthetic CAS(14e,14o) instances, M=14, seeds 1..8, the
   whole space active (11,778,624 determinants each: the size of the paper's
   largest Hubbard CASCI).
+* ``hubbardN_pm`` (``hubbardN_pm_uU``) -- 1D Hubbard, N sites, open, t=1, U=2
+  (or U), half filling, in Pipek-Mezey localised orbitals: the paper's Type-3
+  lattice runs (22, 34 and 46 sites, U/t <= 3), empty reference space, every
+  MO in X, orders up to min(N, 14).
+
+Localised orbitals: the occupied and the virtual hopping eigenvectors are
+rotated separately (so the reference determinant, and its energy, stay the
+same) to maximise the Pipek-Mezey locality sum_i sum_A (c_Ai^2)^2, the site
+populations of an orthonormal site basis; then each block is ordered by
+orbital centroid sum_A A c_Ai^2 and each orbital's largest coefficient made
+positive.  The occupied block comes first.
 
 Hubbard MOs are the eigenvectors of the open-chain hopping matrix in closed
 form, phi_k(j) = sqrt(2/(N+1)) sin(pi j k/(N+1)), ordered by orbital energy
@@ -36,6 +47,7 @@ from __future__ import annotations
 import dataclasses
 import hashlib
 import math
+import re
 
 import numpy as np
 
@@ -44,6 +56,9 @@ __all__ = [
     "hubbard_site",
     "hubbard_mo",
     "synthetic",
+    "pipek_mezey",
+    "hubbard_pm",
+    "lieb_wu_energy",
     "problem",
     "WORKLOADS",
     "checksum",
@@ -102,6 +117,87 @@ def hubbard_mo(nsite: int, t: float, u: float):
     return h, g
 
 
+def pipek_mezey(c: np.ndarray, tol: float = 1e-13, max_sweeps: int = 5000) -> np.ndarray:
+    """Pipek-Mezey localisation of the orthonormal columns of ``c`` (rows: an
+    orthonormal site basis, so column i has population c[A, i]^2 on site A).
+
+    Maximises L = sum_i sum_A c[A, i]^4 by Jacobi sweeps over column pairs.
+    Rotating the pair (x, y) -> (cos g x + sin g y, -sin g x + cos g y) changes
+    L by P (1 - cos 4g) + Q sin 4g, with P = sum_A [(x y)^2 - (x^2 - y^2)^2 / 4]
+    and Q = sum_A x y (x^2 - y^2); the best angle has (cos 4g, sin 4g)
+    proportional to (-P, Q) and gains P + sqrt(P^2 + Q^2) >= 0.  Sweeps stop
+    when no pair gains more than ``tol``.
+    """
+    c = np.array(c, dtype=np.float64, copy=True)
+    n = c.shape[1]
+    for _ in range(max_sweeps):
+        best = 0.0
+        for s in range(n):
+            for t in range(s + 1, n):
+                x, y = c[:, s].copy(), c[:, t].copy()
+                xy = x * y
+                d = x * x - y * y
+                p = float(np.sum(xy * xy - 0.25 * d * d))
+                q = float(np.sum(d * xy))
+                gain = p + math.hypot(p, q)
+                if gain > tol:
+                    g = 0.25 * math.atan2(q, -p)
+                    cs, sn = math.cos(g), math.sin(g)
+                    c[:, s] = cs * x + sn * y
+                    c[:, t] = -sn * x + cs * y
+                    best = max(best, gain)
+        if best <= tol:
+            return c
+    raise RuntimeError("Pipek-Mezey sweeps did not converge")
+
+
+def _order_and_sign(c: np.ndarray) -> np.ndarray:
+    sites = np.arange(c.shape[0], dtype=np.float64)
+    cen = sites @ (c * c)
+    c = c[:, np.argsort(cen, kind="stable")]
+    big = np.argmax(np.abs(c), axis=0)
+    sign = np.sign(c[big, np.arange(c.shape[1])])
+    return c * sign
+
+
+def hubbard_pm(nsite: int, t: float, u: float):
+    """Hubbard integrals in Pipek-Mezey localised orbitals (occupied block
+    first, see the module docstring); returns (h, g, C) with C the site x
+    orbital coefficients."""
+    if nsite % 2:
+        raise ValueError("half filling needs an even number of sites")
+    h_site, _ = hubbard_site(nsite, t, u)
+    c0 = hubbard_orbitals(nsite)
+    nocc = nsite // 2
+    c = np.hstack([_order_and_sign(pipek_mezey(c0[:, :nocc])),
+                   _order_and_sign(pipek_mezey(c0[:, nocc:]))])
+    h = c.T @ h_site @ c
+    h = 0.5 * (h + h.T)
+    pair = np.einsum("jp,jq->jpq", c, c).reshape(nsite, nsite * nsite)
+    g = (u * pair.T @ pair).reshape((nsite,) * 4)
+    return h, g, c
+
+
+def lieb_wu_energy(u: float, t: float = 1.0) -> float:
+    """Ground-state energy per site of the half-filled 1D Hubbard model in the
+    thermodynamic limit (Lieb and Wu, 1968):
+    E/N = -4t int_0^inf J0(w) J1(w) / (w (1 + exp(w U / 2t))) dw.
+    A reference value for the lattice workloads (open chains of N sites lie
+    above it by a boundary term of order 1/N), not part of the expansion.
+    """
+    from scipy import integrate, special
+
+    def f(w):
+        return special.j0(w) * special.j1(w) / w * special.expit(-w * u / (2.0 * t))
+
+    wmax = 4000.0 if u <= 0 else min(4000.0, 90.0 * t / u + 40.0)
+    edges = np.arange(0.0, wmax + math.pi, math.pi)
+    val = 0.0
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        val += integrate.quad(f, lo, hi, limit=100, epsabs=1e-14, epsrel=1e-12)[0]
+    return -4.0 * t * val
+
+
 def synthetic(norb: int, seed: int, nchol: int = 120):
     """Molecular-like synthetic integrals (see module docstring)."""
     rng = np.random.default_rng(seed)
@@ -156,6 +252,12 @@ def problem(name: str, instance: int = 0) -> Problem:
         h, g = synthetic(14, instance + 1)
         occ = list(range(7))
         return Problem(f"cas14[{instance}]", h, g, 0.0, occ, list(range(14)), [], 0)
+    pm = re.fullmatch(r"hubbard(\d+)_pm(?:_u(\d+(?:\.\d+)?))?", name)
+    if pm:
+        n = int(pm.group(1))
+        u = float(pm.group(2)) if pm.group(2) else 2.0
+        h, g, _ = hubbard_pm(n, 1.0, u)
+        return Problem(name, h, g, 0.0, list(range(n // 2)), [], list(range(n)), min(n, 14))
     if name.startswith("hubbard") and name[7:].isdigit():
         n = int(name[7:])
         return _hubbard_problem(name, n, 2.0, [], n)
