@@ -80,16 +80,17 @@ typedef struct {
   int32_t precond;       /* Davidson correction: 0 = diagonal (theta - H_II)^-1 r,
                             1 = Olsen-corrected, orthogonal to the Ritz vector
                             (default 0)                                          */
-  int32_t pspace;        /* P-space size 0..112 for CASCIs of at least
-                            8 x pspace determinants: the determinants of lowest
-                            diagonal energy whose block H_PP is diagonalised
-                            once per CASCI; it gives the guess and, on that
-                            block, the exact (theta - H_PP)^-1 correction;
-                            0 = unit-vector guesses and the diagonal correction
-                            only (also used between 113 and 8 x pspace
-                            determinants).  CASCIs of at most 112 determinants
-                            are always solved from their whole-space block.
-                            Ignored with precond = 1 (default 112)            */
+  int32_t pspace;        /* largest P-space, 0..112: a CASCI of ndet > 112
+                            determinants uses the P = min(pspace, ndet / 64)
+                            determinants of lowest diagonal energy, whose block
+                            H_PP is diagonalised once per CASCI; it gives the
+                            guess and, on that block, the exact
+                            (theta - H_PP)^-1 correction.  P < 24, or
+                            pspace = 0: unit-vector guesses and the diagonal
+                            correction only.  CASCIs of at most 112
+                            determinants are always solved from their
+                            whole-space block.  Ignored with precond = 1
+                            (default 112)                                     */
   int32_t screen_batch;  /* most CASCIs per solve batch of mbefci_mbe_screened
                             (an order with more tuples, or more than 2^25
                             determinants, is solved in several batches);

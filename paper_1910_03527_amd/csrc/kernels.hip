@@ -1428,12 +1428,21 @@ __device__ double sc_offdiag(const ItemHam& H, uint64_t ia, uint64_t ib, uint64_
 // thread evaluates one point per round), its eigenvector from inverse
 // iteration; the guess is Q z.  A CASCI of at most kMaxPspace determinants
 // is always solved from its whole-space block (the guess is then the exact
-// ground state, whatever pmax); larger ones use a P-space of pmax
-// determinants when they are large enough for the reduction to pay off
-// (ndet >= kPspaceMinRatio * pmax), else `nunit` lowest-diagonal unit
-// vectors and the diagonal correction.  The dense vector is always added.
-constexpr int kPspaceMinRatio = 8;
+// ground state, whatever pmax); larger ones use a P-space of
+// min(pmax, ndet / kPspaceRatio) determinants, since the reduction costs
+// about P^3 against a Davidson iteration's ndet npair^2; below kPspaceMinDim
+// (where small P-spaces can also steer the solver to an excited root) they
+// start from `nunit` lowest-diagonal unit vectors with the diagonal
+// correction.  The dense vector is always added.
+constexpr int kPspaceRatio = 64;
+constexpr int kPspaceMinDim = 24;
 constexpr int kPspaceThreads = 512;
+
+__device__ __forceinline__ int pspace_dim(int64_t nd, int pmax) {
+  if (nd <= kMaxPspace) return (int)nd;
+  const int64_t p = nd / kPspaceRatio < pmax ? nd / kPspaceRatio : pmax;
+  return p >= kPspaceMinDim ? (int)p : 0;
+}
 
 // Solve (theta - T) z = y for symmetric tridiagonal T (diagonal d, off-
 // diagonal e) by an LDL^T sweep without pivoting, pivots kept at |p| >= floor
@@ -1501,7 +1510,8 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
     }
     return;
   }
-  if (nd > kMaxPspace && (pmax == 0 || nd < (int64_t)kPspaceMinRatio * pmax)) {
+  const int n = pspace_dim(nd, pmax);
+  if (n == 0) {
     // unit vectors on the g lowest diagonal determinants (idx is sorted), the
     // dense vector without those components in slot g
     const int g = nunit;
@@ -1532,7 +1542,6 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
     for (int w = 0; w < NT / 64; ++w) s += red[w];
     return s;
   };
-  const int n = nd <= kMaxPspace ? (int)nd : pmax;
   const ItemHam& H = hams[I.ham];
   for (int k = t; k < n; k += NT) {
     const int e = idx[k];  // an address of this item: 0 <= e < ndet
@@ -2309,11 +2318,23 @@ __global__ void k_screen_increments(const uint64_t* __restrict__ masks, int64_t 
 }
 
 // E^(k) = sum of the order-k increments, in index order (one thread).
-__global__ void k_screen_order_sum(const double* __restrict__ inc, int64_t n, double* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double e = 0.0;
-    for (int64_t i = 0; i < n; ++i) e += inc[i];
-    out[0] = e;
+// E^(k): one block, every thread a strided partial sum, then a fixed-order
+// wave and block reduction (the order depends only on n, so the result is
+// reproducible).
+__global__ void __launch_bounds__(1024) k_screen_order_sum(const double* __restrict__ inc,
+                                                           int64_t n, double* out) {
+  __shared__ double part[16];
+  const int t = threadIdx.x;
+  double e = 0.0;
+  for (int64_t i = t; i < n; i += 1024) e += inc[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) e += __shfl_down(e, o, 64);
+  if ((t & 63) == 0) part[t >> 6] = e;
+  __syncthreads();
+  if (t == 0) {
+    double sum = 0.0;
+    for (int w = 0; w < 16; ++w) sum += part[w];
+    out[0] = sum;
   }
 }
 
@@ -2583,6 +2604,6 @@ void launch_screen_increments(const uint64_t* masks, int64_t n, int k, const dou
   if (n > 0)
     hipLaunchKernelGGL(k_screen_increments, dim3(nblk(n, 128)), dim3(128), 0, s, masks, n, k, f,
                        e_ref, lv, inc);
-  hipLaunchKernelGGL(k_screen_order_sum, dim3(1), dim3(64), 0, s, inc, n, order_sum);
+  hipLaunchKernelGGL(k_screen_order_sum, dim3(1), dim3(1024), 0, s, inc, n, order_sum);
 }
 }  // namespace mbefci
