@@ -1492,9 +1492,8 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
   __shared__ double Q[PM * PM];
   __shared__ uint64_t sa[PM], sb[PM];
   __shared__ double vv[PM], pw[PM], dd[PM], ee[PM], beta[PM], zz[PM], piv[PM];
-  __shared__ double red[NT / 64];
   __shared__ double lo_hi[2];
-  __shared__ double nrm2;
+  __shared__ int cnt[NT];
   const int it = ibase + blockIdx.x;
   const Item& I = items[it];
   DavState& S = st[it];
@@ -1530,18 +1529,6 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
     }
     return;
   }
-  // fixed-order block sum of one value per thread
-  auto block_sum = [&](double x) -> double {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-    __syncthreads();
-    if (lane == 0) red[wv] = x;
-    __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < NT / 64; ++w) s += red[w];
-    return s;
-  };
   const ItemHam& H = hams[I.ham];
   for (int k = t; k < n; k += NT) {
     const int e = idx[k];  // an address of this item: 0 <= e < ndet
@@ -1550,28 +1537,40 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
   }
   __syncthreads();
   auto L = [](int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; };
-  for (int i = t; i < n; i += NT)   // row i of the packed lower triangle
-    for (int j = 0; j <= i; ++j)
-      A[i * (i + 1) / 2 + j] =
-          (i == j) ? diag[I.off + idx[i]] : sc_offdiag(H, sa[i], sb[i], sa[j], sb[j]);
+  // the packed lower triangle, its elements dealt evenly over the threads
+  // (element x is row i, column x - i(i+1)/2)
+  for (int x = t; x < n * (n + 1) / 2; x += NT) {
+    int i = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= x) ++i;
+    while (i * (i + 1) / 2 > x) --i;
+    const int j = x - i * (i + 1) / 2;
+    A[x] = (i == j) ? diag[I.off + idx[i]] : sc_offdiag(H, sa[i], sb[i], sa[j], sb[j]);
+  }
   __syncthreads();
 
-  // ---- Householder reduction: step k annihilates A[k+2.., k]
+  // ---- Householder reduction: step k annihilates A[k+2.., k].  The two
+  // dot products of a step are formed by every wave for itself (a butterfly
+  // over the wave leaves the same value in every lane of every wave), so a
+  // step needs three block barriers.
+  auto wave_sum = [&](double x) -> double {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+  };
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
-    double x = 0.0;
-    if (t < m) {
-      x = A[L(k + 1 + t, k)];
-      vv[t] = x;
+    double sq = 0.0;
+    for (int i = lane; i < m; i += 64) {
+      const double xi = A[L(k + 1 + i, k)];
+      sq += xi * xi;
     }
-    const double sig = block_sum(x * x);  // (includes a barrier)
-    const double x0 = vv[0];
+    const double sig = wave_sum(sq);
+    const double x0 = A[L(k + 1, k)];
     const double sg = sqrt(sig);
     const double alpha = x0 >= 0.0 ? -sg : sg;
     const double bt = sig > 0.0 ? 1.0 / (sig - x0 * alpha) : 0.0;
-    __syncthreads();
+    if (t < m) vv[t] = t == 0 ? x0 - alpha : A[L(k + 1 + t, k)];
     if (t == 0) {
-      vv[0] = x0 - alpha;
       ee[k] = sig > 0.0 ? alpha : x0;
       beta[k] = bt;
     }
@@ -1581,21 +1580,26 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
       {
         const int row = t >> 2, part = t & 3;
         double acc = 0.0;
-        if (row < m)
+        if (row < m) {
+#pragma unroll 4
           for (int j = part; j < m; j += 4) acc += A[L(k + 1 + row, k + 1 + j)] * vv[j];
+        }
         acc += __shfl_xor(acc, 1, 64);
         acc += __shfl_xor(acc, 2, 64);
         if (row < m && part == 0) pw[row] = bt * acc;
       }
       __syncthreads();
-      const double Kc = 0.5 * bt * block_sum(t < m ? pw[t] * vv[t] : 0.0);
-      __syncthreads();
-      if (t < m) pw[t] -= Kc * vv[t];   // w = p - K v
-      __syncthreads();
-      // B -= v w^T + w v^T (lower triangle), rows strided by 64, columns by 8
-      for (int i = t >> 3; i < m; i += NT / 8)
+      double pv = 0.0;
+      for (int i = lane; i < m; i += 64) pv += pw[i] * vv[i];
+      const double Kc = 0.5 * bt * wave_sum(pv);
+      // B -= v w^T + w v^T with w = p - K v (lower triangle), rows strided
+      // by 64, columns by 8
+      for (int i = t >> 3; i < m; i += NT / 8) {
+        const double vi = vv[i], wi = pw[i] - Kc * vi;
+#pragma unroll 4
         for (int j = t & 7; j <= i; j += 8)
-          A[L(k + 1 + i, k + 1 + j)] -= vv[i] * pw[j] + pw[i] * vv[j];
+          A[L(k + 1 + i, k + 1 + j)] -= vi * (pw[j] - Kc * vv[j]) + wi * vv[j];
+      }
     }
     // keep v in column k below the diagonal (A[k+1+i, k] = v_i)
     if (t < m) A[L(k + 1 + t, k)] = vv[t];
@@ -1618,16 +1622,29 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
     {
       const int col = k + 1 + (t >> 2), part = t & 3;
       double acc = 0.0;
-      if (col < n)
+      if (col < n) {
+#pragma unroll 4
         for (int i = part; i < m; i += 4) acc += A[L(k + 1 + i, k)] * Q[(k + 1 + i) * n + col];
+      }
       acc += __shfl_xor(acc, 1, 64);
       acc += __shfl_xor(acc, 2, 64);
       if (col < n && part == 0) pw[col - k - 1] = bt * acc;
     }
     __syncthreads();
-    for (int x = t; x < m * m; x += NT) {
-      const int i = x / m, j = x % m;
-      Q[(k + 1 + i) * n + (k + 1 + j)] -= A[L(k + 1 + i, k)] * pw[j];
+    // element x = i m + j of the trailing block, x = t, t + NT, ... (the
+    // row and column step by NT / m and NT % m)
+    {
+      const int di = NT / m, dj = NT % m;
+      int i = t / m, j = t % m;
+      while (i < m) {
+        Q[(k + 1 + i) * n + (k + 1 + j)] -= A[L(k + 1 + i, k)] * pw[j];
+        i += di;
+        j += dj;
+        if (j >= m) {
+          j -= m;
+          ++i;
+        }
+      }
     }
     __syncthreads();
   }
@@ -1643,13 +1660,18 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
     lo_hi[1] = hi;
   }
   __syncthreads();
-  for (int round = 0; round < 8; ++round) {
+  // six rounds of NT points narrow the interval by NT^6 ~ 1.8e16, to the
+  // rounding level of the spectrum
+  for (int round = 0; round < 6; ++round) {
     const double lo = lo_hi[0], hi = lo_hi[1];
     const double x = lo + (hi - lo) * (double)(t + 1) / (double)NT;
     const int c = sturm_count(dd, ee, n, x);
-    // the first point with at least one eigenvalue below it
+    // the first point with at least one eigenvalue below it (the count at
+    // the previous point is the previous thread's)
     __syncthreads();
-    if (c >= 1 && (t == 0 || sturm_count(dd, ee, n, lo + (hi - lo) * (double)t / (double)NT) == 0)) {
+    cnt[t] = c;
+    __syncthreads();
+    if (c >= 1 && (t == 0 || cnt[t - 1] == 0)) {
       lo_hi[0] = lo + (hi - lo) * (double)t / (double)NT;
       lo_hi[1] = x;
     }
