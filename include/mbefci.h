@@ -68,9 +68,12 @@ typedef struct {
                             against the other guesses                       */
   int32_t mode;          /* MBEFCI_BATCHED (default) or MBEFCI_PER_LAUNCH            */
   int32_t use_graph;     /* batched mode: replay captured iterations (default 1)     */
-  int32_t tile;          /* sigma tile width 32/64/128; 0 = autotuned schedule: the
-                            first batched solve of a plan times the candidates per
-                            active size and keeps the fastest (default 0)       */
+  int32_t tile;          /* sigma tile width 32/64/128 (one alpha string per tile);
+                            0 = autotuned schedule: the first batched solve of a
+                            plan times the candidates per active size (also
+                            flattened tiles of 32 or 64 consecutive
+                            determinants for active sizes up to 9) and keeps
+                            the fastest (default 0)                           */
   int32_t keep_ci;       /* keep converged CI vectors for the backward (default 1)   */
   int32_t validate;      /* host checks of integral symmetry/finiteness (default 1)  */
   int32_t sigma_pass_mb; /* sigma sweeps run in passes whose G block (the W-contracted
@@ -97,7 +100,8 @@ typedef struct {
                             0 = 65536 (default 0)                            */
   int64_t max_workspace; /* workspace cap in bytes, 0 = no cap                       */
   const char* tune_cache;/* autotuner cache file (read/written) or NULL: one line per
-                            active size n, "n tile tiles_per_workgroup"          */
+                            active size n, "n tile tiles_per_workgroup" (tile
+                            -32 or -64: flattened tiles)                      */
 } mbefci_opts;
 
 typedef struct {
@@ -254,7 +258,8 @@ int64_t mbefci_screened_tuples(mbefci_ctx* ctx, int32_t order, int32_t* tuples,
  * kernels run on).  Replays recompute identical values; the results of the
  * last call are unchanged.  Fills up to `cap` records, *count = records. */
 typedef struct {
-  char name[64];          /* kernel and shape, e.g. "sigma_dgemm<n=10,tile=64>"       */
+  char name[64];          /* kernel and shape, e.g. "sigma_dgemm<n=10,tile=64>",
+                             "sigma_dgemm_flat<n=8,tile=32>", "sigma_gather"        */
   int32_t launches;       /* launches of this kernel in one sigma sweep               */
   int32_t pad_;
   double ms_per_launch;   /* average device time of one launch                        */

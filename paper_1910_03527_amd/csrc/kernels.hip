@@ -585,6 +585,196 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
   }
 }
 
+// The same contraction on flattened tiles, for active spaces of at most 9
+// orbitals (short beta strings, where a tile of one alpha string leaves the
+// last beta block mostly empty): a tile is TN consecutive determinants
+// K = Ka Nb + Kb of one item and may cross alpha strings, so only an item's
+// last tile is ragged.  The whole beta pair table of the item is staged in LDS
+// once per work unit, and per tile the c rows it spans (a contiguous stretch of
+// c); the alpha pair entries and the alpha-half c values are per-lane loads,
+// fetched one tile ahead.  D+ and the MFMA contraction are formed from
+// the same operands in the same order as in k_sigma_dgemm, so G is identical.
+// Work units hold ranges of flat tile numbers of one item.
+template <int NACT, int TN>
+__global__ void __launch_bounds__(256) k_sigma_dgemm_flat(const Item* __restrict__ items,
+                                                          const Work* __restrict__ work,
+                                                          const double* __restrict__ warena,
+                                                          const double* __restrict__ V,
+                                                          int64_t ntot,
+                                                          double* __restrict__ Garena,
+                                                          const DavState* __restrict__ st,
+                                                          int slot) {
+  static_assert(NACT <= 9, "flattened tiles stage the whole beta pair table");
+  constexpr int NP = NACT * (NACT + 1) / 2;
+  constexpr int KPAD = (NP + 15) / 16 * 16;
+  constexpr int KS = (NP + 3) / 4;
+  constexpr int KR = KS * 4;
+  constexpr int NRB = KPAD / 16;
+  constexpr int RBW = (NRB + 3) / 4;
+  constexpr int NCB = TN / 16;
+  constexpr int NSUB = 256 / TN;
+  constexpr int NPER = (NP + NSUB - 1) / NSUB;
+  constexpr int LDT = TN + 1;
+  constexpr int CMAX = (int)binom_c(NACT, NACT / 2);
+  constexpr int CRMAX = TN + 2 * CMAX;                 // c rows a tile can touch
+  constexpr int CPT = (CRMAX + 255) / 256;
+  __shared__ double Ds[KR * LDT];
+  __shared__ int32_t Tb[NP * CMAX];  // beta pair table [pair][Kb]
+  __shared__ double Cr[CRMAX];       // c rows Ka_lo .. Ka_hi of the tile
+
+  const Work wk = work[blockIdx.x];
+  const Item& I = items[wk.item];
+  const DavState& S = st[wk.item];
+  if (!item_active(S, slot)) return;
+  const int vs = vec_slot(S, slot);
+  const double* __restrict__ c = V + (int64_t)vs * ntot + I.off;
+  double* __restrict__ G = Garena + I.goff;
+  const int Nb = I.Nb;
+  const int nd = (int)I.ndet;
+  const int32_t* __restrict__ pA = I.pairA;
+  const int32_t* __restrict__ pB = I.pairB;
+
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int col = t % TN;
+  const int sub = (TN >= 64) ? __builtin_amdgcn_readfirstlane(t / TN) : t / TN;
+  const int wrot = (wave + (int)blockIdx.x) & 3;
+  double wreg[RBW][KS];
+  const double* __restrict__ W = warena + I.woff;
+#pragma unroll
+  for (int r = 0; r < RBW; ++r) {
+    const int rb = wrot + 4 * r;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+      wreg[r][ks] = (rb < NRB) ? ldg(W + (rb * 16 + (lane & 15)) * KPAD + ks * 4 + (lane >> 4))
+                               : 0.0;
+  }
+  for (int x = t; x < NP * Nb; x += 256) Tb[x] = ldg(pB + x);
+  for (int x = NP * LDT + t; x < KR * LDT; x += 256) Ds[x] = 0.0;
+  __syncthreads();
+
+  // column position of this thread in a tile (past the item's end: the last
+  // determinant, with weight zero)
+  auto colpos = [&](int tile, int& ka, int& kb, double& kp) {
+    int k = tile * TN + col;
+    kp = k < nd ? 1.0 : 0.0;
+    if (k >= nd) k = nd - 1;
+    ka = k / Nb;
+    kb = k - ka * Nb;
+  };
+  // first alpha string of a tile (its c rows are staged from there)
+  auto row_lo = [&](int tile) { return (tile * TN) / Nb; };
+  int32_t ea[NPER];  // alpha pair-table entries of the tile
+  double ga[NPER];   // the c values they address (alpha half of D+)
+  double cr[CPT];    // this thread's share of the tile's c rows
+  auto load_entries = [&](int ka, int32_t (&xa)[NPER]) {
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) {
+      const int ab = sub + NSUB * i;
+      xa[i] = ab < NP ? ldg(pA + ka * NP + ab) : 0;
+    }
+  };
+  auto load_values = [&](int tile, int kb) {
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) ga[i] = ea[i] ? ldg(c + ((ea[i] >> 1) - 1) * Nb + kb) : 0.0;
+    const int lo = row_lo(tile) * Nb;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const int x = lo + t + 256 * j;
+      cr[j] = (t + 256 * j < CRMAX && x < nd) ? ldg(c + x) : 0.0;
+    }
+  };
+  int ka, kb;
+  double keep;
+  colpos(wk.begin, ka, kb, keep);
+  load_entries(ka, ea);
+  load_values(wk.begin, kb);
+
+  for (int tile = wk.begin; tile < wk.end; ++tile) {
+    const bool more = tile + 1 < wk.end;
+    int kan = 0, kbn = 0;
+    double keepn = 0.0;
+    int32_t ean[NPER];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j)
+      if (t + 256 * j < CRMAX) Cr[t + 256 * j] = cr[j];
+    if (more) {
+      colpos(tile + 1, kan, kbn, keepn);
+      load_entries(kan, ean);
+    } else {
+#pragma unroll
+      for (int i = 0; i < NPER; ++i) ean[i] = 0;
+    }
+    __syncthreads();
+    const int crow = (ka - row_lo(tile)) * Nb;  // this column's c row in Cr
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) {
+      const int ab = sub + NSUB * i;
+      if (ab < NP) {
+        const int32_t eb = Tb[ab * Nb + kb];
+        const int jb = eb ? (eb >> 1) - 1 : 0;
+        const double fa = ea[i] ? ((ea[i] & 1) ? -keep : keep) : 0.0;
+        const double fb = eb ? ((eb & 1) ? -keep : keep) : 0.0;
+        Ds[ab * LDT + col] = fa * ga[i] + fb * Cr[crow + jb];
+      }
+    }
+    __syncthreads();
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < NPER; ++i) ea[i] = ean[i];
+      ka = kan;
+      kb = kbn;
+      keep = keepn;
+      load_values(tile + 1, kb);
+    }
+#pragma unroll
+    for (int r = 0; r < RBW; ++r) {
+      const int rb = wrot + 4 * r;
+      if (rb >= NRB) continue;
+      double4_t acc[NCB];
+#pragma unroll
+      for (int cb2 = 0; cb2 < NCB; ++cb2) acc[cb2] = (double4_t){0.0, 0.0, 0.0, 0.0};
+      double bq[2][NCB];
+      const double* bbase = Ds + (lane >> 4) * LDT + (lane & 15);
+#pragma unroll
+      for (int cb2 = 0; cb2 < NCB; ++cb2) bq[0][cb2] = bbase[cb2 * 16];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        if (ks + 1 < KS) {
+#pragma unroll
+          for (int cb2 = 0; cb2 < NCB; ++cb2)
+            bq[(ks + 1) & 1][cb2] = bbase[(ks + 1) * 4 * LDT + cb2 * 16];
+        }
+#pragma unroll
+        for (int cb2 = 0; cb2 < NCB; ++cb2)
+          acc[cb2] = __builtin_amdgcn_mfma_f64_16x16x4f64(wreg[r][ks], bq[ks & 1][cb2], acc[cb2],
+                                                          0, 0, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x100, NCB, 0);
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        if (ks + 1 < KS) __builtin_amdgcn_sched_group_barrier(0x100, NCB, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, NCB, 0);
+      }
+#pragma unroll
+      for (int cb2 = 0; cb2 < NCB; ++cb2) {
+        const int Kc = tile * TN + cb2 * 16 + (lane & 15);
+        if (Kc < nd) {
+          const int kac = Kc / Nb, kbc = Kc - kac * Nb;
+          double* __restrict__ Grow = G + (int64_t)kac * NP * Nb + kbc;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = rb * 16 + (lane >> 4) + 4 * v;
+            if (row < NP) Grow[row * Nb] = acc[cb2][v];
+          }
+        }
+      }
+    }
+    // No barrier here: the next tile's Cr stores follow this tile's second
+    // barrier (every D+ read of Cr is done), and its D+ stores follow the
+    // next first barrier (every MFMA read of Ds is done).
+  }
+}
+
 // sigma_I = sum_{links (x,y,J,s) of Ia} s G_xy[J, Ib] + sum_{links of Ib} s G_xy[Ia, J]
 // One wave per 64-determinant segment of one alpha row (segments are
 // row-aligned), so the alpha string and its links are wave-uniform (scalar
@@ -2423,11 +2613,30 @@ static bool sigma_dgemm_n(int n, const Item* items, const Work* work, int nwork,
   }
 }
 
+template <int TN>
+static bool sigma_dgemm_flat_n(int n, const Item* items, const Work* work, int nwork,
+                               const double* warena, const double* V, int64_t ntot, double* G,
+                               const DavState* st, int slot, hipStream_t s) {
+  switch (n) {
+#define MBEFCI_CASE(N)                                                                       \
+  case N:                                                                                    \
+    hipLaunchKernelGGL((k_sigma_dgemm_flat<N, TN>), dim3(nwork), dim3(256), 0, s, items,     \
+                       work, warena, V, ntot, G, st, slot);                                  \
+    return true;
+    MBEFCI_CASE(2) MBEFCI_CASE(3) MBEFCI_CASE(4) MBEFCI_CASE(5) MBEFCI_CASE(6) MBEFCI_CASE(7)
+    MBEFCI_CASE(8) MBEFCI_CASE(9)
+#undef MBEFCI_CASE
+    default: return false;
+  }
+}
+
 bool launch_sigma_dgemm(int n, int tn, const Item* items, const Work* work, int nwork,
                         const double* warena, const double* V, int64_t ntot, double* G,
                         const DavState* st, int slot, hipStream_t s) {
   if (nwork <= 0) return true;
   switch (tn) {
+    case -32: return sigma_dgemm_flat_n<32>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
+    case -64: return sigma_dgemm_flat_n<64>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
     case 32: return sigma_dgemm_n<32>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
     case 64: return sigma_dgemm_n<64>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
     case 128:

@@ -21,6 +21,8 @@ void launch_casci_setup(int n, const double* const* h1s, const double* const* er
                         double* warena, hipStream_t s);
 void launch_hdiag(const Item* items, const Work* work, int nwork, const ItemHam* hams,
                   double* diag, hipStream_t s);
+// tn: 32, 64 or 128 columns of one alpha string per tile; -32 or -64: flattened
+// tiles of that many consecutive determinants (active spaces of at most 9)
 bool launch_sigma_dgemm(int n, int tn, const Item* items, const Work* work, int nwork,
                         const double* warena, const double* V, int64_t ntot, double* G,
                         const DavState* st, int slot, hipStream_t s);

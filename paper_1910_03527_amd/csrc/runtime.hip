@@ -236,7 +236,8 @@ void load_tune_cache(mbefci_ctx* c) {
   char line[128];
   while (std::fgets(line, sizeof(line), f))
     if (std::sscanf(line, "%d %d %d", &n, &tn, &tpw) == 3 && n >= 2 && n <= 14 &&
-        (tn == 32 || tn == 64 || tn == 128) && tpw >= 1 && tpw <= 256)
+        (tn == 32 || tn == 64 || tn == 128 || ((tn == -32 || tn == -64) && n <= 9)) &&
+        tpw >= 1 && tpw <= 256)
       c->tuned[n] = {tn, tpw};
   std::fclose(f);
 }
@@ -244,7 +245,8 @@ void save_tune_cache(mbefci_ctx* c) {
   if (!c->opts.tune_cache) return;
   FILE* f = std::fopen(c->opts.tune_cache, "w");
   if (!f) return;
-  std::fprintf(f, "# n tile tiles_per_workgroup (sigma contraction schedule, gfx950)\n");
+  std::fprintf(f, "# n tile tiles_per_workgroup (sigma contraction schedule, gfx950; a negative\n"
+                 "# tile is that many consecutive determinants per flattened tile)\n");
   for (auto& kv : c->tuned) std::fprintf(f, "%d %d %d\n", kv.first, kv.second.first, kv.second.second);
   std::fclose(f);
 }
@@ -253,12 +255,22 @@ void save_tune_cache(mbefci_ctx* c) {
 // Sigma-contraction work units of group gi: tiles (one alpha string x tn beta
 // strings) numbered column-major, tile = block * Na + Ka; a unit covers
 // tiles_per_wg alpha strings of one beta block and never crosses a block.
+// With flattened tiles (tn < 0) tile f holds determinants f|tn| .. f|tn|+|tn|-1
+// of the item and a unit covers tiles_per_wg consecutive tiles.
 void build_tiles(Plan& P, int gi) {
   Group& g = P.groups[gi];
   g.tiles.clear();
   for (int i = 0; i < P.nitem; ++i) {
     if (P.item_group[i] != gi) continue;
     const Item& I = P.items[i];
+    if (g.tn < 0) {
+      const int nt = (int)((I.ndet - g.tn - 1) / -g.tn);
+      g.item_lo[i] = (int)g.tiles.size();
+      for (int a = 0; a < nt; a += g.tiles_per_wg)
+        g.tiles.push_back(Work{i, a, std::min(a + g.tiles_per_wg, nt), 0});
+      g.item_hi[i] = (int)g.tiles.size();
+      continue;
+    }
     const int nblk = (I.Nb + g.tn - 1) / g.tn;
     g.item_lo[i] = (int)g.tiles.size();
     for (int bk = 0; bk < nblk; ++bk)
@@ -566,8 +578,9 @@ void autotune(mbefci_ctx* c, Plan& P) {
     }
     float best = 1e30f;
     std::pair<int, int> pick{g.tn, g.tiles_per_wg};
-    for (int tn : {32, 64, 128}) {
+    for (int tn : {32, 64, 128, -32, -64}) {
       if (tn == 128 && g.n >= 13) continue;
+      if (tn < 0 && g.n > 9) continue;
       for (int tpw : {4, 8, 16, 32}) {
         g.tn = tn;
         g.tiles_per_wg = tpw;
@@ -1617,7 +1630,8 @@ int mbefci_time_kernels(mbefci_ctx* c, int32_t reps, mbefci_kernel_time* out, in
         const double np = g.n * (g.n + 1) / 2;
         flops = 2.0 * np * np * nd;
         bytes = 8.0 * (1.0 + np) * nd;  // c read once, G written once
-        name = "sigma_dgemm<n=" + std::to_string(g.n) + ",tile=" + std::to_string(g.tn) + ">";
+        name = (g.tn < 0 ? "sigma_dgemm_flat<n=" : "sigma_dgemm<n=") + std::to_string(g.n) +
+               ",tile=" + std::to_string(g.tn < 0 ? -g.tn : g.tn) + ">";
       } else {
         for (int w = L.lo; w < L.lo + L.cnt; ++w)
           if (P.segs[w].begin == 0) {

@@ -31,10 +31,46 @@ def test_autotune_cache_and_bitwise_results(tmp_path):
     c.close()
     assert r0["increments"] == r1["increments"] and r0["e_order"] == r1["e_order"]
     lines = [l.split() for l in cache.read_text().splitlines() if not l.startswith("#")]
-    assert lines and all(len(l) == 3 and int(l[1]) in (32, 64, 128) for l in lines)
+    assert lines and all(len(l) == 3 and int(l[1]) in (32, 64, 128, -32, -64) for l in lines)
     # a new context reads the cache and does not time again
     c2 = Context(0, tile=0, tune_cache=str(cache))
     r2 = c2.mbe_forward(h, g, p.occ, p.ref, p.exp, p.max_order, want_increments=True)
     assert c2.last_stats["ms_tune"] < 50.0
     c2.close()
     assert r2["increments"] == r1["increments"]
+
+
+def _forced_cache(path, tile, tpw):
+    path.write_text("".join(f"{n} {tile} {tpw}\n" for n in range(2, 10)))
+    return str(path)
+
+
+@pytest.mark.parametrize("tile", [-32, -64])
+def test_flat_tiles_bitwise(tmp_path, tile):
+    """Flattened tiles (forced through the cache for every active size up to
+    9, with an odd number of tiles per workgroup so units end raggedly) give
+    the same G, hence bitwise the same energies, as one-alpha-string tiles."""
+    from paper_1910_03527_amd import Context
+    cache = _forced_cache(tmp_path / "flat.txt", tile, 3)
+    for name in ("hubbard8", "hubbard12"):
+        p = W.problem(name)
+        h, g = _dev(p.h1), _dev(p.eri)
+        ref = Context(0, tile=64)
+        r0 = ref.mbe_forward(h, g, p.occ, p.ref, p.exp, p.max_order, want_increments=True)
+        ref.close()
+        c = Context(0, tile=0, tune_cache=cache)
+        r1 = c.mbe_forward(h, g, p.occ, p.ref, p.exp, p.max_order, want_increments=True)
+        assert c.last_stats["ms_tune"] < 50.0  # read from the cache, not timed
+        c.close()
+        assert r0["increments"] == r1["increments"] and r0["e_order"] == r1["e_order"], name
+    # the largest flattened shape: 9 orbitals, C(9,4)^2 = 15,876 determinants
+    hs, gs = W.synthetic(9, 99)
+    ref = Context(0, tile=64)
+    e0 = ref.casci([_dev(hs)], [_dev(gs)], 4, 4)
+    ref.close()
+    c = Context(0, tile=0, tune_cache=cache)
+    e1 = c.casci([_dev(hs)], [_dev(gs)], 4, 4)
+    names = [k["name"] for k in c.time_kernels(reps=1)]
+    c.close()
+    assert e0 == e1
+    assert f"sigma_dgemm_flat<n=9,tile={-tile}>" in names
