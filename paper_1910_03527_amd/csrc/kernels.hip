@@ -1097,6 +1097,17 @@ __global__ void k_dav_rr(const Item* __restrict__ items, int ibase,
   }
 }
 
+// Subspace size at which a CASCI restarts.  For active spaces of at most 9
+// orbitals a sigma evaluation (2 npair^2 flops and ~8 npair bytes per
+// determinant) costs little next to the 4m + 4 vector passes of an iteration,
+// so these restart at 8 vectors (more iterations, fewer passes); larger ones
+// use the whole subspace.
+__device__ __forceinline__ int subspace_cap(const Item& I, const DavState& S, int mmax) {
+  if (I.n > 9) return mmax;
+  const int c = S.nguess + 2 > 8 ? S.nguess + 2 : 8;
+  return c < mmax ? c : mmax;
+}
+
 // Restart: when the subspace is full, collapse it onto the Ritz vector
 // x = V y (and H x = S y) in slot 0.
 __global__ void __launch_bounds__(256) k_dav_collapse(const Item* __restrict__ items,
@@ -1106,7 +1117,7 @@ __global__ void __launch_bounds__(256) k_dav_collapse(const Item* __restrict__ i
   const Work wk = work[blockIdx.x];
   const Item& I = items[wk.item];
   const DavState& S = st[wk.item];
-  if (S.conv || S.m < mmax) return;
+  if (S.conv || S.m < subspace_cap(I, S, mmax)) return;
   const int64_t e0 = (int64_t)(wk.begin - I.chunk0) * kChunk;
   const int64_t e1 = min(e0 + kChunk, I.ndet);
   for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
@@ -1119,12 +1130,13 @@ __global__ void __launch_bounds__(256) k_dav_collapse(const Item* __restrict__ i
     Sv[I.off + e] = sx;
   }
 }
-__global__ void k_dav_collapse_state(DavState* st, int ibase, int nitem, int mmax) {
+__global__ void k_dav_collapse_state(const Item* __restrict__ items, DavState* st, int ibase,
+                                     int nitem, int mmax) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nitem) return;
   i += ibase;
   DavState& S = st[i];
-  if (S.conv || S.m < mmax) return;
+  if (S.conv || S.m < subspace_cap(items[i], S, mmax)) return;
   S.m = 1;
   S.Hs[0] = S.theta;
   S.y[0] = 1.0;
@@ -2691,7 +2703,8 @@ void launch_dav_iteration(const Item* items, int ibase, int nitem, const Work* c
   const int nb = nblk(nitem, 64);
   hipLaunchKernelGGL(k_dav_collapse, dim3(nchunk), dim3(256), 0, s, items, chunks, V, Sv, ntot, st,
                      mmax);
-  hipLaunchKernelGGL(k_dav_collapse_state, dim3(nb), dim3(64), 0, s, st, ibase, nitem, mmax);
+  hipLaunchKernelGGL(k_dav_collapse_state, dim3(nb), dim3(64), 0, s, items, st, ibase, nitem,
+                     mmax);
   if (Rb && Xb) {
     hipLaunchKernelGGL(k_dav_residual_olsen, dim3(nchunk), dim3(256), 0, s, items, chunks, V, Sv,
                        diag, ntot, st, Rb, Xb, part);
