@@ -1699,7 +1699,7 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
   const int it = ibase + blockIdx.x;
   const Item& I = items[it];
   DavState& S = st[it];
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int t = threadIdx.x, lane = t & 63;
   const int64_t nd = I.ndet;
   const int32_t* __restrict__ idx = pidx + (int64_t)it * PM;
   if (nd == 1) {  // nothing to solve: the single determinant
@@ -2020,7 +2020,6 @@ __global__ void __launch_bounds__(256) k_rdm_syrk(const Item* __restrict__ items
                                                   double* __restrict__ part) {
   constexpr int NP = NACT * (NACT + 1) / 2;
   constexpr int KPAD = (NP + 15) / 16 * 16;
-  constexpr int KR = ((NP + 1) + 3) / 4 * 4;  // D+ rows plus the c row
   constexpr int NRB = KPAD / 16;
   constexpr int NBLK = NRB * (NRB + 1) / 2;   // upper 16x16 blocks
   constexpr int BPW = (NBLK + 3) / 4;         // blocks per wave
@@ -2372,7 +2371,7 @@ __global__ void k_mbe_order_sums(const BucketDev* __restrict__ buckets, int nbuc
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) e_order[n - 1] = red[0];
@@ -2387,7 +2386,7 @@ __global__ void k_count_active(const DavState* __restrict__ st, int ibase, int n
   red[threadIdx.x] = c;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = red[0];
