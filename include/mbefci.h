@@ -194,7 +194,11 @@ int mbefci_casci_rdm(mbefci_ctx* ctx, double* const* rdm1s, double* const* rdm2s
  * e_total = e_ref + sum e_order, tuple_incr [num_tuples] or NULL (order by
  * order, lexicographic tuples of the sorted X within an order) and
  * tuple_energy [num_tuples] or NULL (the CASCI energies E(R u T), same order).  Converged
- * CI vectors are kept on ctx for mbefci_mbe_backward when keep_ci is set. */
+ * CI vectors are kept on ctx for mbefci_mbe_backward when keep_ci is set.
+ * Every CASCI is solved in one batch (Davidson subspace, sigma intermediates
+ * and kept CI vectors of all tuples at once); an expansion too large for the
+ * device gives ENOMEM.  mbefci_mbe_screened with t_init = 0 computes the same
+ * energies order by order in bounded batches (no backward). */
 int mbefci_mbe_forward(mbefci_ctx* ctx, const mbefci_problem* prob, double* e_ref,
                        double* e_order, double* e_total, double* tuple_incr,
                        double* tuple_energy, mbefci_stats* stats, void* hip_stream);
@@ -234,6 +238,8 @@ int mbefci_partition(int32_t type, int32_t norb, int32_t nocc, const int32_t* oc
  * n_order [max_order] (tuples computed per order).  The computed tuples and
  * their increments stay on ctx for mbefci_screened_tuples; the call drops the
  * cached plan of mbefci_mbe_forward (no backward follows a screened call).
+ * Each order is solved in batches of at most opts.screen_batch CASCIs and
+ * 2^25 determinants, so device memory bounds the batch, not the expansion.
  * Errors: EINVAL for t_init < 0, a < 1, m_init < 0 or a bad problem. */
 typedef struct {
   double t_init;          /* T_init in E_h (the paper: 1e-10)                         */
