@@ -73,6 +73,51 @@ def _traffic(kernel_name, workload):
     return None
 
 
+def _copy_calibration(dev):
+    """One plain device copy of 512 MiB: the reference the HBM byte counters
+    of a kernel-replay run are scaled by."""
+    import torch
+    src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    return src.numel() * 8
+
+
+def kernel_replay_cas14x8(args):
+    """Kernel-replay mode for the 8 x CAS(14e,14o) batch: one batched solve
+    stopped after its guess sweeps, then the sigma kernels of the whole batch
+    re-timed."""
+    import torch
+    import workloads as W
+    from paper_1910_03527_amd import Context
+    dev = torch.device("cuda", 0)
+    probs = [W.problem("cas14", i) for i in range(8)]
+    ctx = Context(0, tile=args.tile, tune_cache=args.tune_cache, conv_tol=1e3)
+    hs = [torch.as_tensor(q.h1, device=dev) for q in probs]
+    gs = [torch.as_tensor(q.eri, device=dev) for q in probs]
+    ctx.casci(hs, gs, 7, 7)
+    kt = ctx.time_kernels(args.reps)
+    nbytes = _copy_calibration(dev)
+    ctx.close()
+    print(json.dumps({"mode": "kernel-replay", "copy_bytes_each_way": nbytes,
+                      "workload": "cas14x8", "reps": args.reps, "kernels": kt}), flush=True)
+
+
+def _kernel_rows(kt, workload):
+    """Per-kernel rates of one re-timed sigma sweep, with the measured HBM
+    rate where a counter record of that kernel and workload exists."""
+    rows = []
+    for k in kt:
+        s = k["ms_per_launch"] * 1e-3
+        tr = _traffic(k["name"], workload)
+        rows.append({"name": k["name"], "ms_per_launch": round(k["ms_per_launch"], 4),
+                     "tflops": round(k["flops"] / s / 1e12, 3),
+                     "gbps": round(k["bytes"] / s / 1e9, 1),
+                     "gbps_hbm_measured": round(tr / s / 1e9, 1) if tr else None})
+    return rows
+
+
 def _buckets(prob):
     occ = set(prob.occ)
     xo = sorted(p for p in prob.exp if p in occ)
@@ -158,6 +203,8 @@ def main():
     import workloads as W
     from paper_1910_03527_amd import PER_LAUNCH, BATCHED, Context
 
+    if args.kernel_replay and args.workload == "cas14x8":
+        return kernel_replay_cas14x8(args)
     prob = W.problem(args.workload)
     nsolve_expected = 1 + sum(math.comb(len(prob.exp), n) for n in range(1, prob.max_order + 1))
     # the oracle runs first, in worker processes forked before this process
@@ -183,12 +230,8 @@ def main():
         ctx.set_opts(conv_tol=1e3)
         ctx.mbe_forward(h1, eri, prob.occ, prob.ref, prob.exp, prob.max_order, prob.e_const)
         kt = ctx.time_kernels(args.reps)
-        # calibration for HBM byte counters: one plain device copy of 512 MiB
-        src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"mode": "kernel-replay", "copy_bytes_each_way": src.numel() * 8, "workload": args.workload,
+        nbytes = _copy_calibration(dev)
+        print(json.dumps({"mode": "kernel-replay", "copy_bytes_each_way": nbytes, "workload": args.workload,
                           "sigma_pass_mb": args.sigma_pass_mb, "reps": args.reps,
                           "kernels": kt}), flush=True)
         return
@@ -364,6 +407,8 @@ def main():
                                  "step": "forward + backward" if grad else "forward",
                                  "ncasci": int(sc["ntuples"]), "max_order": cp.max_order,
                                  "sigma_calls": sc["sigma_calls"], "e_total": rc["e_total"]}
+                if name == "synthetic40":
+                    configs[name]["kernels"] = _kernel_rows(cctx.time_kernels(2), name)
             finally:
                 cctx.close()
         # 8 x CAS(14e,14o): one batched solve plus the RDMs, and the sigma
@@ -387,10 +432,7 @@ def main():
                 "step": "forward + RDMs", "ndet_each": 11778624,
                 "sigma_calls": sc["sigma_calls"], "max_iters": sc["max_iters"],
                 "energies": ec,
-                "kernels": [{"name": k["name"], "ms_per_launch": round(k["ms_per_launch"], 4),
-                             "tflops": round(k["flops"] / (k["ms_per_launch"] * 1e-3) / 1e12, 3),
-                             "gbps": round(k["bytes"] / (k["ms_per_launch"] * 1e-3) / 1e9, 1)}
-                            for k in kc]}
+                "kernels": _kernel_rows(kc, "cas14x8")}
         finally:
             cctx.close()
 

@@ -73,7 +73,8 @@ typedef struct {
                             plan times the candidates per active size (also
                             flattened tiles of 32 or 64 consecutive
                             determinants for active sizes up to 9) and keeps
-                            the fastest (default 0)                           */
+                            the fastest; a later candidate must be 3% faster
+                            to replace an earlier one (default 0)             */
   int32_t keep_ci;       /* keep converged CI vectors for the backward (default 1)   */
   int32_t validate;      /* host checks of integral symmetry/finiteness (default 1)  */
   int32_t sigma_pass_mb; /* sigma sweeps run in passes whose G block (the W-contracted

@@ -1482,41 +1482,32 @@ __device__ inline uint64_t order_key(double x) {
   return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
 }
 
-// Selection of the np lowest (diagonal, address) keys of one item, by radix
-// select over the 96-bit key (order_key(H_II) << 32 | address) in 8-bit
-// digits (12 histogram passes), then a rank sort of the np survivors.
-// One 256-thread block per item; pidx[item][k] receives the addresses in
-// ascending key order.
-__global__ void __launch_bounds__(256) k_pspace_select(const Item* __restrict__ items, int ibase,
-                                                       const double* __restrict__ diag,
-                                                       int32_t* __restrict__ pidx, int pmax) {
-  const int it = ibase + blockIdx.x;
-  const Item& I = items[it];
-  const int64_t nd = I.ndet;
-  // small CASCIs: every determinant; larger ones: pmax (at least the eight
-  // lowest, the unit guesses when the P-space is not used)
-  const int np = nd <= kMaxPspace ? (int)nd : (pmax > 8 ? pmax : 8);
-  const double* __restrict__ d = diag + I.off;
+// The np lowest of n distinct 96-bit keys (key_at(i) -> order_key(H_II) and
+// address) by radix select in 8-bit digits (12 histogram passes: 8 over the
+// value key from the top, 4 over the address), then every key up to the np-th
+// is collected, unordered, into khi/klo (exactly min(np, n) of them).
+// 256 threads.
+template <class KeyAt>
+__device__ void select_lowest(const KeyAt& key_at, int64_t n, int np, uint64_t* khi,
+                              uint32_t* klo) {
   const int t = threadIdx.x;
   __shared__ uint32_t hist[256];
   __shared__ uint64_t pre_hi;
   __shared__ uint32_t pre_lo;
   __shared__ int64_t need;
   __shared__ uint32_t ncol;
-  __shared__ uint64_t khi[kMaxPspace];
-  __shared__ uint32_t klo[kMaxPspace];
   if (t == 0) { pre_hi = 0; pre_lo = 0; need = np; ncol = 0; }
   __syncthreads();
-  if (np < nd) {
-    // digits 0..7: the value key from the top; digits 8..11: the address
+  if (np < n) {
     for (int dg = 0; dg < 12; ++dg) {
       hist[t] = 0;
       __syncthreads();
       const uint64_t ph = pre_hi;
       const uint32_t pl = pre_lo;
-      for (int64_t K = t; K < nd; K += 256) {
-        const uint64_t kh = order_key(d[K]);
-        const uint32_t kl = (uint32_t)K;
+      for (int64_t K = t; K < n; K += 256) {
+        uint64_t kh;
+        uint32_t kl;
+        key_at(K, kh, kl);
         bool match;
         int b;
         if (dg < 8) {
@@ -1549,18 +1540,99 @@ __global__ void __launch_bounds__(256) k_pspace_select(const Item* __restrict__ 
     pre_lo = ~0u;
   }
   __syncthreads();
-  // collect every key <= the np-th smallest (exactly np of them)
   const uint64_t ph = pre_hi;
   const uint32_t pl = pre_lo;
-  for (int64_t K = t; K < nd; K += 256) {
-    const uint64_t kh = order_key(d[K]);
-    const uint32_t kl = (uint32_t)K;
+  for (int64_t K = t; K < n; K += 256) {
+    uint64_t kh;
+    uint32_t kl;
+    key_at(K, kh, kl);
     if (kh < ph || (kh == ph && kl <= pl)) {
       const uint32_t slot = atomicAdd(&ncol, 1u);
       if (slot < (uint32_t)kMaxPspace) { khi[slot] = kh; klo[slot] = kl; }
     }
   }
   __syncthreads();
+}
+
+// P-space size requested from the selection: every determinant of a small
+// CASCI, else pmax (at least the eight lowest, the unit guesses when the
+// P-space is not used).
+__device__ __forceinline__ int select_count(int64_t nd, int pmax) {
+  return nd <= kMaxPspace ? (int)nd : (pmax > 8 ? pmax : 8);
+}
+
+// First phase for CASCIs of more than kSelectChunk determinants: one block per
+// chunk of kSelectChunk addresses writes the chunk's np lowest keys to the
+// item's candidate slots (chunk c of an item whose slots start at s:
+// slot s + c, kMaxPspace keys each; unused keys are the sentinel ~0, which is
+// never selected since the item has at least np real keys).  Work: item,
+// chunk index, first slot of the item.
+__global__ void __launch_bounds__(256) k_pspace_select_chunk(const Item* __restrict__ items,
+                                                             const Work* __restrict__ work,
+                                                             int ibase, int nitem,
+                                                             const double* __restrict__ diag,
+                                                             uint64_t* __restrict__ cand_hi,
+                                                             uint32_t* __restrict__ cand_lo,
+                                                             int pmax) {
+  const Work wk = work[blockIdx.x];
+  if (wk.item < ibase || wk.item >= ibase + nitem) return;
+  const Item& I = items[wk.item];
+  const int np = select_count(I.ndet, pmax);
+  const int64_t lo = (int64_t)wk.begin * kSelectChunk;
+  const int64_t hi = min(I.ndet, lo + kSelectChunk);
+  const double* __restrict__ d = diag + I.off;
+  __shared__ uint64_t khi[kMaxPspace];
+  __shared__ uint32_t klo[kMaxPspace];
+  auto key_at = [&](int64_t i, uint64_t& kh, uint32_t& kl) {
+    kh = order_key(d[lo + i]);
+    kl = (uint32_t)(lo + i);
+  };
+  const int64_t n = hi - lo;
+  select_lowest(key_at, n, np, khi, klo);
+  const int got = n < np ? (int)n : np;
+  const int64_t s = ((int64_t)wk.end + wk.begin) * kMaxPspace;
+  for (int j = threadIdx.x; j < kMaxPspace; j += 256) {
+    cand_hi[s + j] = j < got ? khi[j] : ~0ull;
+    cand_lo[s + j] = j < got ? klo[j] : ~0u;
+  }
+}
+
+// Selection of the np lowest (diagonal, address) keys of one item, then a rank
+// sort of the np survivors; pidx[item][k] receives the addresses in ascending
+// key order.  One 256-thread block per item.  An item with candidate slots
+// (cand_slot[item] >= 0, filled by k_pspace_select_chunk) selects among them;
+// the others read the diagonal directly.
+__global__ void __launch_bounds__(256) k_pspace_select(const Item* __restrict__ items, int ibase,
+                                                       const double* __restrict__ diag,
+                                                       int32_t* __restrict__ pidx, int pmax,
+                                                       const int32_t* __restrict__ cand_slot,
+                                                       const uint64_t* __restrict__ cand_hi,
+                                                       const uint32_t* __restrict__ cand_lo) {
+  const int it = ibase + blockIdx.x;
+  const Item& I = items[it];
+  const int64_t nd = I.ndet;
+  const int np = select_count(nd, pmax);
+  const int t = threadIdx.x;
+  __shared__ uint64_t khi[kMaxPspace];
+  __shared__ uint32_t klo[kMaxPspace];
+  const int slot = cand_slot ? cand_slot[it] : -1;
+  if (slot >= 0) {
+    const int64_t nchunk = (nd + kSelectChunk - 1) / kSelectChunk;
+    const uint64_t* __restrict__ ch = cand_hi + (int64_t)slot * kMaxPspace;
+    const uint32_t* __restrict__ cl = cand_lo + (int64_t)slot * kMaxPspace;
+    auto key_at = [&](int64_t i, uint64_t& kh, uint32_t& kl) {
+      kh = ch[i];
+      kl = cl[i];
+    };
+    select_lowest(key_at, nchunk * kMaxPspace, np, khi, klo);
+  } else {
+    const double* __restrict__ d = diag + I.off;
+    auto key_at = [&](int64_t i, uint64_t& kh, uint32_t& kl) {
+      kh = order_key(d[i]);
+      kl = (uint32_t)i;
+    };
+    select_lowest(key_at, nd, np, khi, klo);
+  }
   // rank sort (keys are distinct)
   if (t < np) {
     const uint64_t kh = khi[t];
@@ -2689,8 +2761,13 @@ void launch_dav_rr(const Item* items, int ibase, int nitem, const double* part, 
 }
 void launch_pspace_setup(const Item* items, int ibase, int nitem, const ItemHam* hams,
                          const double* diag, int32_t* pidx, double* pQ, double* pT, double* V,
-                         int64_t ntot, DavState* st, int pmax, int nunit, hipStream_t s) {
-  hipLaunchKernelGGL(k_pspace_select, dim3(nitem), dim3(256), 0, s, items, ibase, diag, pidx, pmax);
+                         int64_t ntot, DavState* st, int pmax, int nunit,
+                         const PspaceSelect& sel, hipStream_t s) {
+  if (sel.nwork > 0)
+    hipLaunchKernelGGL(k_pspace_select_chunk, dim3(sel.nwork), dim3(256), 0, s, items, sel.work,
+                       ibase, nitem, diag, sel.hi, sel.lo, pmax);
+  hipLaunchKernelGGL(k_pspace_select, dim3(nitem), dim3(256), 0, s, items, ibase, diag, pidx, pmax,
+                     sel.slot, sel.hi, sel.lo);
   hipLaunchKernelGGL(k_pspace_eigen, dim3(nitem), dim3(kPspaceThreads), 0, s, items, ibase, hams,
                      diag, pidx, pQ, pT, V, ntot, st, pmax, nunit);
 }

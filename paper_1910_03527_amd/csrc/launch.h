@@ -46,9 +46,21 @@ struct PspaceArgs {
   const double* pT;
   double* pdots;
 };
+// chunked P-space selection of large CASCIs: per chunk of kSelectChunk
+// determinants a work unit (item, chunk, first candidate slot of the item),
+// per item its first slot or -1, and the candidate keys (kMaxPspace per slot)
+constexpr int64_t kSelectChunk = 65536;
+struct PspaceSelect {
+  const Work* work;
+  int nwork;
+  const int32_t* slot;
+  uint64_t* hi;
+  uint32_t* lo;
+};
 void launch_pspace_setup(const Item* items, int ibase, int nitem, const ItemHam* hams,
                          const double* diag, int32_t* pidx, double* pQ, double* pT, double* V,
-                         int64_t ntot, DavState* st, int pmax, int nunit, hipStream_t s);
+                         int64_t ntot, DavState* st, int pmax, int nunit,
+                         const PspaceSelect& sel, hipStream_t s);
 void launch_dav_iteration(const Item* items, int ibase, int nitem, const Work* chunks, int nchunk,
                           double* V, double* Sv, const double* diag, int64_t ntot, DavState* st,
                           double* part, double tol, int max_iter, int mmax, double* Rb,
