@@ -13,6 +13,8 @@ path (needs an MI355X), with the paper's screening parameters (T_init =
   the energy per site lies above the Lieb-Wu thermodynamic limit by less
   than the open chain's boundary term allows (a loose check: no exact
   22-site energy is available here).
+* 46 sites (the paper's largest lattice), orders 2..4: the same sampled
+  increments, spawning replay and loose bound.
 * The solve batches of an order (opts.screen_batch) do not change results.
 """
 import itertools
@@ -99,12 +101,12 @@ def test_pm22_spawning_replayed(lattice22):
     assert got["n_order"][1] == 11 * 11  # the mixed pairs
 
 
-def test_pm22_sampled_increments(lattice22):
-    p, got = lattice22
+def _sampled_increments(p, got, per_order):
+    """Recompute sampled increments with the oracle from the CASCI energies of
+    each tuple and its computed sub-tuples (Eq. 2) and compare."""
     computed = set()
     inc_of = {}
-    for n in range(6):
-        tu, inc = got["per_order"][n]
+    for tu, inc in got["per_order"]:
         for row, d in zip(tu, inc):
             t = tuple(int(x) for x in row)
             computed.add(t)
@@ -113,7 +115,7 @@ def test_pm22_sampled_increments(lattice22):
     assert abs(got["e_ref"] - e_ref) < 1e-9
     rng = np.random.default_rng(7)
     sample = []
-    for n, cnt in ((2, 6), (3, 6), (4, 5), (5, 4), (6, 3)):
+    for n, cnt in per_order:
         tu = got["per_order"][n - 1][0]
         for i in rng.choice(len(tu), size=cnt, replace=False):
             sample.append(tuple(int(x) for x in tu[i]))
@@ -140,6 +142,27 @@ def test_pm22_sampled_increments(lattice22):
     for t in sample:
         _log("  sampled tuple", t)
         assert abs(increment(t) - inc_of[t]) < 1e-9, t
+
+
+def test_pm22_sampled_increments(lattice22):
+    p, got = lattice22
+    _sampled_increments(p, got, ((2, 6), (3, 6), (4, 5), (5, 4), (6, 3)))
+
+
+def test_pm46_sampled_increments_and_spawning(ctx):
+    """The paper's largest lattice (46 sites, M = 46), orders 2..4."""
+    p = W.problem("hubbard46_pm")
+    _log("pm lattice 46 sites, orders 2..4")
+    got = _run(ctx, p, 4)
+    assert got["n_order"][1] == 23 * 23
+    occ = set(p.occ)
+    for n in range(1, 3):
+        tu, inc = got["per_order"][n]
+        prev = {tuple(int(x) for x in row): d for row, d in zip(tu, inc)}
+        nxt = [tuple(int(x) for x in row) for row in got["per_order"][n + 1][0]]
+        assert screen.spawn(prev, p.exp, occ, p.ref, T_INIT, M_INIT, A) == nxt, n + 2
+    _sampled_increments(p, got, ((2, 5), (3, 5), (4, 5)))
+    assert 0.0 < got["e_total"] / p.norb - W.lieb_wu_energy(2.0) < 0.05
 
 
 def test_pm22_energy_per_site_vs_lieb_wu(lattice22):
