@@ -1,0 +1,95 @@
+"""Solver options of the HIP path (needs an MI355X).  Options change how the
+Davidson iteration gets to the eigenpair, never the eigenpair itself:
+
+* the Olsen correction (precond = 1) and the diagonal/P-space correction
+  (precond = 0) give the same energies to the convergence tolerance;
+* replaying captured graphs (use_graph = 1) and launching every kernel
+  (use_graph = 0) run the same kernels in the same order: bitwise equal;
+* more guess vectors or a smaller subspace change only the iteration count;
+* forced tile widths give bitwise the autotuned results (the contraction
+  order over pairs does not depend on the tiling).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL = 1e-9
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _forward(p, **opts):
+    from paper_1910_03527_amd import Context
+    c = Context(0, conv_tol=TOL, **opts)
+    try:
+        r = c.mbe_forward(_dev(p.h1), _dev(p.eri), p.occ, p.ref, p.exp, p.max_order,
+                          p.e_const, want_increments=True)
+        r["stats"] = dict(c.last_stats)
+    finally:
+        c.close()
+    return r
+
+
+@pytest.fixture(scope="module")
+def hub12():
+    p = W.problem("hubbard12")
+    _log("options: hubbard12 reference run")
+    return p, _forward(p)
+
+
+@pytest.mark.parametrize("opts", [{"precond": 1}, {"nguess": 3, "max_space": 6},
+                                  {"max_space": 4}, {"pspace": 0}])
+def test_options_reach_the_same_energies(hub12, opts):
+    p, ref = hub12
+    _log("options", opts)
+    got = _forward(p, **opts)
+    assert got["stats"]["first_failed"] == -1
+    # per-CASCI energy errors are ~|r|^2 / gap; increments and order sums
+    # combine a few thousand of them with binomial weights
+    assert np.max(np.abs(np.array(got["increments"]) - np.array(ref["increments"]))) < 1e-10
+    assert max(abs(a - b) for a, b in zip(got["e_order"], ref["e_order"])) < 1e-9
+    assert abs(got["e_total"] - ref["e_total"]) < 1e-9
+
+
+def test_graph_replay_is_bitwise_plain_launches(hub12):
+    p, ref = hub12
+    got = _forward(p, use_graph=0)
+    assert got["increments"] == ref["increments"] and got["e_order"] == ref["e_order"]
+    assert ref["stats"]["graph_launches"] > 0 and got["stats"]["graph_launches"] == 0
+
+
+@pytest.mark.parametrize("tile", [32, 64, 128])
+def test_forced_tiles_bitwise(hub12, tile):
+    p, ref = hub12
+    got = _forward(p, tile=tile)
+    assert got["increments"] == ref["increments"], tile
+
+
+def test_olsen_casci_batch():
+    """Larger CASCIs (synthetic CAS(10,10), 63,504 determinants) through the
+    Olsen correction and through the P-space correction."""
+    from paper_1910_03527_amd import Context
+    probs = [W.synthetic(10, s) for s in (3, 4)]
+    es = []
+    for opts in ({"precond": 0}, {"precond": 1}):
+        c = Context(0, conv_tol=TOL, **opts)
+        try:
+            es.append(c.casci([_dev(h) for h, _ in probs], [_dev(g) for _, g in probs], 5, 5))
+            assert c.last_stats["first_failed"] == -1
+        finally:
+            c.close()
+    assert max(abs(a - b) for a, b in zip(*es)) < 1e-10
