@@ -141,6 +141,18 @@ void mbefci_destroy(mbefci_ctx* ctx);
 /* Message of the last failure on ctx (valid until the next call on ctx). */
 const char* mbefci_last_error(const mbefci_ctx* ctx);
 int mbefci_set_opts(mbefci_ctx* ctx, const mbefci_opts* opts);
+/* Workspace allocator (the context's arenas: Davidson vectors, sigma
+ * intermediates, kept CI vectors, per-CASCI state): alloc(bytes, user) returns
+ * device memory of the context's device, aligned to at least 256 bytes, or NULL
+ * (the call that needed it then fails with ENOMEM); release(ptr, user) takes
+ * back a block, called only after the library stream has finished every queued
+ * use of it.  Both NULL: hipMalloc/hipFree (the default).  The small string and
+ * link tables always come from hipMalloc.  Setting or clearing the allocator
+ * releases every arena through the function that allocated it and drops the
+ * cached plan (a backward must follow a new forward).  The callbacks run on the
+ * thread that calls the library.  EINVAL: null ctx, or only one function. */
+int mbefci_set_allocator(mbefci_ctx* ctx, void* (*alloc)(size_t bytes, void* user),
+                         void (*release)(void* ptr, void* user), void* user);
 
 /* ---- integer layer: strings and single-excitation link tables ------------
  * A string of nelec electrons in norb active orbitals is a bitmask; strings

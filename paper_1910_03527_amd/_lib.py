@@ -20,11 +20,17 @@ ERROR_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", ENOTCONV: "ENOTCONV", EDEVICE
 # every symbol include/mbefci.h declares
 EXPORTS = (
     "mbefci_default_opts", "mbefci_create", "mbefci_destroy", "mbefci_last_error",
-    "mbefci_set_opts", "mbefci_num_strings", "mbefci_num_links", "mbefci_strings",
+    "mbefci_set_opts", "mbefci_set_allocator", "mbefci_num_strings", "mbefci_num_links", "mbefci_strings",
     "mbefci_link_table", "mbefci_num_tuples", "mbefci_hdiag", "mbefci_sigma", "mbefci_casci",
     "mbefci_casci_rdm", "mbefci_mbe_forward", "mbefci_mbe_backward", "mbefci_mbe_screened",
     "mbefci_screened_tuples", "mbefci_partition", "mbefci_time_kernels",
 )
+
+
+# workspace allocator callbacks: alloc(bytes, user) -> device pointer or NULL,
+# release(ptr, user)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class Opts(ctypes.Structure):
@@ -131,6 +137,8 @@ def load():
     L.mbefci_last_error.restype = ctypes.c_char_p
     L.mbefci_set_opts.argtypes = [vp, ctypes.POINTER(Opts)]
     L.mbefci_set_opts.restype = ctypes.c_int
+    L.mbefci_set_allocator.argtypes = [vp, ALLOC_FN, RELEASE_FN, vp]
+    L.mbefci_set_allocator.restype = ctypes.c_int
     L.mbefci_num_strings.argtypes = [i32, i32]
     L.mbefci_num_strings.restype = i64
     L.mbefci_num_links.argtypes = [i32, i32]

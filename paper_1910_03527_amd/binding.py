@@ -115,6 +115,28 @@ class Context:
         self._check(self._L.mbefci_set_opts(self._h, ctypes.byref(o)))
         self._opts = o
 
+    def use_torch_allocator(self, enable: bool = True):
+        """Take the context's workspaces from torch's caching allocator
+        (mbefci_set_allocator), or give them back to hipMalloc."""
+        if enable:
+            dev = self.device
+
+            def alloc(nbytes, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev)
+                except RuntimeError:
+                    return None
+
+            def release(ptr, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            cbs = (_lib.ALLOC_FN(alloc), _lib.RELEASE_FN(release))
+        else:
+            cbs = (_lib.ALLOC_FN(), _lib.RELEASE_FN())
+        self._check(self._L.mbefci_set_allocator(self._h, cbs[0], cbs[1], None))
+        self._fwd = None
+        self._allocator = cbs  # the callbacks must outlive every arena they made
+
     def _dev(self):
         return torch.device("cuda", self.device)
 

@@ -49,6 +49,10 @@ int64_t binom_host(int n, int k) {
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  // the caller's release function when the block came from its allocator
+  // (null: hipMalloc)
+  void (*release)(void*, void*) = nullptr;
+  void* user = nullptr;
 };
 
 struct StringTab {
@@ -141,6 +145,10 @@ struct mbefci_ctx {
   hipEvent_t ev_in = nullptr, ev_out = nullptr, t0 = nullptr, t1 = nullptr;
   std::map<std::pair<int, int>, StringTab> tabs;
   std::map<std::string, DevBuf> bufs;
+  // workspace allocator of the caller (mbefci_set_allocator), or hipMalloc
+  void* (*alloc_fn)(size_t, void*) = nullptr;
+  void (*release_fn)(void*, void*) = nullptr;
+  void* alloc_user = nullptr;
   std::unique_ptr<Plan> plan;
   // autotuned sigma-contraction schedule per active size n: (tile width,
   // tiles per workgroup); loaded from / saved to opts.tune_cache when set
@@ -166,20 +174,44 @@ constexpr int64_t kScreenChunkItems = (int64_t)1 << 16;
 constexpr int64_t kScreenChunkDets = (int64_t)1 << 25;
 
 // ------------------------------------------------------------ device memory
+// Free one workspace block the way it was allocated.  A block of the caller's
+// allocator is handed back only after the library stream has finished every
+// queued use of it (hipFree synchronises by itself).
+void release_buf(mbefci_ctx* c, DevBuf& b) {
+  if (b.p) {
+    if (b.release) {
+      (void)hipStreamSynchronize(c->stream);
+      b.release(b.p, b.user);
+    } else {
+      (void)hipFree(b.p);
+    }
+  }
+  b.p = nullptr;
+  b.bytes = 0;
+  b.release = nullptr;
+  b.user = nullptr;
+}
+
 template <class T>
 T* arena(mbefci_ctx* c, const std::string& name, size_t count, bool* grown = nullptr) {
   size_t bytes = std::max<size_t>(count * sizeof(T), 256);
   DevBuf& b = c->bufs[name];
   if (b.bytes < bytes) {
-    if (b.p) HIPCHK(hipFree(b.p));
-    b.p = nullptr;
-    b.bytes = 0;
+    release_buf(c, b);
     size_t total = 0;
     for (auto& kv : c->bufs) total += kv.second.bytes;
     if (c->opts.max_workspace > 0 && (int64_t)(total + bytes) > c->opts.max_workspace)
       throw Error(MBEFCI_ENOMEM, "workspace cap exceeded by arena '" + name + "'");
-    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+    if (c->alloc_fn) {
+      b.p = c->alloc_fn(bytes, c->alloc_user);
+      if (!b.p)
+        throw Error(MBEFCI_ENOMEM, "the caller's allocator returned no block of " +
+                                       std::to_string(bytes) + " bytes for '" + name + "'");
+      b.release = c->release_fn;
+      b.user = c->alloc_user;
+    } else if (hipMalloc(&b.p, bytes) != hipSuccess) {
       (void)hipGetLastError();
+      b.p = nullptr;
       throw Error(MBEFCI_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes for '" + name +
                                      "' failed");
     }
@@ -1052,8 +1084,7 @@ void mbefci_destroy(mbefci_ctx* c) {
     if (kv.second.pair) (void)hipFree(kv.second.pair);
     if (kv.second.pairT) (void)hipFree(kv.second.pairT);
   }
-  for (auto& kv : c->bufs)
-    if (kv.second.p) (void)hipFree(kv.second.p);
+  for (auto& kv : c->bufs) release_buf(c, kv.second);
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_out) (void)hipEventDestroy(c->ev_out);
   if (c->t0) (void)hipEventDestroy(c->t0);
@@ -1063,6 +1094,28 @@ void mbefci_destroy(mbefci_ctx* c) {
 }
 
 const char* mbefci_last_error(const mbefci_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int mbefci_set_allocator(mbefci_ctx* c, void* (*alloc)(size_t, void*),
+                         void (*release)(void*, void*), void* user) {
+  if (!c) return MBEFCI_EINVAL;
+  if ((alloc == nullptr) != (release == nullptr)) {
+    c->err = "set_allocator needs both functions or neither";
+    return MBEFCI_EINVAL;
+  }
+  return guarded(c, [&] {
+    HIPCHK(hipSetDevice(c->device));
+    // every workspace block goes back to the allocator it came from; the
+    // cached plan and the kept CI vectors go with them
+    if (c->plan && c->plan->graph) HIPCHK(hipGraphExecDestroy(c->plan->graph));
+    c->plan.reset();
+    c->have_forward = false;
+    for (auto& kv : c->bufs) release_buf(c, kv.second);
+    c->bufs.clear();
+    c->alloc_fn = alloc;
+    c->release_fn = release;
+    c->alloc_user = user;
+  });
+}
 
 int mbefci_set_opts(mbefci_ctx* c, const mbefci_opts* o) {
   if (!c || !o) return MBEFCI_EINVAL;

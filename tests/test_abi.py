@@ -60,6 +60,7 @@ def test_null_context_is_rejected(lib):
     assert lib.mbefci_mbe_screened(None, None, None, None, None, None, None, None, None) == \
         _lib.EINVAL
     assert lib.mbefci_screened_tuples(None, 1, None, None) == _lib.EINVAL
+    assert lib.mbefci_set_allocator(None, _lib.ALLOC_FN(), _lib.RELEASE_FN(), None) == _lib.EINVAL
     assert lib.mbefci_last_error(None) == b"null context"
 
 

@@ -93,3 +93,39 @@ def test_olsen_casci_batch():
         finally:
             c.close()
     assert max(abs(a - b) for a, b in zip(*es)) < 1e-10
+
+
+def test_torch_allocator_workspaces():
+    """Workspaces from torch's caching allocator (mbefci_set_allocator): the
+    same energies bitwise, the memory counted by torch while the context holds
+    it and handed back on close and on switching back to hipMalloc."""
+    from paper_1910_03527_amd import Context, MbefciError
+    p = W.problem("hubbard12")
+    h, g = _dev(p.h1), _dev(p.eri)
+    ref = Context(0, conv_tol=TOL)
+    r0 = ref.mbe_forward(h, g, p.occ, p.ref, p.exp, p.max_order, want_increments=True)
+    ref.close()
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    c = Context(0, conv_tol=TOL)
+    try:
+        c.use_torch_allocator()
+        r1 = c.mbe_forward(h, g, p.occ, p.ref, p.exp, p.max_order, want_increments=True)
+        held = torch.cuda.memory_allocated() - base
+        assert held > 1 << 20, held
+        assert r1["increments"] == r0["increments"] and r1["e_order"] == r0["e_order"]
+        dh, dg = c.mbe_backward([1.0] * (1 + p.max_order))
+        assert torch.isfinite(dh).all() and torch.isfinite(dg).all()
+        del dh, dg
+        c.use_torch_allocator(False)  # arenas go back to torch, then hipMalloc
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() - base < held
+        with pytest.raises(MbefciError):
+            c.mbe_backward([1.0] * (1 + p.max_order))  # the plan was dropped
+        c.use_torch_allocator()
+        r2 = c.mbe_forward(h, g, p.occ, p.ref, p.exp, p.max_order, want_increments=True)
+        assert r2["increments"] == r0["increments"]
+    finally:
+        c.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() - base <= 0
