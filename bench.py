@@ -141,6 +141,26 @@ def _oracle_job(args):
         return e, time.perf_counter() - t0
 
 
+def _oracle_sigma_job(args):
+    """Oracle sigma rows of one CAS(14e,14o) instance: `nrow` sampled rows of
+    H c for a seeded random c; returns the seconds per row."""
+    seed, nrow = args
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import workloads as W
+    from oracle import fci
+    p = W.problem("cas14", 0)
+    a = fci.string_masks(range(14), 7)
+    rng = np.random.default_rng(seed)
+    c = rng.standard_normal(len(a) * len(a))
+    c /= np.linalg.norm(c)
+    rows = np.sort(rng.choice(len(c), nrow, replace=False))
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        fci.sigma_rows(p.h1, p.eri, 0.0, a, a, c, rows)
+        return (time.perf_counter() - t0) / nrow
+
+
 def cpu_baseline(prob, nsolve, workers):
     """The CPU oracle (Slater-Condon CASCI, single-threaded per CASCI) on the
     reference CASCI plus the first tuple of every bucket, run in parallel;
@@ -153,8 +173,12 @@ def cpu_baseline(prob, nsolve, workers):
     t0 = time.perf_counter()
     with ProcessPoolExecutor(max_workers=workers) as ex:
         res = list(ex.map(_oracle_job, jobs))
-    wall = time.perf_counter() - t0
+        wall = time.perf_counter() - t0
+        # one sigma of the CAS(14e,14o) workload: sampled rows, extrapolated
+        nrow = 512
+        per_row = list(ex.map(_oracle_sigma_job, [(s, nrow) for s in range(workers)]))
     core_s = res[0][1] + sum(b[2] * r[1] for b, r in zip(bks, res[1:]))
+    sig_core_s = 11778624 * sum(per_row) / len(per_row)
     return {
         "value": nsolve / (core_s / workers),
         "unit": "CASCI solves/s",
@@ -165,6 +189,12 @@ def cpu_baseline(prob, nsolve, workers):
                    f"each); whole workload = sum over buckets of count x sampled time = "
                    f"{core_s:.0f} core-s, spread over {workers} cores"),
         "core_seconds_estimate": core_s,
+        "cas14_sigma": {
+            "core_seconds_per_sigma_estimate": sig_core_s,
+            "seconds_per_sigma_on_cores": sig_core_s / workers,
+            "sample": (f"{nrow} rows of H c per process, {workers} processes (seeded random c), "
+                       "x 11,778,624 rows"),
+        },
     }, dict(zip(tups, [r[0] for r in res]))
 
 
