@@ -140,6 +140,11 @@ int mbefci_create(int device, const mbefci_opts* opts, mbefci_ctx** out);
 void mbefci_destroy(mbefci_ctx* ctx);
 /* Message of the last failure on ctx (valid until the next call on ctx). */
 const char* mbefci_last_error(const mbefci_ctx* ctx);
+/* New options apply from the next call.  Changing max_space, tile,
+ * sigma_pass_mb, precond or pspace drops the cached plan (a backward then needs
+ * a new forward); changing conv_tol or max_iter keeps the plan and captures its
+ * iteration graph again.  A call that fails while building a plan leaves no
+ * plan behind. */
 int mbefci_set_opts(mbefci_ctx* ctx, const mbefci_opts* opts);
 /* Workspace allocator (the context's arenas: Davidson vectors, sigma
  * intermediates, kept CI vectors, per-CASCI state): alloc(bytes, user) returns

@@ -124,6 +124,9 @@ struct Plan {
   int32_t* d_collect = nullptr;
   // MBE description (for the combine and the backward)
   bool is_mbe = false;
+  // set once every array of the plan is allocated and filled: a call that
+  // fails before that leaves a plan nothing may reuse
+  bool ready = false;
   bool tuned = false;
   MbeSpaces sp{};
   int max_order = 0, norb = 0;
@@ -887,6 +890,15 @@ MbeSpaces make_spaces(int M, const std::vector<int>& role, const std::vector<int
   return sp;
 }
 
+// A plan whose construction did not finish is dropped after a failed call.
+void discard_partial_plan(mbefci_ctx* c) {
+  if (c->plan && !c->plan->ready) {
+    if (c->plan->graph) (void)hipGraphExecDestroy(c->plan->graph);
+    c->plan.reset();
+    c->have_forward = false;
+  }
+}
+
 template <class F>
 int guarded(mbefci_ctx* c, F&& f) {
   if (!c) return MBEFCI_EINVAL;
@@ -896,9 +908,11 @@ int guarded(mbefci_ctx* c, F&& f) {
     return MBEFCI_OK;
   } catch (const Error& e) {
     c->err = e.what();
+    discard_partial_plan(c);
     return e.code;
   } catch (const std::exception& e) {
     c->err = e.what();
+    discard_partial_plan(c);
     return MBEFCI_EDEVICE;
   }
 }
@@ -934,6 +948,7 @@ void casci_plan(mbefci_ctx* c, int nprob, int n, int na, int nb, const double* c
   upload(c, d_e, ev);
   launch_casci_setup(n, d_h, d_g, d_e, P.d_items, P.nitem, P.hams, P.W, c->stream);
   HIPCHK(hipGetLastError());
+  P.ready = true;
 }
 
 // ------------------------------------------------------------- RDM pass
@@ -1128,11 +1143,17 @@ int mbefci_set_opts(mbefci_ctx* c, const mbefci_opts* o) {
   bool plan_dead = o->max_space != c->opts.max_space || o->tile != c->opts.tile ||
                    o->sigma_pass_mb != c->opts.sigma_pass_mb || o->precond != c->opts.precond ||
                    o->pspace != c->opts.pspace;
+  // the captured iteration graph holds the tolerance and the iteration cap
+  // as kernel arguments: it is captured again at the next solve
+  const bool graph_dead = o->conv_tol != c->opts.conv_tol || o->max_iter != c->opts.max_iter;
   c->opts = *o;
   if (plan_dead && c->plan) {
     if (c->plan->graph) (void)hipGraphExecDestroy(c->plan->graph);
     c->plan.reset();
     c->have_forward = false;
+  } else if (graph_dead && c->plan && c->plan->graph) {
+    (void)hipGraphExecDestroy(c->plan->graph);
+    c->plan->graph = nullptr;
   }
   return MBEFCI_OK;
 }
@@ -1285,7 +1306,7 @@ int mbefci_mbe_forward(mbefci_ctx* c, const mbefci_problem* pb, double* e_ref, d
     // ---- plan (bucket by order and occupied count; items in bucket order)
     std::string sig = std::to_string(M) + "|" + std::to_string(pb->max_order) + "|";
     for (int i = 0; i < M; ++i) sig += char('0' + role[i] + 3 * occ[i]);
-    const bool reuse = c->plan && c->plan->is_mbe && c->plan->signature == sig;
+    const bool reuse = c->plan && c->plan->ready && c->plan->is_mbe && c->plan->signature == sig;
     if (!reuse) {
       if (c->plan && c->plan->graph) HIPCHK(hipGraphExecDestroy(c->plan->graph));
       c->plan.reset(new Plan());
@@ -1363,6 +1384,8 @@ int mbefci_mbe_forward(mbefci_ctx* c, const mbefci_problem* pb, double* e_ref, d
       upload(c, d_oo, ooff);
     }
     Plan& P = *c->plan;
+    P.ready = true;
+    c->have_forward = false;  // until this solve has succeeded
     // ---- set-up, solve, combine
     launch_mbe_setup(&P.sp, P.d_buckets, (int)P.buckets.size(), P.d_items, P.nitem, pb->h1,
                      pb->eri, pb->e_const, P.hams, P.W, P.tuple_pos, P.max_order, P.act, c->stream);
@@ -1546,6 +1569,7 @@ int mbefci_mbe_screened(mbefci_ctx* c, const mbefci_problem* pb, const mbefci_sc
         launch_mbe_setup_list(&P.sp, d_masks, P.d_items, P.nitem, pb->h1, pb->eri, pb->e_const,
                               P.hams, P.W, c->stream);
         HIPCHK(hipGetLastError());
+        P.ready = true;
         mbefci_stats st{};
         solve_plan(c, P, &st);
         tot.ntuples += st.ntuples - (with_ref ? 1 : 0);

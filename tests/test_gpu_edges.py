@@ -148,3 +148,38 @@ def test_backward_needs_forward():
         assert rc == _lib.EINVAL
     finally:
         c.close()
+
+
+def test_iteration_limit_reports_enotconv():
+    """max_iter = 1 forced from the host: the expansion fails with ENOTCONV
+    naming the first CASCI that did not converge; the context stays usable."""
+    from paper_1910_03527_amd import Context, MbefciError, _lib
+    p = W.problem("hubbard12")
+    c = Context(0, max_iter=1)
+    try:
+        with pytest.raises(MbefciError) as ei:
+            c.mbe_forward(_dev(p.h1), _dev(p.eri), p.occ, p.ref, p.exp, p.max_order)
+        assert ei.value.code == _lib.ENOTCONV
+        assert "did not converge for CASCI" in str(ei.value)
+        c.set_opts(max_iter=200)
+        r = c.mbe_forward(_dev(p.h1), _dev(p.eri), p.occ, p.ref, p.exp, p.max_order)
+        assert c.last_stats["first_failed"] == -1 and math.isfinite(r["e_total"])
+    finally:
+        c.close()
+
+
+def test_workspace_cap_reports_enomem():
+    """A workspace cap below what the expansion needs: ENOMEM before any
+    launch that needs the memory; lifting the cap makes it run."""
+    from paper_1910_03527_amd import Context, MbefciError, _lib
+    p = W.problem("hubbard12")
+    c = Context(0, max_workspace=1 << 20)
+    try:
+        with pytest.raises(MbefciError) as ei:
+            c.mbe_forward(_dev(p.h1), _dev(p.eri), p.occ, p.ref, p.exp, p.max_order)
+        assert ei.value.code == _lib.ENOMEM
+        c.set_opts(max_workspace=0)
+        r = c.mbe_forward(_dev(p.h1), _dev(p.eri), p.occ, p.ref, p.exp, p.max_order)
+        assert math.isfinite(r["e_total"])
+    finally:
+        c.close()

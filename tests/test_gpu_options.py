@@ -129,3 +129,30 @@ def test_torch_allocator_workspaces():
         c.close()
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated() - base <= 0
+
+
+def test_tolerance_change_reaches_the_cached_plan():
+    """A forward at a loose tolerance, then set_opts(conv_tol) and the same
+    forward again on the cached plan: it must converge to the new tolerance
+    (the captured iteration graph holds the old one and is captured again)."""
+    from paper_1910_03527_amd import Context
+    p = W.problem("hubbard12")
+    h, g = _dev(p.h1), _dev(p.eri)
+    c = Context(0, conv_tol=1e-10)
+    try:
+        ref = c.mbe_forward(h, g, p.occ, p.ref, p.exp, p.max_order, want_increments=True)
+    finally:
+        c.close()
+    c = Context(0, conv_tol=1e-3)
+    try:
+        loose = c.mbe_forward(h, g, p.occ, p.ref, p.exp, p.max_order, want_increments=True)
+        it_loose = c.last_stats["max_iters"]
+        c.set_opts(conv_tol=1e-10)
+        again = c.mbe_forward(h, g, p.occ, p.ref, p.exp, p.max_order, want_increments=True)
+        it_again = c.last_stats["max_iters"]
+    finally:
+        c.close()
+    assert it_again > it_loose
+    err_loose = abs(loose["e_total"] - ref["e_total"])
+    err_again = abs(again["e_total"] - ref["e_total"])
+    assert err_again < 1e-10 and err_again < err_loose, (err_loose, err_again)
