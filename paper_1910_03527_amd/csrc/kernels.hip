@@ -797,7 +797,6 @@ __global__ void __launch_bounds__(256) k_sigma_gather(const Item* __restrict__ i
   const int Kb = (seg % segs) * 64 + (threadIdx.x & 63);
   if (Kb >= Nb) return;
   const double* __restrict__ G = Garena + I.goff;
-  const int64_t nd = I.ndet;
   const int La = I.La, Lb = I.Lb;
   double acc0 = 0.0, acc1 = 0.0;
   const int np = I.npair;
