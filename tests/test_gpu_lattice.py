@@ -177,7 +177,7 @@ def test_pm22_energy_per_site_vs_lieb_wu(lattice22):
     assert got["e_ref"] / p.norb - e_tdl > 3 * (e_site - e_tdl)
 
 
-@pytest.mark.parametrize("name,k,t_init,batch", [("hubbard12", 6, 1e-5, 37),
+@pytest.mark.parametrize("name,k,t_init,batch", [("hubbard12", 6, 1e-5, 7),
                                                   ("hubbard22_pm", 5, T_INIT, 1000)])
 def test_screen_batches_do_not_change_results(ctx, name, k, t_init, batch):
     from paper_1910_03527_amd import Context
