@@ -44,7 +44,7 @@ def kernel_source_sha(kernel_name):
     fn = "k_" + kernel_name.split("<")[0]
     with open(os.path.join(csrc, "kernels.hip")) as fh:
         text = fh.read()
-    m = re.search(r"\n(template <[^>]*>\n)?__global__ void (__launch_bounds__\([^)]*\) )?" +
+    m = re.search(r"\n(template <[^>]*>\n)?__global__ void (__launch_bounds__\((?:[^()]|\([^()]*\))*\) )?" +
                   re.escape(fn) + r"\(", text)
     if not m:
         return None

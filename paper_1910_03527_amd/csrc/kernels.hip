@@ -368,25 +368,29 @@ __device__ inline bool item_active(const DavState& st, int slot) {
 // Contraction G = W D+ on FP64 MFMA.  A tile is one alpha string Ka and TN
 // consecutive beta strings; a workgroup keeps one beta block (TN strings)
 // and walks down a range of alpha strings (tiles are numbered column-major:
-// tile = block * Na + Ka).  Per workgroup the beta pair-table block is staged
-// once in LDS; per tile the c row of Ka is staged in LDS, so the beta half of
-// every D+ entry is two LDS reads.  The alpha half is wave-uniform: a scalar
-// pair-table load and a coalesced row segment of c.  D+ [pair][TN] (B
-// operand) is staged in LDS, the wave's W rows (A operand) sit in registers.
-// G is stored [Ka][pair][Kb].
+// tile = block * Na + Ka).  A thread builds the same (pair, column) slots of
+// D+ in every tile; their beta pair-table entries are loaded once per work
+// unit, into registers for 32-column tiles of up to 10 orbitals (where the
+// kernel still fits four waves per SIMD) and into LDS otherwise.  Per tile
+// the c row of Ka is staged in LDS.  The alpha half of a D+ entry is
+// wave-uniform: a scalar pair-table load and a coalesced row segment of c.
+// D+ [pair][TN] (B operand) is staged in LDS, the wave's W rows (A operand)
+// sit in registers.  G is stored [Ka][pair][Kb].
 constexpr int64_t binom_c(int n, int k) {
   int64_t r = 1;
   for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
   return r;
 }
 
+// With 32-column tiles of up to 10 orbitals the pair-table entries stay in
+// registers and the kernel is compiled for four waves per SIMD (128 registers
+// per lane, accumulators included), which those shapes reach without
+// spilling; larger shapes take the registers they need.
 template <int NACT, int TN>
-__global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ items,
-                                                     const Work* __restrict__ work,
-                                                     const double* __restrict__ warena,
-                                                     const double* __restrict__ V, int64_t ntot,
-                                                     double* __restrict__ Garena,
-                                                     const DavState* __restrict__ st, int slot) {
+__global__ void __launch_bounds__(256, (TN == 32 && NACT <= 10) ? 4 : 1) k_sigma_dgemm(
+    const Item* __restrict__ items, const Work* __restrict__ work,
+    const double* __restrict__ warena, const double* __restrict__ V, int64_t ntot,
+    double* __restrict__ Garena, const DavState* __restrict__ st, int slot) {
   constexpr int NP = NACT * (NACT + 1) / 2;
   constexpr int KPAD = (NP + 15) / 16 * 16;
   constexpr int KS = (NP + 3) / 4;       // MFMA k-steps (4 pair rows per step)
@@ -400,8 +404,9 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
   constexpr int CMAX = (int)binom_c(NACT, NACT / 2);  // largest string count for NACT
   constexpr int CPT = (CMAX + 255) / 256;             // c-row doubles per thread
   constexpr int TPT = (NP * TN + 255) / 256;          // beta-table entries per thread
+  constexpr bool EREG = TN == 32 && NACT <= 10;  // the launch-bounds rule
   __shared__ double Ds[KR * LDT];
-  __shared__ int32_t Tb[NP * TN];
+  __shared__ int32_t Tb[EREG ? 1 : NP * TN];
   __shared__ double Cr[CMAX];
 
   const Work wk = work[blockIdx.x];
@@ -442,23 +447,20 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
       wreg[r][ks] = (rb < NRB) ? ldg(W + (rb * 16 + (lane & 15)) * KPAD + ks * 4 + (lane >> 4))
                                : 0.0;
   }
-  // beta pair-table block [pair][TN] (all loads issued before the LDS
-  // stores) and the zero padding rows of D+
-  {
-    int32_t tv[TPT];
+  // This thread's beta pair-table entries: slot i is pair sub + NSUB i of
+  // column col (x = t + 256 i has x / TN = sub + NSUB i and x % TN = col),
+  // the slots it writes in every tile's D+.  Then the zero padding rows of D+.
+  static_assert(TPT == NPER, "one pair-table entry per D+ slot of a thread");
+  int32_t eb[NPER];
 #pragma unroll
-    for (int i = 0; i < TPT; ++i) {
-      const int x = t + 256 * i;
-      tv[i] = 0;
-      if (x < NP * TN) {
-        const int ab = x / TN, cc = x - ab * TN;
-        const int kb = Kb0 + cc < Nb ? Kb0 + cc : Nb - 1;
-        tv[i] = ldg(pB + ab * Nb + kb);
-      }
-    }
+  for (int i = 0; i < NPER; ++i) {
+    const int ab = sub + NSUB * i;
+    eb[i] = ab < NP ? ldg(pB + ab * Nb + Kbc) : 0;
+  }
+  if constexpr (!EREG) {
 #pragma unroll
-    for (int i = 0; i < TPT; ++i)
-      if (t + 256 * i < NP * TN) Tb[t + 256 * i] = tv[i];
+    for (int i = 0; i < NPER; ++i)
+      if (sub + NSUB * i < NP) Tb[t + 256 * i] = eb[i];
   }
   for (int x = NP * LDT + t; x < KR * LDT; x += 256) Ds[x] = 0.0;
 
@@ -517,10 +519,12 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm(const Item* __restrict__ it
     for (int i = 0; i < NPER; ++i) {
       const int ab = sub + NSUB * i;
       if (ab < NP) {
-        const int32_t eb = Tb[ab * TN + col];
-        const int jb = eb ? (eb >> 1) - 1 : 0;
+        int32_t e;
+        if constexpr (EREG) e = eb[i];
+        else e = Tb[t + 256 * i];
+        const int jb = e ? (e >> 1) - 1 : 0;
         const double fa = ea[i] ? ((ea[i] & 1) ? -keep : keep) : 0.0;
-        const double fb = eb ? ((eb & 1) ? -keep : keep) : 0.0;
+        const double fb = e ? ((e & 1) ? -keep : keep) : 0.0;
         Ds[ab * LDT + col] = fa * ga[i] + fb * Cr[jb];
       }
     }
