@@ -224,8 +224,8 @@ def main():
                          "only the sigma-sweep replays (every sigma launch does the same work)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the library drives one device per context and has "
+              "no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
