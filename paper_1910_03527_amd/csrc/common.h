@@ -104,6 +104,7 @@ struct DavState {
   double tnorm2;      // squared norm of the correction vector
   double eps;         // Olsen shift of the correction equation
   double y[kMaxSpace];
+  double yp[kMaxSpace];   // Ritz coefficients of the previous iteration (restart)
   double coef[kMaxSpace + 1];
   double Hs[kMaxSpace * kMaxSpace];
 };

@@ -1070,6 +1070,8 @@ __global__ void k_dav_rr(const Item* __restrict__ items, int ibase,
   const int j = slot >= 0 ? slot : S.m - 1;
   const int m = j + 1;
   const int lane = threadIdx.x;
+  // the Ritz coefficients of the subspace before the newest vector
+  const double yold = (lane < kMaxSpace && lane < j) ? S.y[lane] : 0.0;
   if (lane < m) {
     double v = 0.0;
     for (int c = 0; c < I.nchunk; ++c) v += part[(int64_t)(I.chunk0 + c) * kPart + lane];
@@ -1089,7 +1091,10 @@ __global__ void k_dav_rr(const Item* __restrict__ items, int ibase,
   if (lane == 0) th = thl;
   __syncthreads();
   __syncthreads();
-  if (lane < kMaxSpace) S.y[lane] = lane < m ? y[lane] : 0.0;
+  if (lane < kMaxSpace) {
+    S.y[lane] = lane < m ? y[lane] : 0.0;
+    S.yp[lane] = yold;
+  }
   if (lane == 0) {
     S.theta = th;
     if (slot >= 0) {   // end of the guess phase
@@ -1112,7 +1117,25 @@ __device__ __forceinline__ int subspace_cap(const Item& I, const DavState& S, in
 }
 
 // Restart: when the subspace is full, collapse it onto the Ritz vector
-// x = V y (and H x = S y) in slot 0.
+// x = V y (and H x = S y) in slot 0 and the previous iteration's Ritz vector,
+// made orthogonal to x, in slot 1: z = yp - (y.yp) y in the subspace's
+// orthonormal basis, x' = V z / |z| (kept when |z| > kRestartMin).  The
+// projected matrix becomes diag(theta, z^T Hs z / |z|^2): y is an
+// eigenvector of Hs and z is orthogonal to it.
+// Both collapse kernels call restart_coef and must take the same decision:
+// explicit fused multiply-adds fix its rounding wherever it is inlined.
+constexpr double kRestartMin = 1e-8;
+__device__ inline double restart_coef(const DavState& S, double* z) {
+  double c = 0.0;
+  for (int i = 0; i < S.m; ++i) c = fma(S.y[i], S.yp[i], c);
+  double nz = 0.0;
+  for (int i = 0; i < S.m; ++i) {
+    z[i] = fma(-c, S.y[i], S.yp[i]);
+    nz = fma(z[i], z[i], nz);
+  }
+  nz = sqrt(nz);
+  return nz > kRestartMin ? nz : 0.0;
+}
 __global__ void __launch_bounds__(256) k_dav_collapse(const Item* __restrict__ items,
                                                       const Work* __restrict__ work, double* V,
                                                       double* Sv, int64_t ntot,
@@ -1121,16 +1144,29 @@ __global__ void __launch_bounds__(256) k_dav_collapse(const Item* __restrict__ i
   const Item& I = items[wk.item];
   const DavState& S = st[wk.item];
   if (S.conv || S.m < subspace_cap(I, S, mmax)) return;
+  __shared__ double z[kMaxSpace];
+  __shared__ double nz;
+  if (threadIdx.x == 0) nz = restart_coef(S, z);
+  __syncthreads();
+  const double inv = nz > 0.0 ? 1.0 / nz : 0.0;
   const int64_t e0 = (int64_t)(wk.begin - I.chunk0) * kChunk;
   const int64_t e1 = min(e0 + kChunk, I.ndet);
   for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
-    double x = 0.0, sx = 0.0;
+    double x = 0.0, sx = 0.0, xp = 0.0, sxp = 0.0;
     for (int i = 0; i < S.m; ++i) {
-      x += S.y[i] * V[(int64_t)i * ntot + I.off + e];
-      sx += S.y[i] * Sv[(int64_t)i * ntot + I.off + e];
+      const double v = V[(int64_t)i * ntot + I.off + e];
+      const double s = Sv[(int64_t)i * ntot + I.off + e];
+      x += S.y[i] * v;
+      sx += S.y[i] * s;
+      xp += z[i] * v;
+      sxp += z[i] * s;
     }
     V[I.off + e] = x;
     Sv[I.off + e] = sx;
+    if (nz > 0.0) {
+      V[ntot + I.off + e] = xp * inv;
+      Sv[ntot + I.off + e] = sxp * inv;
+    }
   }
 }
 __global__ void k_dav_collapse_state(const Item* __restrict__ items, DavState* st, int ibase,
@@ -1140,8 +1176,22 @@ __global__ void k_dav_collapse_state(const Item* __restrict__ items, DavState* s
   i += ibase;
   DavState& S = st[i];
   if (S.conv || S.m < subspace_cap(items[i], S, mmax)) return;
-  S.m = 1;
+  double z[kMaxSpace];
+  const double nz = restart_coef(S, z);
+  double h11 = 0.0;
+  if (nz > 0.0) {
+    for (int a = 0; a < S.m; ++a) {
+      double row = 0.0;
+      for (int b = 0; b < S.m; ++b) row += S.Hs[a * kMaxSpace + b] * z[b];
+      h11 += z[a] * row;
+    }
+    h11 /= nz * nz;
+  }
   S.Hs[0] = S.theta;
+  S.Hs[1] = 0.0;
+  S.Hs[kMaxSpace] = 0.0;
+  S.Hs[kMaxSpace + 1] = h11;
+  S.m = nz > 0.0 ? 2 : 1;
   S.y[0] = 1.0;
   for (int k = 1; k < kMaxSpace; ++k) S.y[k] = 0.0;
 }
