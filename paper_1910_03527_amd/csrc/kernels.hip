@@ -1105,17 +1105,6 @@ __global__ void k_dav_rr(const Item* __restrict__ items, int ibase,
   }
 }
 
-// Subspace size at which a CASCI restarts.  For active spaces of at most 9
-// orbitals a sigma evaluation (2 npair^2 flops and ~8 npair bytes per
-// determinant) costs little next to the 4m + 4 vector passes of an iteration,
-// so these restart at 8 vectors (more iterations, fewer passes); larger ones
-// use the whole subspace.
-__device__ __forceinline__ int subspace_cap(const Item& I, const DavState& S, int mmax) {
-  if (I.n > 9) return mmax;
-  const int c = S.nguess + 2 > 8 ? S.nguess + 2 : 8;
-  return c < mmax ? c : mmax;
-}
-
 // Restart: when the subspace is full, collapse it onto the Ritz vector
 // x = V y (and H x = S y) in slot 0 and the previous iteration's Ritz vector,
 // made orthogonal to x, in slot 1: z = yp - (y.yp) y in the subspace's
@@ -1143,7 +1132,7 @@ __global__ void __launch_bounds__(256) k_dav_collapse(const Item* __restrict__ i
   const Work wk = work[blockIdx.x];
   const Item& I = items[wk.item];
   const DavState& S = st[wk.item];
-  if (S.conv || S.m < subspace_cap(I, S, mmax)) return;
+  if (S.conv || S.m < mmax) return;
   __shared__ double z[kMaxSpace];
   __shared__ double nz;
   if (threadIdx.x == 0) nz = restart_coef(S, z);
@@ -1175,7 +1164,7 @@ __global__ void k_dav_collapse_state(const Item* __restrict__ items, DavState* s
   if (i >= nitem) return;
   i += ibase;
   DavState& S = st[i];
-  if (S.conv || S.m < subspace_cap(items[i], S, mmax)) return;
+  if (S.conv || S.m < mmax) return;
   double z[kMaxSpace];
   const double nz = restart_coef(S, z);
   double h11 = 0.0;

@@ -1031,7 +1031,7 @@ void mbefci_default_opts(mbefci_opts* o) {
   std::memset(o, 0, sizeof(*o));
   o->conv_tol = 1e-6;
   o->max_iter = 200;
-  o->max_space = 16;
+  o->max_space = 8;
   o->nguess = 1;
   o->mode = MBEFCI_BATCHED;
   o->use_graph = 1;
@@ -1048,7 +1048,7 @@ void mbefci_default_opts(mbefci_opts* o) {
 static int check_opts(const mbefci_opts* o, std::string* why) {
   if (!(o->conv_tol > 0)) { *why = "conv_tol must be positive"; return MBEFCI_EINVAL; }
   if (o->max_iter < 1) { *why = "max_iter must be >= 1"; return MBEFCI_EINVAL; }
-  if (o->max_space < 2 || o->max_space > kMaxSpace) { *why = "max_space must be in 2..16"; return MBEFCI_EINVAL; }
+  if (o->max_space < 3 || o->max_space > kMaxSpace) { *why = "max_space must be in 3..16"; return MBEFCI_EINVAL; }
   if (o->nguess < 1 || o->nguess > 8 || o->nguess + 1 >= o->max_space) { *why = "nguess must be in 1..8 and below max_space - 1"; return MBEFCI_EINVAL; }
   if (o->mode != MBEFCI_BATCHED && o->mode != MBEFCI_PER_LAUNCH) { *why = "unknown mode"; return MBEFCI_EINVAL; }
   if (o->tile != 0 && o->tile != 32 && o->tile != 64 && o->tile != 128) { *why = "tile must be 0, 32, 64 or 128"; return MBEFCI_EINVAL; }

@@ -52,7 +52,7 @@ def hub12():
 
 
 @pytest.mark.parametrize("opts", [{"precond": 1}, {"nguess": 3, "max_space": 6},
-                                  {"max_space": 4}, {"pspace": 0}])
+                                  {"max_space": 4}, {"max_space": 16}, {"pspace": 0}])
 def test_options_reach_the_same_energies(hub12, opts):
     p, ref = hub12
     _log("options", opts)
