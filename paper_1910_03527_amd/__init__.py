@@ -12,6 +12,7 @@ Names mirror the C ABI without the ``mbefci_`` prefix:
 * ``Context.strings``, ``Context.link_table``  (device string / link tables)
 * ``Context.hdiag``, ``Context.sigma``         (one CASCI Hamiltonian)
 * ``Context.casci``                            (batch of same-shape CASCIs)
+* ``casci``                                    (one CASCI, optionally with its RDMs)
 * ``Context.casci_rdm``                        (their 1- and 2-RDMs)
 * ``Context.mbe_forward``, ``Context.mbe_backward``  (Eq. 1 / Eq. 2)
 * ``Context.mbe_screened``  (order-by-order expansion with the Eq. 4 screening)
@@ -25,6 +26,7 @@ from .binding import (  # noqa: F401
     PER_LAUNCH,
     Context,
     MbefciError,
+    casci,
     MBEEnergy,
     num_links,
     num_strings,

@@ -321,6 +321,26 @@ class Context:
         return dh, dg
 
 
+def casci(h1, eri, nalpha: int, nbeta: int, e_core: float = 0.0, want_rdm: bool = False,
+          **opts):
+    """One CASCI on the device of ``h1`` (mbefci_casci with a batch of one):
+    the lowest eigenvalue of the S_z sector (nalpha, nbeta) plus ``e_core``,
+    and with ``want_rdm`` also (gamma [n, n], Gamma [n, n, n, n]) in the
+    chemist convention E = sum h gamma + 1/2 sum (pq|rs) Gamma + e_core.
+    ``opts`` are Context options.  A context is created and closed per call;
+    batches of CASCIs go through Context.casci."""
+    dev = h1.device.index if h1.device.index is not None else torch.cuda.current_device()
+    ctx = Context(dev, **opts)
+    try:
+        e = ctx.casci([h1], [eri], nalpha, nbeta, e_core=[e_core])[0]
+        if not want_rdm:
+            return e
+        g1, g2 = ctx.casci_rdm()
+        return e, g1[0], g2[0]
+    finally:
+        ctx.close()
+
+
 class MBEEnergy(torch.autograd.Function):
     """E = [E_ref, E^(1), ..., E^(k)] as a differentiable function of the MO
     integrals: ``MBEEnergy.apply(h1, eri, ctx, occ, ref, exp, max_order)``;
