@@ -2321,16 +2321,27 @@ __device__ double sym_gamma2(int p, int q, int r, int s, int cp, int cq, int cr,
   return 0.25 * acc;
 }
 
-// dE/dh_pq = sum_it w_it gamma_full(p, q)
-__global__ void k_grad_h(const Item* __restrict__ items, int nitem, const int32_t* __restrict__ act,
-                         uint64_t occmask, int M, const double* __restrict__ w,
-                         const double* __restrict__ rdmp, const int64_t* __restrict__ roff,
-                         double* out) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= M * M) return;
+// Sum over a wave by a butterfly: every lane ends with the same value, and
+// the order of the additions is fixed by the lane numbering alone.
+__device__ inline double wave_sum64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// dE/dh_pq = sum_it w_it gamma_full(p, q).  One wave per element: lane l
+// sums the items l, l + 64, ..., then the lanes' sums meet in wave_sum64
+// (a fixed order, so the result is bitwise reproducible).
+__global__ void __launch_bounds__(64) k_grad_h(const Item* __restrict__ items, int nitem,
+                                               const int32_t* __restrict__ act, uint64_t occmask,
+                                               int M, const double* __restrict__ w,
+                                               const double* __restrict__ rdmp,
+                                               const int64_t* __restrict__ roff, double* out) {
+  const int x = blockIdx.x;
   const int p = x / M, q = x % M;
+  const int lane = threadIdx.x;
   double acc = 0.0;
-  for (int it = 0; it < nitem; ++it) {
+  for (int it = lane; it < nitem; it += 64) {
     const double wt = w[it];
     if (wt == 0.0) continue;
     const Item& I = items[it];
@@ -2342,21 +2353,25 @@ __global__ void k_grad_h(const Item* __restrict__ items, int nitem, const int32_
     else if (cp >= 0 && cq >= 0) v = act_gamma(rdmp + roff[it], I.kpad, I.npair, cp, cq);
     acc += wt * v;
   }
-  out[x] = acc;
+  acc = wave_sum64(acc);
+  if (lane == 0) out[x] = acc;
 }
 
-// dE/d(pq|rs) = sum_it w_it 1/2 Sym8(Gamma_full)_pqrs
-__global__ void k_grad_g(const Item* __restrict__ items, int nitem, const int32_t* __restrict__ act,
-                         uint64_t occmask, int M, const double* __restrict__ w,
-                         const double* __restrict__ rdmp, const int64_t* __restrict__ roff,
-                         double* out) {
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// dE/d(pq|rs) = sum_it w_it 1/2 Sym8(Gamma_full)_pqrs, one wave per element
+// as in k_grad_h (four elements per 256-thread block).
+__global__ void __launch_bounds__(256) k_grad_g(const Item* __restrict__ items, int nitem,
+                                                const int32_t* __restrict__ act, uint64_t occmask,
+                                                int M, const double* __restrict__ w,
+                                                const double* __restrict__ rdmp,
+                                                const int64_t* __restrict__ roff, double* out) {
+  const int64_t x = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int64_t M2 = (int64_t)M * M;
-  if (x >= M2 * M2) return;
+  if (x >= M2 * M2) return;  // whole waves
   const int p = (int)(x / (M2 * M)), q = (int)((x / M2) % M), r = (int)((x / M) % M),
             s = (int)(x % M);
   double acc = 0.0;
-  for (int it = 0; it < nitem; ++it) {
+  for (int it = lane; it < nitem; it += 64) {
     const double wt = w[it];
     if (wt == 0.0) continue;
     const Item& I = items[it];
@@ -2372,7 +2387,8 @@ __global__ void k_grad_g(const Item* __restrict__ items, int nitem, const int32_
     if (cs == -2) continue;
     acc += wt * 0.5 * sym_gamma2(p, q, r, s, cp, cq, cr, cs, rdmp + roff[it], I.kpad, I.npair);
   }
-  out[x] = acc;
+  acc = wave_sum64(acc);
+  if (lane == 0) out[x] = acc;
 }
 
 // RDMs of one whole-space CASCI: rdm1 = gamma, rdm2 = Sym8(Gamma).
@@ -2935,10 +2951,10 @@ void launch_mbe_weights(const BucketDev* buckets, int nbucket, int nitem, int ne
 void launch_grad(const Item* items, int nitem, const int32_t* act, uint64_t occmask, int M,
                  const double* w, const double* rdmp, const int64_t* roff, double* dh, double* dg,
                  hipStream_t s) {
-  hipLaunchKernelGGL(k_grad_h, dim3(nblk((int64_t)M * M, 256)), dim3(256), 0, s, items, nitem, act,
-                     occmask, M, w, rdmp, roff, dh);
+  hipLaunchKernelGGL(k_grad_h, dim3(M * M), dim3(64), 0, s, items, nitem, act, occmask, M, w, rdmp,
+                     roff, dh);
   const int64_t M4 = (int64_t)M * M * M * M;
-  hipLaunchKernelGGL(k_grad_g, dim3(nblk(M4, 256)), dim3(256), 0, s, items, nitem, act, occmask, M,
+  hipLaunchKernelGGL(k_grad_g, dim3(nblk(M4, 4)), dim3(256), 0, s, items, nitem, act, occmask, M,
                      w, rdmp, roff, dg);
 }
 void launch_casci_rdm_out(const Item* items, int it, int n, const double* rdmp,
