@@ -49,7 +49,7 @@ struct PspaceArgs {
 // chunked P-space selection of large CASCIs: per chunk of kSelectChunk
 // determinants a work unit (item, chunk, first candidate slot of the item),
 // per item its first slot or -1, and the candidate keys (kMaxPspace per slot)
-constexpr int64_t kSelectChunk = 65536;
+constexpr int64_t kSelectChunk = 16384;
 struct PspaceSelect {
   const Work* work;
   int nwork;

@@ -202,7 +202,7 @@ def test_mbe_deterministic(ctx):
 
 
 def test_large_casci_batched_equals_per_launch():
-    """CASCIs above 65,536 determinants select their P-space in chunks; in
+    """CASCIs above 16,384 determinants select their P-space in chunks; in
     per-launch mode each CASCI is a view of its own.  Both modes give
     bitwise the same energies (same kernels, same work per CASCI)."""
     from paper_1910_03527_amd import Context, PER_LAUNCH
