@@ -1926,7 +1926,12 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
     if (i == n - 2) ee[i] = A[L(n - 1, n - 2)];
   }
   if (t == 0 && n >= 1) ee[n - 1] = 0.0;
+  // A CASCI whose P block is its whole space converges on this guess, so it
+  // needs no correction and no explicit Q: the guess Q z is formed from the
+  // reflectors below.
+  const bool exact = nd == n;
   // ---- Q = H_0 H_1 ... H_{n-3}, accumulated backwards from the identity
+  if (!exact) {
   for (int x = t; x < n * n; x += NT) Q[x] = (x / n == x % n) ? 1.0 : 0.0;
   __syncthreads();
   for (int k = n - 3; k >= 0; --k) {
@@ -1963,6 +1968,7 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
       }
     }
     __syncthreads();
+  }
   }
   // ---- lowest eigenvalue of T: multisection on [lo, hi] (Gershgorin)
   if (t == 0) {
@@ -2011,18 +2017,34 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
   }
   __syncthreads();
   // ---- outputs: Q (row = P position), T, the guess vectors
-  double* __restrict__ Qo = pQ + (int64_t)it * PM * PM;
-  for (int x = t; x < n * n; x += NT) Qo[(x / n) * PM + (x % n)] = Q[x];
-  double* __restrict__ To = pT + (int64_t)it * 2 * PM;
-  for (int i = t; i < n; i += NT) {
-    To[i] = dd[i];
-    To[PM + i] = ee[i];
-  }
-  // u = Q z (row k: P position k)
-  if (t < n) {
-    double u = 0.0;
-    for (int j = 0; j < n; ++j) u += Q[t * n + j] * zz[j];
-    vv[t] = u;
+  if (!exact) {
+    double* __restrict__ Qo = pQ + (int64_t)it * PM * PM;
+    for (int x = t; x < n * n; x += NT) Qo[(x / n) * PM + (x % n)] = Q[x];
+    double* __restrict__ To = pT + (int64_t)it * 2 * PM;
+    for (int i = t; i < n; i += NT) {
+      To[i] = dd[i];
+      To[PM + i] = ee[i];
+    }
+    // u = Q z (row k: P position k)
+    if (t < n) {
+      double u = 0.0;
+      for (int j = 0; j < n; ++j) u += Q[t * n + j] * zz[j];
+      vv[t] = u;
+    }
+  } else if (t < 64) {
+    // u = H_0 (H_1 (... (H_{n-3} z))), H_k = I - beta_k v_k v_k^T with v_k in
+    // column k of A below the diagonal; one wave
+    for (int k = n - 3; k >= 0; --k) {
+      const double bt = beta[k];
+      if (bt == 0.0) continue;  // uniform
+      const int m = n - k - 1;
+      double sp = 0.0;
+      for (int i = lane; i < m; i += 64) sp += A[L(k + 1 + i, k)] * zz[k + 1 + i];
+      const double sc = bt * wave_sum(sp);
+      for (int i = lane; i < m; i += 64) zz[k + 1 + i] -= sc * A[L(k + 1 + i, k)];
+      __builtin_amdgcn_wave_barrier();  // the next step reads other lanes' updates
+    }
+    for (int i = lane; i < n; i += 64) vv[i] = zz[i];
   }
   __syncthreads();
   // guess 0: the P-space eigenvector u; guess 1: the dense vector
@@ -2050,7 +2072,7 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
   if (t == 0) {
     S.m = 0;
     S.nguess = 1 + (dense ? 1 : 0);
-    S.np = n;
+    S.np = exact ? 0 : n;  // an exact guess needs no P-space correction
     S.onepass = 0;
     S.iters = 0;
     S.status = 0;
