@@ -1749,16 +1749,11 @@ __device__ double sc_offdiag(const ItemHam& H, uint64_t ia, uint64_t ib, uint64_
 // about P^3 against a Davidson iteration's ndet npair^2; below kPspaceMinDim
 // (where small P-spaces can also steer the solver to an excited root) they
 // start from `nunit` lowest-diagonal unit vectors with the diagonal
-// correction.  The dense vector is always added.
-constexpr int kPspaceRatio = 64;
-constexpr int kPspaceMinDim = 24;
-constexpr int kPspaceThreads = 512;
-
-__device__ __forceinline__ int pspace_dim(int64_t nd, int pmax) {
-  if (nd <= kMaxPspace) return (int)nd;
-  const int64_t p = nd / kPspaceRatio < pmax ? nd / kPspaceRatio : pmax;
-  return p >= kPspaceMinDim ? (int)p : 0;
-}
+// correction.  The dense vector is always added.  The reduction runs in
+// three instantiations over host-built item lists: P-spaces of larger
+// CASCIs (512 threads, Q in LDS), and CASCIs solved from their whole space
+// of at most 36 determinants (one wave) and of 37..112 (256 threads), which
+// need no Q, so that several of them share a CU.
 
 // Solve (theta - T) z = y for symmetric tridiagonal T (diagonal d, off-
 // diagonal e) by an LDL^T sweep without pivoting, pivots kept at |p| >= floor
@@ -1798,24 +1793,22 @@ __device__ inline int sturm_count(const double* d, const double* e, int n, doubl
   return cnt;
 }
 
-__global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
-    const Item* __restrict__ items, int ibase, const ItemHam* __restrict__ hams,
-    const double* __restrict__ diag, const int32_t* __restrict__ pidx, double* __restrict__ pQ,
-    double* __restrict__ pT, double* V, int64_t ntot, DavState* st, int pmax, int nunit) {
-  constexpr int PM = kMaxPspace;
-  constexpr int NT = kPspaceThreads;
-  __shared__ double A[PM * (PM + 1) / 2];
-  __shared__ double Q[PM * PM];
-  __shared__ uint64_t sa[PM], sb[PM];
-  __shared__ double vv[PM], pw[PM], dd[PM], ee[PM], beta[PM], zz[PM], piv[PM];
-  __shared__ double lo_hi[2];
-  __shared__ int cnt[NT];
+// Guess of the CASCIs without a P-space, one 256-thread block per item of
+// the view (the others return at once): a single determinant is its own
+// solution; otherwise unit vectors on the nunit lowest diagonal determinants
+// (idx is sorted) and the dense vector without those components in slot
+// nunit.
+__global__ void __launch_bounds__(256) k_pspace_guess(const Item* __restrict__ items, int ibase,
+                                                      const double* __restrict__ diag,
+                                                      const int32_t* __restrict__ pidx, double* V,
+                                                      int64_t ntot, DavState* st, int pmax,
+                                                      int nunit) {
   const int it = ibase + blockIdx.x;
   const Item& I = items[it];
   DavState& S = st[it];
-  const int t = threadIdx.x, lane = t & 63;
+  const int t = threadIdx.x;
   const int64_t nd = I.ndet;
-  const int32_t* __restrict__ idx = pidx + (int64_t)it * PM;
+  const int32_t* __restrict__ idx = pidx + (int64_t)it * kMaxPspace;
   if (nd == 1) {  // nothing to solve: the single determinant
     if (t == 0) {
       V[I.off] = 1.0;
@@ -1825,26 +1818,50 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
     }
     return;
   }
-  const int n = pspace_dim(nd, pmax);
-  if (n == 0) {
-    // unit vectors on the g lowest diagonal determinants (idx is sorted), the
-    // dense vector without those components in slot g
-    const int g = nunit;
-    const double sc = 1.0 / sqrt((double)(nd - g));
-    double* __restrict__ vr = V + (int64_t)g * ntot + I.off;
-    for (int64_t K = t; K < nd; K += NT) {
-      bool hit = false;
-      for (int j = 0; j < g; ++j) hit |= idx[j] == K;
-      vr[K] = hit ? 0.0 : hash_sign(K) * sc;
-    }
-    if (t < g) V[(int64_t)t * ntot + I.off + idx[t]] = 1.0;
-    if (t == 0) {
-      S.m = 0; S.nguess = g + 1; S.np = 0; S.iters = 0; S.status = 0; S.rnorm = 0.0; S.conv = 0;
-      S.onepass = 0;
-      S.theta = 0.0;
-    }
-    return;
+  if (pspace_dim(nd, pmax) != 0) return;
+  const int g = nunit;
+  const double sc = 1.0 / sqrt((double)(nd - g));
+  double* __restrict__ vr = V + (int64_t)g * ntot + I.off;
+  for (int64_t K = t; K < nd; K += 256) {
+    bool hit = false;
+    for (int j = 0; j < g; ++j) hit |= idx[j] == K;
+    vr[K] = hit ? 0.0 : hash_sign(K) * sc;
   }
+  if (t < g) V[(int64_t)t * ntot + I.off + idx[t]] = 1.0;
+  if (t == 0) {
+    S.m = 0; S.nguess = g + 1; S.np = 0; S.iters = 0; S.status = 0; S.rnorm = 0.0; S.conv = 0;
+    S.onepass = 0;
+    S.theta = 0.0;
+  }
+}
+
+// One block of NT threads per item of plist (absolute item indices).  PMAX
+// bounds the P-space held in LDS; EXACT: the items whose P-space is their
+// whole space (their guess is exact, so Q is not formed).
+template <int PMAX, int NT, bool EXACT>
+__global__ void __launch_bounds__(NT) k_pspace_eigen(
+    const Item* __restrict__ items, const int32_t* __restrict__ plist,
+    const ItemHam* __restrict__ hams, const double* __restrict__ diag,
+    const int32_t* __restrict__ pidx, double* __restrict__ pQ, double* __restrict__ pT, double* V,
+    int64_t ntot, DavState* st, int pmax) {
+  static_assert(NT >= PMAX && NT % 64 == 0, "a thread per P row");
+  static_assert(EXACT || NT / 4 >= PMAX, "four threads per column when forming Q");
+  constexpr int PM = kMaxPspace;  // stride of the per-item arrays in global memory
+  __shared__ double A[PMAX * (PMAX + 1) / 2];
+  __shared__ double Q[EXACT ? 1 : PMAX * PMAX];
+  __shared__ uint64_t sa[PMAX], sb[PMAX];
+  __shared__ double vv[PMAX], pw[PMAX], dd[PMAX], ee[PMAX], beta[PMAX], zz[PMAX], piv[PMAX];
+  __shared__ double lo_hi[2];
+  __shared__ int cnt[NT];
+  const int it = plist[blockIdx.x];
+  const Item& I = items[it];
+  DavState& S = st[it];
+  const int t = threadIdx.x, lane = t & 63;
+  const int64_t nd = I.ndet;
+  const int32_t* __restrict__ idx = pidx + (int64_t)it * PM;
+  const int n = pspace_dim(nd, pmax);
+  // the list holds only this class (checked again: a mismatch would overrun LDS)
+  if (nd == 1 || n == 0 || n > PMAX || (nd == n) != EXACT) return;
   const ItemHam& H = hams[I.ham];
   for (int k = t; k < n; k += NT) {
     const int e = idx[k];  // an address of this item: 0 <= e < ndet
@@ -1893,8 +1910,8 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
     __syncthreads();
     if (bt != 0.0) {
       // p = beta B v, four threads per row of the trailing block B
-      {
-        const int row = t >> 2, part = t & 3;
+      for (int row0 = 0; row0 < m; row0 += NT / 4) {
+        const int row = row0 + (t >> 2), part = t & 3;
         double acc = 0.0;
         if (row < m) {
 #pragma unroll 4
@@ -1929,9 +1946,8 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
   // A CASCI whose P block is its whole space converges on this guess, so it
   // needs no correction and no explicit Q: the guess Q z is formed from the
   // reflectors below.
-  const bool exact = nd == n;
   // ---- Q = H_0 H_1 ... H_{n-3}, accumulated backwards from the identity
-  if (!exact) {
+  if constexpr (!EXACT) {
   for (int x = t; x < n * n; x += NT) Q[x] = (x / n == x % n) ? 1.0 : 0.0;
   __syncthreads();
   for (int k = n - 3; k >= 0; --k) {
@@ -1982,9 +1998,10 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
     lo_hi[1] = hi;
   }
   __syncthreads();
-  // six rounds of NT points narrow the interval by NT^6 ~ 1.8e16, to the
-  // rounding level of the spectrum
-  for (int round = 0; round < 6; ++round) {
+  // rounds of NT points narrow the interval by NT^rounds >= 1.8e16, to the
+  // rounding level of the spectrum (512^6, 256^7, 64^9)
+  constexpr int kRounds = NT >= 512 ? 6 : NT >= 256 ? 7 : 9;
+  for (int round = 0; round < kRounds; ++round) {
     const double lo = lo_hi[0], hi = lo_hi[1];
     const double x = lo + (hi - lo) * (double)(t + 1) / (double)NT;
     const int c = sturm_count(dd, ee, n, x);
@@ -2017,7 +2034,7 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
   }
   __syncthreads();
   // ---- outputs: Q (row = P position), T, the guess vectors
-  if (!exact) {
+  if constexpr (!EXACT) {
     double* __restrict__ Qo = pQ + (int64_t)it * PM * PM;
     for (int x = t; x < n * n; x += NT) Qo[(x / n) * PM + (x % n)] = Q[x];
     double* __restrict__ To = pT + (int64_t)it * 2 * PM;
@@ -2031,7 +2048,7 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
       for (int j = 0; j < n; ++j) u += Q[t * n + j] * zz[j];
       vv[t] = u;
     }
-  } else if (t < 64) {
+  } else if (t < 64) {  // EXACT
     // u = H_0 (H_1 (... (H_{n-3} z))), H_k = I - beta_k v_k v_k^T with v_k in
     // column k of A below the diagonal; one wave
     for (int k = n - 3; k >= 0; --k) {
@@ -2072,7 +2089,7 @@ __global__ void __launch_bounds__(kPspaceThreads) k_pspace_eigen(
   if (t == 0) {
     S.m = 0;
     S.nguess = 1 + (dense ? 1 : 0);
-    S.np = exact ? 0 : n;  // an exact guess needs no P-space correction
+    S.np = EXACT ? 0 : n;  // an exact guess needs no P-space correction
     S.onepass = 0;
     S.iters = 0;
     S.status = 0;
@@ -2839,17 +2856,26 @@ void launch_dav_rr(const Item* items, int ibase, int nitem, const double* part, 
                    int slot, hipStream_t s) {
   hipLaunchKernelGGL(k_dav_rr, dim3(nitem), dim3(64), 0, s, items, ibase, part, st, slot);
 }
-void launch_pspace_setup(const Item* items, int ibase, int nitem, const ItemHam* hams,
-                         const double* diag, int32_t* pidx, double* pQ, double* pT, double* V,
-                         int64_t ntot, DavState* st, int pmax, int nunit,
+void launch_pspace_setup(const Item* items, int ibase, int nitem, const PspaceLists& pl,
+                         const ItemHam* hams, const double* diag, int32_t* pidx, double* pQ,
+                         double* pT, double* V, int64_t ntot, DavState* st, int pmax, int nunit,
                          const PspaceSelect& sel, hipStream_t s) {
   if (sel.nwork > 0)
     hipLaunchKernelGGL(k_pspace_select_chunk, dim3(sel.nwork), dim3(256), 0, s, items, sel.work,
                        ibase, nitem, diag, sel.hi, sel.lo, pmax);
   hipLaunchKernelGGL(k_pspace_select, dim3(nitem), dim3(256), 0, s, items, ibase, diag, pidx, pmax,
                      sel.slot, sel.hi, sel.lo);
-  hipLaunchKernelGGL(k_pspace_eigen, dim3(nitem), dim3(kPspaceThreads), 0, s, items, ibase, hams,
-                     diag, pidx, pQ, pT, V, ntot, st, pmax, nunit);
+  hipLaunchKernelGGL(k_pspace_guess, dim3(nitem), dim3(256), 0, s, items, ibase, diag, pidx, V,
+                     ntot, st, pmax, nunit);
+  if (pl.n[0] > 0)
+    hipLaunchKernelGGL((k_pspace_eigen<kMaxPspace, 512, false>), dim3(pl.n[0]), dim3(512), 0, s,
+                       items, pl.list[0], hams, diag, pidx, pQ, pT, V, ntot, st, pmax);
+  if (pl.n[1] > 0)
+    hipLaunchKernelGGL((k_pspace_eigen<kExactSmall, 64, true>), dim3(pl.n[1]), dim3(64), 0, s,
+                       items, pl.list[1], hams, diag, pidx, pQ, pT, V, ntot, st, pmax);
+  if (pl.n[2] > 0)
+    hipLaunchKernelGGL((k_pspace_eigen<kMaxPspace, 256, true>), dim3(pl.n[2]), dim3(256), 0, s,
+                       items, pl.list[2], hams, diag, pidx, pQ, pT, V, ntot, st, pmax);
 }
 void launch_dav_iteration(const Item* items, int ibase, int nitem, const Work* chunks, int nchunk,
                           double* V, double* Sv, const double* diag, int64_t ntot, DavState* st,

@@ -50,6 +50,31 @@ struct PspaceArgs {
 // determinants a work unit (item, chunk, first candidate slot of the item),
 // per item its first slot or -1, and the candidate keys (kMaxPspace per slot)
 constexpr int64_t kSelectChunk = 16384;
+// P-space size of a CASCI of nd determinants: its whole space up to
+// kMaxPspace determinants, else min(pmax, nd / kPspaceRatio) when that
+// reaches kPspaceMinDim, else 0 (unit-vector guess, diagonal correction).
+constexpr int kPspaceRatio = 64;
+constexpr int kPspaceMinDim = 24;
+__host__ __device__ inline int pspace_dim(int64_t nd, int pmax) {
+  if (nd <= kMaxPspace) return (int)nd;
+  const int64_t p = nd / kPspaceRatio < pmax ? nd / kPspaceRatio : pmax;
+  return p >= kPspaceMinDim ? (int)p : 0;
+}
+// Which P-space reduction a CASCI takes: 0 its P-space (more than
+// kMaxPspace determinants), 1 its whole space of at most kExactSmall
+// determinants, 2 its whole space of more; -1 none (a single determinant or
+// unit-vector guesses).
+constexpr int kExactSmall = 36;
+__host__ __device__ inline int pspace_class(int64_t nd, int pmax) {
+  if (nd <= 1 || pspace_dim(nd, pmax) == 0) return -1;
+  if (nd > kMaxPspace) return 0;
+  return nd <= kExactSmall ? 1 : 2;
+}
+// per class, the items of a view that take it (absolute indices, ascending)
+struct PspaceLists {
+  const int32_t* list[3];
+  int n[3];
+};
 struct PspaceSelect {
   const Work* work;
   int nwork;
@@ -57,9 +82,9 @@ struct PspaceSelect {
   uint64_t* hi;
   uint32_t* lo;
 };
-void launch_pspace_setup(const Item* items, int ibase, int nitem, const ItemHam* hams,
-                         const double* diag, int32_t* pidx, double* pQ, double* pT, double* V,
-                         int64_t ntot, DavState* st, int pmax, int nunit,
+void launch_pspace_setup(const Item* items, int ibase, int nitem, const PspaceLists& pl,
+                         const ItemHam* hams, const double* diag, int32_t* pidx, double* pQ,
+                         double* pT, double* V, int64_t ntot, DavState* st, int pmax, int nunit,
                          const PspaceSelect& sel, hipStream_t s);
 void launch_dav_iteration(const Item* items, int ibase, int nitem, const Work* chunks, int nchunk,
                           double* V, double* Sv, const double* diag, int64_t ntot, DavState* st,

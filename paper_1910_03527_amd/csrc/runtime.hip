@@ -108,6 +108,10 @@ struct Plan {
   // Gram-Schmidt dot corrections; null when the P-space is off
   int32_t* pidx = nullptr;
   double *pQ = nullptr, *pT = nullptr, *pdots = nullptr;
+  // the items of each P-space class (pspace_class), ascending; host copies
+  // kept for the views' sub-ranges and while the uploads may be in flight
+  std::vector<int32_t> pcls_h[3];
+  int32_t* pcls[3] = {nullptr, nullptr, nullptr};
   // chunked selection of the P-space of CASCIs above kSelectChunk
   // determinants (host copies kept while the uploads may be in flight)
   std::vector<Work> psel_works;
@@ -482,6 +486,16 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
     P.pQ = arena<double>(c, "pQ", (size_t)P.nitem * kMaxPspace * kMaxPspace, &grown);
     P.pT = arena<double>(c, "pT", (size_t)P.nitem * 2 * kMaxPspace, &grown);
     P.pdots = arena<double>(c, "pdots", (size_t)P.nitem * (kMaxSpace + 1), &grown);
+    for (int q = 0; q < 3; ++q) P.pcls_h[q].clear();
+    for (int i = 0; i < P.nitem; ++i) {
+      const int q = pspace_class(P.items[i].ndet, c->opts.pspace);
+      if (q >= 0) P.pcls_h[q].push_back(i);
+    }
+    for (int q = 0; q < 3; ++q) {
+      P.pcls[q] = arena<int32_t>(c, "pclass" + std::to_string(q),
+                                 std::max<size_t>(P.pcls_h[q].size(), 1), &grown);
+      upload(c, P.pcls[q], P.pcls_h[q]);
+    }
     P.psel_works.clear();
     P.psel_slots.assign(P.nitem, -1);
     int32_t nslot = 0;
@@ -691,7 +705,15 @@ void solve_view(mbefci_ctx* c, Plan& P, const View& v, int* graph_launches) {
   if (P.pidx) {
     const PspaceSelect sel{P.psel_work, (int)P.psel_works.size(), P.psel_slot, P.psel_hi,
                            P.psel_lo};
-    launch_pspace_setup(P.d_items, v.ibase, v.nitem, P.hams, P.diag, P.pidx, P.pQ, P.pT, P.V,
+    PspaceLists pl{};
+    for (int q = 0; q < 3; ++q) {
+      const auto& h = P.pcls_h[q];
+      const auto lo = std::lower_bound(h.begin(), h.end(), v.ibase);
+      const auto hi = std::lower_bound(lo, h.end(), v.ibase + v.nitem);
+      pl.list[q] = P.pcls[q] + (lo - h.begin());
+      pl.n[q] = (int)(hi - lo);
+    }
+    launch_pspace_setup(P.d_items, v.ibase, v.nitem, pl, P.hams, P.diag, P.pidx, P.pQ, P.pT, P.V,
                         P.ntot, P.st, c->opts.pspace, g, sel, c->stream);
     g += 1;  // unit vectors (or the P-space eigenvector) and the dense vector
   } else {
