@@ -61,19 +61,21 @@ __host__ __device__ inline int pspace_dim(int64_t nd, int pmax) {
   return p >= kPspaceMinDim ? (int)p : 0;
 }
 // Which P-space reduction a CASCI takes: 0 its P-space (more than
-// kMaxPspace determinants), 1 its whole space of at most kExactSmall
-// determinants, 2 its whole space of more; -1 none (a single determinant or
-// unit-vector guesses).
+// kMaxPspace determinants); its whole space of 1 at most kExactSmall,
+// 2 at most kExactMid, 3 at most kMaxPspace determinants; -1 none (a single
+// determinant or unit-vector guesses).
 constexpr int kExactSmall = 36;
+constexpr int kExactMid = 100;
+constexpr int kPspaceClasses = 4;
 __host__ __device__ inline int pspace_class(int64_t nd, int pmax) {
   if (nd <= 1 || pspace_dim(nd, pmax) == 0) return -1;
   if (nd > kMaxPspace) return 0;
-  return nd <= kExactSmall ? 1 : 2;
+  return nd <= kExactSmall ? 1 : nd <= kExactMid ? 2 : 3;
 }
 // per class, the items of a view that take it (absolute indices, ascending)
 struct PspaceLists {
-  const int32_t* list[3];
-  int n[3];
+  const int32_t* list[kPspaceClasses];
+  int n[kPspaceClasses];
 };
 struct PspaceSelect {
   const Work* work;

@@ -110,8 +110,8 @@ struct Plan {
   double *pQ = nullptr, *pT = nullptr, *pdots = nullptr;
   // the items of each P-space class (pspace_class), ascending; host copies
   // kept for the views' sub-ranges and while the uploads may be in flight
-  std::vector<int32_t> pcls_h[3];
-  int32_t* pcls[3] = {nullptr, nullptr, nullptr};
+  std::vector<int32_t> pcls_h[kPspaceClasses];
+  int32_t* pcls[kPspaceClasses] = {};
   // chunked selection of the P-space of CASCIs above kSelectChunk
   // determinants (host copies kept while the uploads may be in flight)
   std::vector<Work> psel_works;
@@ -486,12 +486,12 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
     P.pQ = arena<double>(c, "pQ", (size_t)P.nitem * kMaxPspace * kMaxPspace, &grown);
     P.pT = arena<double>(c, "pT", (size_t)P.nitem * 2 * kMaxPspace, &grown);
     P.pdots = arena<double>(c, "pdots", (size_t)P.nitem * (kMaxSpace + 1), &grown);
-    for (int q = 0; q < 3; ++q) P.pcls_h[q].clear();
+    for (int q = 0; q < kPspaceClasses; ++q) P.pcls_h[q].clear();
     for (int i = 0; i < P.nitem; ++i) {
       const int q = pspace_class(P.items[i].ndet, c->opts.pspace);
       if (q >= 0) P.pcls_h[q].push_back(i);
     }
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < kPspaceClasses; ++q) {
       P.pcls[q] = arena<int32_t>(c, "pclass" + std::to_string(q),
                                  std::max<size_t>(P.pcls_h[q].size(), 1), &grown);
       upload(c, P.pcls[q], P.pcls_h[q]);
@@ -706,7 +706,7 @@ void solve_view(mbefci_ctx* c, Plan& P, const View& v, int* graph_launches) {
     const PspaceSelect sel{P.psel_work, (int)P.psel_works.size(), P.psel_slot, P.psel_hi,
                            P.psel_lo};
     PspaceLists pl{};
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < kPspaceClasses; ++q) {
       const auto& h = P.pcls_h[q];
       const auto lo = std::lower_bound(h.begin(), h.end(), v.ibase);
       const auto hi = std::lower_bound(lo, h.end(), v.ibase + v.nitem);
