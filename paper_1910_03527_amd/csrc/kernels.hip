@@ -1750,10 +1750,11 @@ __device__ double sc_offdiag(const ItemHam& H, uint64_t ia, uint64_t ib, uint64_
 // (where small P-spaces can also steer the solver to an excited root) they
 // start from `nunit` lowest-diagonal unit vectors with the diagonal
 // correction.  The dense vector is always added.  The reduction runs in
-// four instantiations over host-built item lists: P-spaces of larger
-// CASCIs (512 threads, Q in LDS), and CASCIs solved from their whole space
-// of at most 36 determinants (one wave), 37..100 and 101..112 (256 threads),
-// which need no Q and are sized so that several of them share a CU.
+// five instantiations over host-built item lists: P-spaces of larger
+// CASCIs (512 threads, Q in LDS; sized for 112 and for 76), and CASCIs
+// solved from their whole space of at most 36 determinants (one wave),
+// 37..100 and 101..112 (256 threads), which need no Q; the sizes let
+// several blocks share a CU.
 
 // Solve (theta - T) z = y for symmetric tridiagonal T (diagonal d, off-
 // diagonal e) by an LDL^T sweep without pivoting, pivots kept at |p| >= floor
@@ -2879,6 +2880,9 @@ void launch_pspace_setup(const Item* items, int ibase, int nitem, const PspaceLi
   if (pl.n[3] > 0)
     hipLaunchKernelGGL((k_pspace_eigen<kMaxPspace, 256, true>), dim3(pl.n[3]), dim3(256), 0, s,
                        items, pl.list[3], hams, diag, pidx, pQ, pT, V, ntot, st, pmax);
+  if (pl.n[4] > 0)
+    hipLaunchKernelGGL((k_pspace_eigen<kPspaceMid, 512, false>), dim3(pl.n[4]), dim3(512), 0, s,
+                       items, pl.list[4], hams, diag, pidx, pQ, pT, V, ntot, st, pmax);
 }
 void launch_dav_iteration(const Item* items, int ibase, int nitem, const Work* chunks, int nchunk,
                           double* V, double* Sv, const double* diag, int64_t ntot, DavState* st,

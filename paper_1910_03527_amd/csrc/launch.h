@@ -60,16 +60,18 @@ __host__ __device__ inline int pspace_dim(int64_t nd, int pmax) {
   const int64_t p = nd / kPspaceRatio < pmax ? nd / kPspaceRatio : pmax;
   return p >= kPspaceMinDim ? (int)p : 0;
 }
-// Which P-space reduction a CASCI takes: 0 its P-space (more than
-// kMaxPspace determinants); its whole space of 1 at most kExactSmall,
-// 2 at most kExactMid, 3 at most kMaxPspace determinants; -1 none (a single
-// determinant or unit-vector guesses).
+// Which P-space reduction a CASCI takes: a P-space of a larger CASCI of
+// 0 more than kPspaceMid, 4 at most kPspaceMid determinants; its whole space
+// of 1 at most kExactSmall, 2 at most kExactMid, 3 at most kMaxPspace
+// determinants; -1 none (a single determinant or unit-vector guesses).
 constexpr int kExactSmall = 36;
 constexpr int kExactMid = 100;
-constexpr int kPspaceClasses = 4;
+constexpr int kPspaceMid = 76;
+constexpr int kPspaceClasses = 5;
 __host__ __device__ inline int pspace_class(int64_t nd, int pmax) {
-  if (nd <= 1 || pspace_dim(nd, pmax) == 0) return -1;
-  if (nd > kMaxPspace) return 0;
+  const int p = nd <= 1 ? 0 : pspace_dim(nd, pmax);
+  if (p == 0) return -1;
+  if (nd > kMaxPspace) return p <= kPspaceMid ? 4 : 0;
   return nd <= kExactSmall ? 1 : nd <= kExactMid ? 2 : 3;
 }
 // per class, the items of a view that take it (absolute indices, ascending)
