@@ -1737,9 +1737,9 @@ __device__ double sc_offdiag(const ItemHam& H, uint64_t ia, uint64_t ib, uint64_
   return par ? -v : v;
 }
 
-// One 512-thread block per item: build H_PP (packed lower triangle in LDS)
-// and reduce it to tridiagonal form by Householder reflections,
-// H_PP = Q T Q^T (T: diagonal d, off-diagonal e; Q accumulated explicitly).
+// One block per item: build H_PP (packed lower triangle in LDS) and reduce
+// it to tridiagonal form by Householder reflections, H_PP = Q T Q^T (T:
+// diagonal d, off-diagonal e; Q accumulated explicitly for a P-space).
 // The lowest eigenvalue of T comes from multisection on Sturm counts (every
 // thread evaluates one point per round), its eigenvector from inverse
 // iteration; the guess is Q z.  A CASCI of at most kMaxPspace determinants
