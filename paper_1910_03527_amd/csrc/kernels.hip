@@ -375,7 +375,7 @@ __device__ inline bool item_active(const DavState& st, int slot) {
 // the c row of Ka is staged in LDS.  The alpha half of a D+ entry is
 // wave-uniform: a scalar pair-table load and a coalesced row segment of c.
 // D+ [pair][TN] (B operand) is staged in LDS, the wave's W rows (A operand)
-// sit in registers.  G is stored [Ka][pair][Kb].
+// sit in registers.  G is stored [Ka][pair][Kb], rows g_stride(Nb) long.
 constexpr int64_t binom_c(int n, int k) {
   int64_t r = 1;
   for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
@@ -568,7 +568,8 @@ __global__ void __launch_bounds__(256, (TN == 32 && NACT <= 10) ? 4 : 1) k_sigma
         if (ks + 1 < KS) __builtin_amdgcn_sched_group_barrier(0x100, NCB, 0);
         __builtin_amdgcn_sched_group_barrier(0x008, NCB, 0);
       }
-      double* __restrict__ Grow = G + (int64_t)Ka * NP * Nb;
+      const int Gs = g_stride(Nb);  // row stride of G
+      double* __restrict__ Grow = G + (int64_t)Ka * NP * Gs;
 #pragma unroll
       for (int cb2 = 0; cb2 < NCB; ++cb2) {
         const int Kc = Kb0 + cb2 * 16 + (lane & 15);
@@ -578,7 +579,7 @@ __global__ void __launch_bounds__(256, (TN == 32 && NACT <= 10) ? 4 : 1) k_sigma
             // gfx950 FP64 16x16x4 output layout: register v of lane l is
             // row l/16 + 4v, column l%16 of the 16x16 block
             const int row = rb * 16 + (lane >> 4) + 4 * v;
-            if (row < NP) Grow[row * Nb + Kc] = acc[cb2][v];
+            if (row < NP) Grow[row * Gs + Kc] = acc[cb2][v];
           }
         }
       }
@@ -764,11 +765,11 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm_flat(const Item* __restrict
         const int Kc = tile * TN + cb2 * 16 + (lane & 15);
         if (Kc < nd) {
           const int kac = Kc / Nb, kbc = Kc - kac * Nb;
-          double* __restrict__ Grow = G + (int64_t)kac * NP * Nb + kbc;
+          double* __restrict__ Grow = G + (int64_t)kac * NP * g_stride(Nb) + kbc;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int row = rb * 16 + (lane >> 4) + 4 * v;
-            if (row < NP) Grow[row * Nb] = acc[cb2][v];
+            if (row < NP) Grow[row * g_stride(Nb)] = acc[cb2][v];
           }
         }
       }
@@ -801,41 +802,42 @@ __global__ void __launch_bounds__(256) k_sigma_gather(const Item* __restrict__ i
   const int Kb = (seg % segs) * 64 + (threadIdx.x & 63);
   if (Kb >= Nb) return;
   const double* __restrict__ G = Garena + I.goff;
+  const int Gs = g_stride(Nb);  // row stride of G
   const int La = I.La, Lb = I.Lb;
   double acc0 = 0.0, acc1 = 0.0;
   const int np = I.npair;
   const uint32_t* __restrict__ la = I.linkA + Ka * La;
-  const double* __restrict__ Gcol = G + Kb;  // G[(Ja * npair + pair) * Nb + Kb]
+  const double* __restrict__ Gcol = G + Kb;  // G[(Ja * npair + pair) * Gs + Kb]
   int l = 0;
   for (; l + 3 < La; l += 4) {
     const uint32_t e0 = ldc(la + l), e1 = ldc(la + l + 1), e2 = ldc(la + l + 2), e3 = ldc(la + l + 3);
-    const double g0 = ldg(Gcol + (int64_t)(link_addr(e0) * np + link_pair(e0)) * Nb);
-    const double g1 = ldg(Gcol + (int64_t)(link_addr(e1) * np + link_pair(e1)) * Nb);
-    const double g2 = ldg(Gcol + (int64_t)(link_addr(e2) * np + link_pair(e2)) * Nb);
-    const double g3 = ldg(Gcol + (int64_t)(link_addr(e3) * np + link_pair(e3)) * Nb);
+    const double g0 = ldg(Gcol + (int64_t)(link_addr(e0) * np + link_pair(e0)) * Gs);
+    const double g1 = ldg(Gcol + (int64_t)(link_addr(e1) * np + link_pair(e1)) * Gs);
+    const double g2 = ldg(Gcol + (int64_t)(link_addr(e2) * np + link_pair(e2)) * Gs);
+    const double g3 = ldg(Gcol + (int64_t)(link_addr(e3) * np + link_pair(e3)) * Gs);
     acc0 += link_sign(e0) * g0 + link_sign(e2) * g2;
     acc1 += link_sign(e1) * g1 + link_sign(e3) * g3;
   }
   for (; l < La; ++l) {
     const uint32_t e0 = ldc(la + l);
-    acc0 += link_sign(e0) * ldg(Gcol + (int64_t)(link_addr(e0) * np + link_pair(e0)) * Nb);
+    acc0 += link_sign(e0) * ldg(Gcol + (int64_t)(link_addr(e0) * np + link_pair(e0)) * Gs);
   }
   const uint32_t* __restrict__ lb = I.linkBT + Kb;               // link l of Kb: lb[l * Nb]
-  const double* __restrict__ Grow = G + (int64_t)Ka * np * Nb;  // G[(Ka * npair + pair) * Nb + Jb]
+  const double* __restrict__ Grow = G + (int64_t)Ka * np * Gs;  // G[(Ka * npair + pair) * Gs + Jb]
   l = 0;
   for (; l + 3 < Lb; l += 4) {
     const uint32_t e0 = ldg(lb + l * Nb), e1 = ldg(lb + (l + 1) * Nb), e2 = ldg(lb + (l + 2) * Nb),
                    e3 = ldg(lb + (l + 3) * Nb);
-    const double g0 = ldg(Grow + link_pair(e0) * Nb + link_addr(e0));
-    const double g1 = ldg(Grow + link_pair(e1) * Nb + link_addr(e1));
-    const double g2 = ldg(Grow + link_pair(e2) * Nb + link_addr(e2));
-    const double g3 = ldg(Grow + link_pair(e3) * Nb + link_addr(e3));
+    const double g0 = ldg(Grow + link_pair(e0) * Gs + link_addr(e0));
+    const double g1 = ldg(Grow + link_pair(e1) * Gs + link_addr(e1));
+    const double g2 = ldg(Grow + link_pair(e2) * Gs + link_addr(e2));
+    const double g3 = ldg(Grow + link_pair(e3) * Gs + link_addr(e3));
     acc0 += link_sign(e0) * g0 + link_sign(e2) * g2;
     acc1 += link_sign(e1) * g1 + link_sign(e3) * g3;
   }
   for (; l < Lb; ++l) {
     const uint32_t e0 = ldg(lb + l * Nb);
-    acc0 += link_sign(e0) * ldg(Grow + link_pair(e0) * Nb + link_addr(e0));
+    acc0 += link_sign(e0) * ldg(Grow + link_pair(e0) * Gs + link_addr(e0));
   }
   Sarena[(int64_t)vs * ntot + I.off + (int64_t)Ka * Nb + Kb] = acc0 + acc1;
 }

@@ -50,6 +50,15 @@ struct PspaceArgs {
 // determinants a work unit (item, chunk, first candidate slot of the item),
 // per item its first slot or -1, and the candidate keys (kMaxPspace per slot)
 constexpr int64_t kSelectChunk = 16384;
+// Row stride of G (doubles): the beta-string count rounded up to 16, so
+// that every row of G starts on a 128-byte line, when that adds at most
+// 1/16 to the row (252 -> 256, 3432 -> 3440); short rows, where padding
+// would grow G by up to 60%, keep their length.  Item offsets into G are
+// multiples of 16 doubles.
+__host__ __device__ inline int g_stride(int nb) {
+  const int p = (nb + 15) & ~15;
+  return (p - nb) * 16 <= nb ? p : nb;
+}
 // P-space size of a CASCI of nd determinants: its whole space up to
 // kMaxPspace determinants, else min(pmax, nd / kPspaceRatio) when that
 // reaches kPspaceMinDim, else 0 (unit-vector guess, diagonal correction).

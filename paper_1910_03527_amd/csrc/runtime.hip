@@ -358,8 +358,9 @@ int64_t build_passes(mbefci_ctx* c, Plan& P) {
     for (int i = 0; i < P.nitem; ++i) {
       Item& I = P.items[i];
       if (I.ndet <= 1) continue;
-      const int64_t gb = (int64_t)I.npair * I.ndet;
-      if (gpass > 0 && (gpass + gb) * 8 > cap) close(i);
+      const int64_t gb = (int64_t)I.npair * I.Na * g_stride(I.Nb);
+      if (gpass > 0 && (((gpass + 15) & ~(int64_t)15) + gb) * 8 > cap) close(i);
+      gpass = (gpass + 15) & ~(int64_t)15;  // a 128-byte line
       I.goff = gpass;
       gpass += gb;
       const int g = P.item_group[i];
@@ -422,8 +423,9 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
     I.ham = i;
     P.ndet_total += I.ndet;
     if (I.ndet > 1) {
+      goff = (goff + 15) & ~(int64_t)15;  // a 128-byte line
       I.goff = goff;
-      goff += (int64_t)I.npair * I.ndet;
+      goff += (int64_t)I.npair * I.Na * g_stride(I.Nb);
       I.woff = woff;
       woff += (int64_t)I.kpad * I.kpad;
     } else {
