@@ -573,7 +573,7 @@ __global__ void __launch_bounds__(256, (TN == 32 && NACT <= 10) ? 4 : 1) k_sigma
 #pragma unroll
       for (int cb2 = 0; cb2 < NCB; ++cb2) {
         const int Kc = Kb0 + cb2 * 16 + (lane & 15);
-        if (Kc < Nb) {
+        if (Kc < Gs) {  // the row's padding too (zero: D+ is zero there), whole lines
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             // gfx950 FP64 16x16x4 output layout: register v of lane l is
