@@ -293,6 +293,15 @@ typedef struct {
 } mbefci_kernel_time;
 int mbefci_time_kernels(mbefci_ctx* ctx, int32_t reps, mbefci_kernel_time* out, int32_t cap,
                         int32_t* count);
+/* The device's attainable peaks, measured on ctx's device and stream:
+ * *fp64_mfma_tflops from eight independent chains of v_mfma_f64_16x16x4f64
+ * per wave issued from registers (16 blocks of 256 threads per CU, best of
+ * three launches), *copy_gbps from
+ * a 16-byte-vector copy of 256 MiB (bytes read plus written, best of five).
+ * They put the roofline fractions beside the published peaks (78.6 TFLOP/s
+ * FP64 matrix, 8 TB/s HBM).  Uses a 512 MiB workspace that the context
+ * keeps until it is destroyed.  Errors: EINVAL (null output), EDEVICE. */
+int mbefci_probe_peaks(mbefci_ctx* ctx, double* fp64_mfma_tflops, double* copy_gbps);
 
 #ifdef __cplusplus
 }

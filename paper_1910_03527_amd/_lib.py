@@ -23,7 +23,7 @@ EXPORTS = (
     "mbefci_set_opts", "mbefci_set_allocator", "mbefci_num_strings", "mbefci_num_links", "mbefci_strings",
     "mbefci_link_table", "mbefci_num_tuples", "mbefci_hdiag", "mbefci_sigma", "mbefci_casci",
     "mbefci_casci_rdm", "mbefci_mbe_forward", "mbefci_mbe_backward", "mbefci_mbe_screened",
-    "mbefci_screened_tuples", "mbefci_partition", "mbefci_time_kernels",
+    "mbefci_screened_tuples", "mbefci_partition", "mbefci_time_kernels", "mbefci_probe_peaks",
 )
 
 
@@ -178,6 +178,9 @@ def load():
     L.mbefci_time_kernels.argtypes = [vp, i32, ctypes.POINTER(KernelTime), i32,
                                       ctypes.POINTER(i32)]
     L.mbefci_time_kernels.restype = ctypes.c_int
+    L.mbefci_probe_peaks.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+    L.mbefci_probe_peaks.restype = ctypes.c_int
     _lib = L
     return L
 

@@ -305,6 +305,13 @@ class Context:
         self._check(self._L.mbefci_time_kernels(self._h, int(reps), arr, cap, ctypes.byref(cnt)))
         return [arr[i].as_dict() for i in range(min(cnt.value, cap))]
 
+    def probe_peaks(self):
+        """Measured FP64 MFMA and copy peaks of the device (mbefci_probe_peaks):
+        dict(fp64_mfma_tflops, copy_gbps)."""
+        tf, gb = ctypes.c_double(), ctypes.c_double()
+        self._check(self._L.mbefci_probe_peaks(self._h, ctypes.byref(tf), ctypes.byref(gb)))
+        return {"fp64_mfma_tflops": tf.value, "copy_gbps": gb.value}
+
     def mbe_backward(self, grad_out):
         """d(g0 E_ref + sum_n g_n E^(n)) / d(h1, eri) of the last forward."""
         if self._fwd is None:

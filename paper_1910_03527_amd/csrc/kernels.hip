@@ -2837,6 +2837,43 @@ void launch_sigma_gather(const Item* items, const Work* work, int nwork, const d
                        slot);
 }
 
+// ------------------------------------------------------- peak probes
+// Measurement only, off the solver's path.  k_probe_mfma runs independent
+// chains of FP64 16x16x4 MFMAs per wave from registers (no memory traffic);
+// the sum is stored only if it equals a value the inputs never produce,
+// which keeps the chains live.  k_probe_copy copies 16-byte vectors.
+__global__ void __launch_bounds__(256) k_probe_mfma(double* out, int iters, double seed) {
+  constexpr int CH = 8;
+  double4_t acc[CH];
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch) acc[ch] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  const double a = seed + threadIdx.x * 1e-3, b = 0.5 * seed + threadIdx.x * 1e-4;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) acc[ch] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[ch], 0, 0, 0);
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch) s += acc[ch][0] + acc[ch][1] + acc[ch][2] + acc[ch][3];
+  if (s == -12345.678) out[threadIdx.x] = s;
+}
+__global__ void __launch_bounds__(256) k_probe_copy(const double2* __restrict__ src,
+                                                    double2* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    dst[i] = src[i];
+}
+constexpr int kProbeMfmaChains = 8;  // the chains of k_probe_mfma
+void launch_probe_mfma(double* out, int blocks, int iters, hipStream_t s) {
+  hipLaunchKernelGGL(k_probe_mfma, dim3(blocks), dim3(256), 0, s, out, iters, 1.0);
+}
+double probe_mfma_flops(int blocks, int iters) {
+  return (double)blocks * 4.0 * iters * kProbeMfmaChains * 2.0 * 16 * 16 * 4;
+}
+void launch_probe_copy(const double* src, double* dst, int64_t n, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_probe_copy, dim3(blocks), dim3(256), 0, s,
+                     reinterpret_cast<const double2*>(src), reinterpret_cast<double2*>(dst), n / 2);
+}
+
 void launch_fill(double* p, int64_t n, double v, hipStream_t s) {
   if (n <= 0) return;
   int64_t b = nblk(n, 256);

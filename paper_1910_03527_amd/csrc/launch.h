@@ -29,6 +29,11 @@ bool launch_sigma_dgemm(int n, int tn, const Item* items, const Work* work, int 
 void launch_sigma_gather(const Item* items, const Work* work, int nwork, const double* G,
                          double* Sv, int64_t ntot, const DavState* st, int slot, hipStream_t s);
 void launch_fill(double* p, int64_t n, double v, hipStream_t s);
+// peak probes: FP64 MFMA chains (256-thread blocks; flops of one launch from
+// probe_mfma_flops) and a copy of n doubles (n even, 16-byte aligned)
+void launch_probe_mfma(double* out, int blocks, int iters, hipStream_t s);
+double probe_mfma_flops(int blocks, int iters);
+void launch_probe_copy(const double* src, double* dst, int64_t n, int blocks, hipStream_t s);
 void launch_dav_guess(const Item* items, int ibase, int nitem, const double* diag, double* V,
                       int64_t ntot, DavState* st, int nguess, hipStream_t s);
 void launch_dav_dots(const Item* items, const Work* chunks, int nchunk, const double* V,

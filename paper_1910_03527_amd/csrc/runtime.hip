@@ -1714,6 +1714,47 @@ int mbefci_mbe_backward(mbefci_ctx* c, const double* grad_out, double* d_h1, dou
   });
 }
 
+int mbefci_probe_peaks(mbefci_ctx* c, double* fp64_mfma_tflops, double* copy_gbps) {
+  return guarded(c, [&] {
+    if (!fp64_mfma_tflops || !copy_gbps) throw Error(MBEFCI_EINVAL, "null output");
+    HIPCHK(hipSetDevice(c->device));
+    int ncu = 0;
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+    const int64_t n = (int64_t)32 << 20;  // doubles per copy buffer: 256 MiB
+    double* buf = arena<double>(c, "probe", (size_t)(2 * n + 256));
+    double* src = buf;
+    double* dst = buf + n;
+    double* out = buf + 2 * n;
+    launch_fill(src, n, 1.0, c->stream);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto timed = [&](auto&& launch, int reps) {
+      float best = 1e30f;
+      launch();  // warm
+      for (int r = 0; r < reps; ++r) {
+        HIPCHK(hipEventRecord(e0, c->stream));
+        launch();
+        HIPCHK(hipEventRecord(e1, c->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        best = std::min(best, ms);
+      }
+      return (double)best;
+    };
+    // sixteen blocks per CU in flight or queued, eight chains per wave: the
+    // rate no longer rises with either (measured), about 10 ms per launch
+    const int mblocks = 16 * ncu, iters = 2000;
+    const double tm = timed([&] { launch_probe_mfma(out, mblocks, iters, c->stream); }, 3);
+    const double tc = timed([&] { launch_probe_copy(src, dst, n, 4 * ncu * 8, c->stream); }, 5);
+    HIPCHK(hipEventDestroy(e0));
+    HIPCHK(hipEventDestroy(e1));
+    *fp64_mfma_tflops = probe_mfma_flops(mblocks, iters) / (tm * 1e-3) / 1e12;
+    *copy_gbps = 2.0 * n * 8 / (tc * 1e-3) / 1e9;
+  });
+}
+
 int mbefci_time_kernels(mbefci_ctx* c, int32_t reps, mbefci_kernel_time* out, int32_t cap,
                         int32_t* count) {
   return guarded(c, [&] {

@@ -5,6 +5,8 @@
   E = (U - sqrt(U^2 + 16 t^2)) / 2 and E_1e = -8 t^2 / sqrt(U^2 + 16 t^2).
 * A synthetic CAS(6e,6o) with a core energy: the energy against the oracle's
   Slater-Condon FCI and the batched call, and the RDMs reproducing it.
+* The peak probes return values below the published peaks and within a
+  factor of a few of them.
 """
 import math
 
@@ -58,3 +60,15 @@ def test_casci_synthetic_against_oracle_and_batch():
     g1, g2 = g1.cpu().numpy(), g2.cpu().numpy()
     assert abs(np.trace(g1) - 6.0) < 1e-10
     assert abs((h * g1).sum() + 0.5 * (g * g2).sum() + e_core - e) < 1e-9
+
+
+def test_probe_peaks_plausible():
+    from paper_1910_03527_amd import Context
+    c = Context(0)
+    try:
+        pk = c.probe_peaks()
+    finally:
+        c.close()
+    # published: 78.6 TFLOP/s FP64 matrix, 8 TB/s HBM
+    assert 20.0 < pk["fp64_mfma_tflops"] < 80.0, pk
+    assert 1000.0 < pk["copy_gbps"] < 8200.0, pk
