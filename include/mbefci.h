@@ -242,15 +242,18 @@ int mbefci_partition(int32_t type, int32_t norb, int32_t nocc, const int32_t* oc
 
 /* ---- screened expansion ---------------------------------------------------
  * The order-by-order driver of the paper's production runs (the tuple
- * screening described with Eq. 4).  Order 1 holds every expansion orbital;
- * a tuple of order k+1 is computed iff one of its order-k sub-tuples S was
- * computed with |Delta eps_S| > T_tup(S), where (Eq. 4)
+ * screening described with Eq. 4).  Order 1 holds every expansion orbital.
+ * Spawning is per parent: a computed tuple P of order k and a candidate
+ * orbital c of X outside P spawn P + c when, for some (k-1)-subtuple S of P,
+ * the tuple S + c was computed with |Delta eps_{S+c}| > T_tup(S + c) (a tuple
+ * never computed has no increment and spawns nothing; P itself is not tested).
+ * Order k+1 is the union over all parents and candidates.  Here (Eq. 4)
  *   T_tup = 0                                 if M_tup <  m_init,
  *   T_tup = t_init * a^(M_tup - m_init)       otherwise,
- * and M_tup = max(occupied MOs, virtual MOs) of S.  With an empty reference
- * space (Eq. 3) tuples of only occupied or only virtual MOs have vanishing
- * increments by construction: they are not computed, and every mixed pair is
- * (order 2 is the first order).  Increments follow Eq. 2 over the computed
+ * and M_tup = max(occupied MOs, virtual MOs) of the tested tuple.  With an
+ * empty reference space (Eq. 3) tuples of only occupied or only virtual MOs
+ * have vanishing increments by construction: they are not computed (and are
+ * no parents), and every mixed pair is (order 2 is the first order).  Increments follow Eq. 2 over the computed
  * sub-tuples (a sub-tuple never computed contributes 0).  Outputs (host):
  * e_ref, e_order [max_order] (0 for orders with no tuple), e_total,
  * n_order [max_order] (tuples computed per order).  The computed tuples and

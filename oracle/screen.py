@@ -7,14 +7,23 @@ The paper states the rule in words; this module takes these readings:
   the larger of its numbers of occupied MOs (doubly occupied in the reference
   determinant) and of virtual MOs.
 * Eq. 4: T_tup = 0 when M_tup < M_init, else T_init * a^(M_tup - M_init).
-* Order 1 holds every expansion orbital.  A tuple C of order k+1 is spawned
-  iff at least one of its order-k sub-tuples S was computed at order k with
-  |Delta eps_S| > T_tup(S) (the threshold of the sub-tuple).
+* Order 1 holds every expansion orbital.  Spawning follows the per-parent
+  rule stated with Eq. 4: for a computed parent P of order k and a candidate
+  orbital c of X not in P, the order-k tuples S + c are formed for every
+  (k-1)-subtuple S of P (the parent itself is not among them); the child
+  P + c is spawned when |Delta eps| of any of them exceeds that tuple's own
+  threshold T_tup.  A tuple S + c that was never computed has no increment
+  and cannot trigger a spawn.  Every computed tuple of order k acts as a
+  parent and every orbital of X outside it as a candidate; the children of
+  order k+1 are the union over parents.  (Restricting candidates to orbitals
+  above the parent's last one would make the result depend on the orbital
+  numbering, which the paper does not make part of the rule.)
 * With an empty reference space (Eq. 3) a tuple made only of occupied or
   only of virtual MOs has a vanishing increment for a structural reason (its
   CASCI is the reference determinant itself).  Such tuples are never
-  computed and count as Delta eps = 0; a tuple whose order-k sub-tuples are
-  all of that kind (the mixed pairs at order 2) is spawned.
+  computed and count as Delta eps = 0 (they are no parents and trigger no
+  spawn).  The mixed pairs, whose order-1 sub-tuples are all of that kind,
+  have no computed parent; they form the first order computed, all of them.
 * Increments follow Eq. 2 over the computed sub-tuples: Delta eps_T = eps_T
   minus the increments of its computed proper non-empty sub-tuples (a
   sub-tuple never computed contributes 0).  E^(k) is the sum of the order-k
@@ -50,19 +59,26 @@ def structural_zero(t, occ, ref):
 
 
 def spawn(prev, exp, occ, ref, t_init, m_init, a):
-    """Children of order k+1 from the computed order-k tuples ``prev``
-    (dict tuple -> increment), lexicographically sorted."""
+    """Children of order k+1 from the computed order-k parent tuples ``prev``
+    (dict tuple -> increment), lexicographically sorted.  Per parent P and
+    candidate orbital c: the tuples S + c, S every (k-1)-subtuple of P, are
+    tested against their own thresholds; one above spawns P + c."""
     occ = set(occ)
     x = sorted(exp)
     out = set()
-    k = len(next(iter(prev))) if prev else None
-    for s, d in prev.items():
-        if abs(d) > threshold(s, occ, t_init, m_init, a):
-            for c in x:
-                if c not in s:
-                    t = tuple(sorted(s + (c,)))
-                    if not structural_zero(t, occ, ref):
-                        out.add(t)
+    for par in prev:
+        k = len(par)
+        for c in x:
+            if c in par:
+                continue
+            child = tuple(sorted(par + (c,)))
+            if child in out or structural_zero(child, occ, ref):
+                continue
+            for s in itertools.combinations(par, k - 1):
+                q = tuple(sorted(s + (c,)))
+                if q in prev and abs(prev[q]) > threshold(q, occ, t_init, m_init, a):
+                    out.add(child)
+                    break
     return sorted(out)
 
 

@@ -1631,8 +1631,14 @@ int mbefci_mbe_screened(mbefci_ctx* c, const mbefci_problem* pb, const mbefci_sc
       c->scr_masks[k] = level;
       c->scr_inc[k] = inc;
       if (k == K) break;
-      // spawn order k+1: children of every tuple whose increment exceeds its
-      // threshold
+      // spawn order k+1 (the per-parent rule with Eq. 4): a computed parent P
+      // and a candidate orbital c outside it spawn P + c when one of the
+      // order-k tuples S + c (S a (k-1)-subtuple of P, so never P itself) was
+      // computed with |Delta eps| above its own threshold.  Over all parents
+      // this is: the child has a significant order-k sub-tuple Q and a
+      // second computed one (the parent P != Q).  Candidates come from the
+      // significant tuples; each keeps its place if at least two of its
+      // order-k sub-tuples were computed.  `level` is sorted.
       std::vector<uint64_t> next;
       for (int64_t i = 0; i < n; ++i) {
         if (!(std::fabs(inc[i]) > threshold(level[i]))) continue;
@@ -1642,6 +1648,18 @@ int mbefci_mbe_screened(mbefci_ctx* c, const mbefci_problem* pb, const mbefci_sc
           if (!structural(child)) next.push_back(child);
         }
       }
+      std::sort(next.begin(), next.end());
+      next.erase(std::unique(next.begin(), next.end()), next.end());
+      size_t kept = 0;
+      for (uint64_t child : next) {
+        int computed = 0;
+        for (uint64_t x = child; x && computed < 2; x &= x - 1) {
+          const uint64_t sub = child & ~(x & (~x + 1));
+          if (std::binary_search(level.begin(), level.end(), sub)) ++computed;
+        }
+        if (computed >= 2) next[kept++] = child;
+      }
+      next.resize(kept);
       level.swap(next);
       ++k;
     }

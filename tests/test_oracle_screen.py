@@ -2,8 +2,15 @@
 
 * Eq. 4 with the paper's parameters (T_init = 1e-10 E_h, M_init = 3,
   a = 5.0): zero below M_init, T_init at M_init, times a per extra MO.
-* The order-by-order spawning (parent driven) against the definition taken
-  child by child by brute force over all subsets, on random increment tables.
+* The order-by-order spawning, which the oracle runs per parent as the
+  paper words it, against the same rule restated child by child by brute
+  force over all subsets (a child C is spawned iff C has two different
+  order-k sub-tuples P and Q, P computed and Q computed with |Delta eps_Q|
+  above T_tup(Q): P is the parent, Q = S + c), on random increment tables.
+* A hand-built increment table on which this rule and the looser "any
+  computed order-k sub-tuple above its threshold" rule spawn different
+  children (a child whose only computed sub-tuple is significant is not
+  spawned: that sub-tuple would be its own parent).
 * T_init = 0: every tuple with a non-vanishing increment survives, so the
   screened expansion equals the full one (the oracle's Eq. 2 recursion).
 * Telescoping: when the whole expansion space X is computed, E_total = f(X)
@@ -35,17 +42,50 @@ def test_threshold_eq4_paper_parameters():
 
 
 def _brute_children(prev, exp, occ, ref, t_init, m_init, a):
-    """Definition, child by child: C (not a structural zero) is spawned iff a
-    sub-tuple of order k was computed and exceeds its threshold."""
+    """The per-parent rule, child by child: C (not a structural zero) is
+    spawned iff two different order-k sub-tuples P, Q of C exist with P
+    computed (the parent) and Q computed above its own threshold."""
     k = len(next(iter(prev)))
     out = []
     for c in itertools.combinations(sorted(exp), k + 1):
         if screen.structural_zero(c, occ, ref):
             continue
-        if any(s in prev and abs(prev[s]) > screen.threshold(s, occ, t_init, m_init, a)
-               for s in itertools.combinations(c, k)):
+        subs = list(itertools.combinations(c, k))
+        sig = [q for q in subs
+               if q in prev and abs(prev[q]) > screen.threshold(q, occ, t_init, m_init, a)]
+        if any(p in prev and p != q for p in subs for q in sig):
             out.append(c)
     return out
+
+
+def test_spawn_per_parent_differs_from_any_subtuple_rule():
+    """Hand-built order-2 table (reference space non-empty, so no structural
+    zeros; M_init = 3 puts every pair's threshold at 0): (0,1) and (2,3)
+    significant, (2,4) computed with a zero increment.  Any-sub-tuple rule:
+    the six supersets of (0,1) and (2,3).  Per parent: only (2,3,4), whose
+    parent (2,4) forms (2,3) = {2} + 3; the supersets of (0,1) and (2,3)
+    have no other computed pair, so no parent forms the significant pair."""
+    exp = [0, 1, 2, 3, 4]
+    occ = {0, 1}
+    ref = [5]
+    prev = {(0, 1): 1e-3, (2, 3): -2e-3, (2, 4): 0.0}
+    got = screen.spawn(prev, exp, occ, ref, 1e-10, 3, 5.0)
+    assert got == [(2, 3, 4)]
+    loose = sorted({tuple(sorted(s + (c,))) for s, d in prev.items() if d != 0.0
+                    for c in exp if c not in s})
+    assert loose == [(0, 1, 2), (0, 1, 3), (0, 1, 4), (0, 2, 3), (1, 2, 3), (2, 3, 4)]
+    assert got != loose
+    # the parent's own increment plays no part: make (2,4) huge and (2,3) zero
+    prev2 = {(0, 1): 1e-3, (2, 3): 0.0, (2, 4): 5.0}
+    assert screen.spawn(prev2, exp, occ, ref, 1e-10, 3, 5.0) == [(2, 3, 4)]
+    # thresholds are those of the tested tuple S + c: at order 3 with
+    # M_init = 2, T_tup = t_init * a^(M_tup - 2)
+    prev3 = {(0, 2, 3): 3e-6, (0, 2, 4): 1e-9}
+    occ3 = {0, 1, 2}
+    # (0,2,3): M_tup 2 -> T = 1e-6 -> significant; (0,2,4): T = 1e-6 -> not
+    assert screen.spawn(prev3, exp, occ3, ref, 1e-6, 2, 10.0) == [(0, 2, 3, 4)]
+    # (0,2,3) below its threshold now: nothing
+    assert screen.spawn(prev3, exp, occ3, ref, 1e-5, 2, 10.0) == []
 
 
 @pytest.mark.parametrize("seed", range(6))
@@ -113,19 +153,20 @@ def test_threshold_monotonicity_and_large_limit():
     for a, b in zip(sets, sets[1:]):
         for x, y in zip(a, b):
             assert y <= x
-    # T_init = 1e3: only sub-tuples with M_tup < 3 (threshold 0) spawn, i.e.
-    # from order 2 on the computed tuples are exactly the children of computed
-    # tuples with M_tup < 3 and a non-zero increment
+    # T_init = 1e3: only tuples with M_tup < 3 (threshold 0) are significant,
+    # so from order 2 on the computed tuples are exactly the children C with
+    # a computed order-k sub-tuple P and another one, Q != P, with M_tup < 3
+    # and a non-zero increment
     big = screen.screened_mbe(p, 1e3, 3, 5.0, max_order=6, workers=4)
     for k in range(2, 6):
         prev = dict(big["per_order"][k - 1])
         cur = set(t for t, _ in big["per_order"][k])
         exp_children = set()
-        for s, d in prev.items():
-            if screen.m_tup(s, occ) < 3 and d != 0.0:
-                for c in p.exp:
-                    if c not in s:
-                        t = tuple(sorted(s + (c,)))
-                        if not screen.structural_zero(t, occ, p.ref):
-                            exp_children.add(t)
+        for c in itertools.combinations(sorted(p.exp), k + 1):
+            if screen.structural_zero(c, occ, p.ref):
+                continue
+            subs = [s for s in itertools.combinations(c, k) if s in prev]
+            if any(q != s and screen.m_tup(q, occ) < 3 and prev[q] != 0.0
+                   for s in subs for q in subs):
+                exp_children.add(c)
         assert cur == exp_children
