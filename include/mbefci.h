@@ -189,6 +189,26 @@ int mbefci_sigma(mbefci_ctx* ctx, int32_t norb, int32_t nalpha, int32_t nbeta, c
                  const double* eri, double e_core, const double* c, double* sigma,
                  void* hip_stream);
 
+/* sigma = H c as mbefci_sigma computes it, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Allocates nothing: every intermediate (string, link
+ * and pair tables, W, the contracted pair array G, work lists) lives in one
+ * static device array of 32 MiB per GPU, held until the process ends.  Runs
+ * only kernel launches, on hip_stream itself (no library stream, no events,
+ * no synchronisation, no host copies, no memset nodes), so it may be captured
+ * into a graph.  The integrals are not validated on the host (opts.validate
+ * does not apply).  Shapes: norb 0..14 whose tables, W and G fit the 32 MiB
+ * (every shape up to CAS(10,10), 28.8 MB at 5+5 electrons); larger ones
+ * return ENOMEM with the size in mbefci_last_error(ctx).  ctx supplies the
+ * device and the error message only: neither its plan nor its workspaces are
+ * touched, so its other calls are unaffected.  Every call on a GPU shares that
+ * GPU's array and leaves its contents behind: calls that overlap on one GPU
+ * (several streams, threads or contexts) race and must be serialised by the
+ * caller.  c and sigma: device [Na*Nb], distinct. */
+int mbefci_sigma_noalloc(mbefci_ctx* ctx, int32_t norb, int32_t nalpha, int32_t nbeta,
+                         const double* h1, const double* eri, double e_core, const double* c,
+                         double* sigma, void* hip_stream);
+
 /* ---- batch of independent CASCIs of one shape ---------------------------
  * nprob problems, each with its own integrals: h1s[i] device [n*n], eris[i]
  * device [n^4] (host arrays of device pointers), e_core host [nprob].

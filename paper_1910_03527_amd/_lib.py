@@ -21,7 +21,8 @@ ERROR_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", ENOTCONV: "ENOTCONV", EDEVICE
 EXPORTS = (
     "mbefci_default_opts", "mbefci_create", "mbefci_destroy", "mbefci_last_error",
     "mbefci_set_opts", "mbefci_set_allocator", "mbefci_num_strings", "mbefci_num_links", "mbefci_strings",
-    "mbefci_link_table", "mbefci_num_tuples", "mbefci_hdiag", "mbefci_sigma", "mbefci_casci",
+    "mbefci_link_table", "mbefci_num_tuples", "mbefci_hdiag", "mbefci_sigma",
+    "mbefci_sigma_noalloc", "mbefci_casci",
     "mbefci_casci_rdm", "mbefci_mbe_forward", "mbefci_mbe_backward", "mbefci_mbe_screened",
     "mbefci_screened_tuples", "mbefci_partition", "mbefci_time_kernels", "mbefci_probe_peaks",
 )
@@ -153,6 +154,8 @@ def load():
     L.mbefci_hdiag.restype = ctypes.c_int
     L.mbefci_sigma.argtypes = [vp, i32, i32, i32, vp, vp, dbl, vp, vp, vp]
     L.mbefci_sigma.restype = ctypes.c_int
+    L.mbefci_sigma_noalloc.argtypes = [vp, i32, i32, i32, vp, vp, dbl, vp, vp, vp]
+    L.mbefci_sigma_noalloc.restype = ctypes.c_int
     L.mbefci_casci.argtypes = [vp, i32, i32, i32, i32, pvp, pvp, ctypes.POINTER(dbl),
                                ctypes.POINTER(dbl), pvp, ctypes.POINTER(Stats), vp]
     L.mbefci_casci.restype = ctypes.c_int

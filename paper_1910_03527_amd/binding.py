@@ -180,6 +180,22 @@ class Context:
                                          ctypes.c_void_p(out.data_ptr()), self._stream()))
         return out
 
+    def sigma_noalloc(self, h1, eri, nalpha: int, nbeta: int, c, out, e_core: float = 0.0):
+        """sigma = H c into the caller's ``out`` through mbefci_sigma_noalloc
+        (no device allocation: the library's static scratch array); returns
+        ``out``."""
+        n = h1.shape[0]
+        _dev_f64(h1, (n, n), "h1")
+        _dev_f64(eri, (n, n, n, n), "eri")
+        nd = num_strings(n, nalpha) * num_strings(n, nbeta)
+        _dev_f64(c, (nd,), "c")
+        _dev_f64(out, (nd,), "out")
+        self._check(self._L.mbefci_sigma_noalloc(
+            self._h, n, nalpha, nbeta, ctypes.c_void_p(h1.data_ptr()),
+            ctypes.c_void_p(eri.data_ptr()), float(e_core), ctypes.c_void_p(c.data_ptr()),
+            ctypes.c_void_p(out.data_ptr()), self._stream()))
+        return out
+
     # --------------------------------------------------------- CASCI batch
     def casci(self, h1s, eris, nalpha: int, nbeta: int, e_core=None, want_ci: bool = False):
         """Lowest eigenvalues (host list) of a batch of same-shape CASCIs;

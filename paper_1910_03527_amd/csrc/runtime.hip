@@ -144,6 +144,12 @@ struct Plan {
 
 }  // namespace
 
+namespace mbefci {
+hipError_t noalloc_init(int device);
+int noalloc_sigma(int device, int n, int na, int nb, const double* h1, const double* eri,
+                  double e_core, const double* c, double* sigma, hipStream_t s, std::string* why);
+}  // namespace mbefci
+
 struct mbefci_ctx {
   int device = 0;
   mbefci_opts opts{};
@@ -1107,6 +1113,9 @@ int mbefci_create(int device, const mbefci_opts* opts, mbefci_ctx** out) {
     delete c;
     return MBEFCI_EDEVICE;
   }
+  // device address of the no-allocation sigma's scratch array on this device;
+  // a failure is reported by mbefci_sigma_noalloc, which tries again
+  if (mbefci::noalloc_init(device) != hipSuccess) (void)hipGetLastError();
   *out = c;
   return MBEFCI_OK;
 }
@@ -1261,6 +1270,23 @@ int mbefci_sigma(mbefci_ctx* c, int32_t n, int32_t na, int32_t nb, const double*
     c->have_forward = false;
     sc.done();
   });
+}
+
+int mbefci_sigma_noalloc(mbefci_ctx* c, int32_t n, int32_t na, int32_t nb, const double* h1,
+                         const double* eri, double e_core, const double* cvec, double* sig,
+                         void* stream) {
+  if (!c) return MBEFCI_EINVAL;
+  c->err.clear();
+  const hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) {
+    c->err = std::string("hipSetDevice: ") + hipGetErrorString(e);
+    return MBEFCI_EDEVICE;
+  }
+  std::string why;
+  const int rc = mbefci::noalloc_sigma(c->device, n, na, nb, h1, eri, e_core, cvec, sig,
+                                       (hipStream_t)stream, &why);
+  if (rc != MBEFCI_OK) c->err = why;
+  return rc;
 }
 
 int mbefci_casci(mbefci_ctx* c, int32_t nprob, int32_t n, int32_t na, int32_t nb,
