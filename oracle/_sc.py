@@ -47,6 +47,12 @@ def lib():
         L.sc_sigma_rows.restype = None
         L.sc_sigma_rows.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_int, up,
                                     ctypes.c_int, up, dp, ctypes.c_int, ip64, dp]
+        L.sc_direct_setup.restype = ctypes.c_void_p
+        L.sc_direct_setup.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, up, ctypes.c_int, up, dp]
+        L.sc_direct_free.restype = None
+        L.sc_direct_free.argtypes = [ctypes.c_void_p]
+        L.sc_direct_sigma.restype = None
+        L.sc_direct_sigma.argtypes = [ctypes.c_void_p, dp, dp, ctypes.c_int, ctypes.c_int]
         L.sc_rdm12.restype = None
         L.sc_rdm12.argtypes = [ctypes.c_int, ctypes.c_int, up, ctypes.c_int, up, dp, dp, dp]
         _lib = L

@@ -310,3 +310,216 @@ void sc_rdm12(int M, int na, const uint64_t* amask, int nb, const uint64_t* bmas
                 }
         }
 }
+
+/*
+ * Matrix-free sigma = H c over the product space {(alpha[i], beta[j])} for
+ * spaces too large for a stored H (CAS(14,14): 11.8 M determinants).  Row I
+ * visits only the determinants J within two electrons of I, reached by
+ * exciting one spin string (singles and same-spin doubles) or both strings
+ * once (opposite-spin doubles); every element is a Slater-Condon element:
+ *
+ *  - a same-spin double, and the one-spin part of a same-spin single, are
+ *    sc_element of the two strings with the other spin empty.  In the
+ *    alpha-first ordering a beta operator passes every alpha electron and an
+ *    alpha operator none of the beta ones, and an excitation has an even
+ *    number of operators, so the sign never depends on the other string; a
+ *    double's value does not either, and for a single the other spin adds
+ *    only its Coulomb term sgn * sum_{k in other} (ai|kk) (the exchange
+ *    integral between different spins vanishes);
+ *  - an opposite-spin double (alpha i->a, beta j->b) is
+ *    sgn_alpha * sgn_beta * (ai|bj), the sign of each single excitation
+ *    taken on its own string (the product of the four operator signs of the
+ *    textbook rule reduces to this, the alpha electrons being counted twice
+ *    by the beta operators);
+ *  - the diagonal is passed in (sc_diagonal).
+ *
+ * These reductions are pinned against sc_build_csr on small spaces.  Setup
+ * builds per-string excitation lists (strings outside the space, e.g. with a
+ * frozen orbital emptied or a deleted one filled, are skipped); sigma rows
+ * are computed for alpha strings [ia_lo, ia_hi), so callers can split the
+ * rows over threads.
+ */
+typedef struct {
+    int32_t t;      /* index of the excited string */
+    int8_t a, i;    /* created, annihilated orbital */
+    int8_t sgn;     /* sign of a+_a a_i on the source string */
+    double v1;      /* sc_element of the one-spin part (other spin empty) */
+} sc_single_t;
+
+typedef struct {
+    int32_t t;
+    double v;
+} sc_double_t;
+
+typedef struct {
+    int M, n;
+    const double* g;
+    int ns;              /* singles per string (max) */
+    int nd;              /* doubles per string (max) */
+    int32_t* ns_of;      /* [n] singles of string s */
+    int32_t* nd_of;      /* [n] */
+    sc_single_t* sing;   /* [n][ns] */
+    sc_double_t* dbl;    /* [n][nd] */
+    double* coul;        /* [n][M*M]: sum_{k in s} (ai|kk) */
+} sc_spin_t;
+
+typedef struct {
+    int M, na, nb;
+    const double* diag;
+    sc_spin_t A, B;
+} sc_direct_t;
+
+static int spin_setup(sc_spin_t* T, int M, const double* h, const double* g, int n,
+                      const uint64_t* s, int spin) {
+    T->M = M;
+    T->n = n;
+    T->g = g;
+    int ne = n ? popc(s[0]) : 0;
+    T->ns = ne * (M - ne) + 1;
+    T->nd = (ne * (ne - 1) / 2) * ((M - ne) * (M - ne - 1) / 2) + 1;
+    T->ns_of = (int32_t*)calloc(n ? n : 1, sizeof(int32_t));
+    T->nd_of = (int32_t*)calloc(n ? n : 1, sizeof(int32_t));
+    T->sing = (sc_single_t*)malloc(sizeof(sc_single_t) * (size_t)(n ? n : 1) * T->ns);
+    T->dbl = (sc_double_t*)malloc(sizeof(sc_double_t) * (size_t)(n ? n : 1) * T->nd);
+    T->coul = (double*)calloc((size_t)(n ? n : 1) * M * M, sizeof(double));
+    if (!T->ns_of || !T->nd_of || !T->sing || !T->dbl || !T->coul) return -1;
+    for (int x = 0; x < n; ++x) {
+        uint64_t m = s[x];
+        double* cl = T->coul + (size_t)x * M * M;
+        for (int a = 0; a < M; ++a)
+            for (int i = 0; i < M; ++i) {
+                double acc = 0.0;
+                for (int k = 0; k < M; ++k)
+                    if (m >> k & 1) acc += g[(((size_t)a * M + i) * M + k) * M + k];
+                cl[a * M + i] = acc;
+            }
+        sc_single_t* S1 = T->sing + (size_t)x * T->ns;
+        sc_double_t* S2 = T->dbl + (size_t)x * T->nd;
+        int c1 = 0, c2 = 0;
+        for (int i = 0; i < M; ++i) {
+            if (!(m >> i & 1)) continue;
+            for (int a = 0; a < M; ++a) {
+                if (m >> a & 1) continue;
+                uint64_t t = (m & ~((uint64_t)1 << i)) | ((uint64_t)1 << a);
+                int ti = find_u64(n, s, t);
+                if (ti < 0) continue;
+                det_t d = {{m, 0}};
+                int sg = annihilate(&d, 0, i);
+                sg *= create(&d, 0, a);
+                double v1 = spin == 0 ? sc_element(M, h, g, t, 0, m, 0)
+                                      : sc_element(M, h, g, 0, t, 0, m);
+                S1[c1].t = ti;
+                S1[c1].a = (int8_t)a;
+                S1[c1].i = (int8_t)i;
+                S1[c1].sgn = (int8_t)sg;
+                S1[c1].v1 = v1;
+                ++c1;
+            }
+        }
+        for (int i = 0; i < M; ++i) {
+            if (!(m >> i & 1)) continue;
+            for (int j = i + 1; j < M; ++j) {
+                if (!(m >> j & 1)) continue;
+                for (int a = 0; a < M; ++a) {
+                    if (m >> a & 1) continue;
+                    for (int b = a + 1; b < M; ++b) {
+                        if (m >> b & 1) continue;
+                        uint64_t t = (m & ~(((uint64_t)1 << i) | ((uint64_t)1 << j))) |
+                                     ((uint64_t)1 << a) | ((uint64_t)1 << b);
+                        int ti = find_u64(n, s, t);
+                        if (ti < 0) continue;
+                        S2[c2].t = ti;
+                        S2[c2].v = spin == 0 ? sc_element(M, h, g, t, 0, m, 0)
+                                             : sc_element(M, h, g, 0, t, 0, m);
+                        ++c2;
+                    }
+                }
+            }
+        }
+        T->ns_of[x] = c1;
+        T->nd_of[x] = c2;
+    }
+    return 0;
+}
+
+static void spin_free(sc_spin_t* T) {
+    free(T->ns_of);
+    free(T->nd_of);
+    free(T->sing);
+    free(T->dbl);
+    free(T->coul);
+}
+
+/* Tables for sc_direct_sigma; diag [na*nb] (H_II including the constant) must
+   stay valid while they are used.  NULL when memory runs out. */
+void* sc_direct_setup(int M, const double* h, const double* g, int na, const uint64_t* amask,
+                      int nb, const uint64_t* bmask, const double* diag) {
+    sc_direct_t* D = (sc_direct_t*)calloc(1, sizeof(sc_direct_t));
+    if (!D) return NULL;
+    D->M = M;
+    D->na = na;
+    D->nb = nb;
+    D->diag = diag;
+    if (spin_setup(&D->A, M, h, g, na, amask, 0) || spin_setup(&D->B, M, h, g, nb, bmask, 1)) {
+        spin_free(&D->A);
+        spin_free(&D->B);
+        free(D);
+        return NULL;
+    }
+    return D;
+}
+
+void sc_direct_free(void* p) {
+    sc_direct_t* D = (sc_direct_t*)p;
+    if (!D) return;
+    spin_free(&D->A);
+    spin_free(&D->B);
+    free(D);
+}
+
+/* out[I] = sum_J H_IJ c_J for the rows I of alpha strings [ia_lo, ia_hi). */
+void sc_direct_sigma(const void* p, const double* c, double* out, int ia_lo, int ia_hi) {
+    const sc_direct_t* D = (const sc_direct_t*)p;
+    const int M = D->M, nb = D->nb;
+    const double* g = D->A.g;
+    for (int ia = ia_lo; ia < ia_hi; ++ia) {
+        const sc_single_t* SA = D->A.sing + (size_t)ia * D->A.ns;
+        const sc_double_t* DA = D->A.dbl + (size_t)ia * D->A.nd;
+        const int nsa = D->A.ns_of[ia], nda = D->A.nd_of[ia];
+        const double* ca_coul = D->A.coul + (size_t)ia * M * M;
+        for (int ib = 0; ib < nb; ++ib) {
+            const int64_t I = (int64_t)ia * nb + ib;
+            const sc_single_t* SB = D->B.sing + (size_t)ib * D->B.ns;
+            const sc_double_t* DB = D->B.dbl + (size_t)ib * D->B.nd;
+            const int nsb = D->B.ns_of[ib], ndb = D->B.nd_of[ib];
+            const double* cb_coul = D->B.coul + (size_t)ib * M * M;
+            double acc = D->diag[I] * c[I];
+            /* alpha singles: one-spin part plus the beta electrons' Coulomb term */
+            for (int x = 0; x < nsa; ++x) {
+                const sc_single_t* e = SA + x;
+                acc += (e->v1 + e->sgn * cb_coul[e->a * M + e->i]) * c[(int64_t)e->t * nb + ib];
+            }
+            /* beta singles */
+            for (int x = 0; x < nsb; ++x) {
+                const sc_single_t* e = SB + x;
+                acc += (e->v1 + e->sgn * ca_coul[e->a * M + e->i]) * c[(int64_t)ia * nb + e->t];
+            }
+            /* same-spin doubles */
+            for (int x = 0; x < nda; ++x) acc += DA[x].v * c[(int64_t)DA[x].t * nb + ib];
+            for (int x = 0; x < ndb; ++x) acc += DB[x].v * c[(int64_t)ia * nb + DB[x].t];
+            /* opposite-spin doubles */
+            for (int x = 0; x < nsa; ++x) {
+                const sc_single_t* ea = SA + x;
+                const double* crow = c + (int64_t)ea->t * nb;
+                const double* gai = g + ((size_t)ea->a * M + ea->i) * M * M;
+                double part = 0.0;
+                for (int y = 0; y < nsb; ++y) {
+                    const sc_single_t* eb = SB + y;
+                    part += eb->sgn * gai[eb->a * M + eb->i] * crow[eb->t];
+                }
+                acc += ea->sgn * part;
+            }
+            out[I] = acc;
+        }
+    }
+}
