@@ -160,27 +160,47 @@ int mbefci_set_allocator(mbefci_ctx* ctx, void* (*alloc)(size_t bytes, void* use
                          void (*release)(void* ptr, void* user), void* user);
 
 /* ---- integer layer: strings and single-excitation link tables ------------
- * A string of nelec electrons in norb active orbitals is a bitmask; strings
- * are numbered in ascending integer order (address = sum_j C(o_j, j) over the
- * occupied orbitals o_1 < o_2 < ..., the combinatorial number system).  The
- * determinant with alpha string Ia and beta string Ib has address
- * Ia * N_beta + Ib.  These tables are the integer backbone of every CASCI
- * solve (the constituent CASCI calculations of Eq. 1). */
-int64_t mbefci_num_strings(int32_t norb, int32_t nelec);     /* C(norb, nelec) */
-int32_t mbefci_num_links(int32_t norb, int32_t nelec);       /* nelec*(norb-nelec+1) */
-/* out: device [nstr] uint64 bitmasks. */
-int mbefci_strings(mbefci_ctx* ctx, int32_t norb, int32_t nelec, uint64_t* out, void* hip_stream);
-/* out: device [nstr][nlink][4] int32 = (p, q, J, sign) with E_pq|I> = sign|J>,
- * E_pq = a+_p a_q of one spin.  Per string: the diagonal entries (o,o,I,+1)
- * for occupied o ascending, then for occupied q ascending and empty p
- * ascending; sign = (-1)^(occupied orbitals strictly between p and q). */
-int mbefci_link_table(mbefci_ctx* ctx, int32_t norb, int32_t nelec, int32_t* out, void* hip_stream);
-/* Number of tuples of 1..max_order orbitals out of nexp: sum_n C(nexp, n). */
+ * Every CASCI of the expansion (the constituent CASCI calculations whose
+ * energies enter eps_T of Eq. 2) is a full CI in its active space, over the
+ * determinants |Ia Ib> of an alpha and a beta string.  A string of nelec
+ * electrons in norb active orbitals is a bitmask; strings are numbered in
+ * ascending integer order (address = sum_j C(o_j, j) over the occupied
+ * orbitals o_1 < o_2 < ..., the combinatorial number system).  The
+ * determinant of alpha string Ia and beta string Ib has address
+ * Ia * N_beta + Ib. */
+int64_t mbefci_num_strings(int32_t norb, int32_t nelec);     /* C(norb, nelec); 0 if invalid */
+int32_t mbefci_num_links(int32_t norb, int32_t nelec);       /* nelec*(norb-nelec+1)        */
+/* Host, no context, no device: out host [nstr] uint64 bitmasks, ascending
+ * (the caller allocates mbefci_num_strings(norb, nelec) entries).  EINVAL for
+ * norb outside 0..64, nelec outside 0..norb, a null out, or more than 2^31 - 1
+ * strings; ENOMEM if host memory runs out. */
+int mbefci_strings(int32_t norb, int32_t nelec, uint64_t* out);
+/* Host, no context, no device: out host [nstr][nlink][4] int32 = (p, q, J,
+ * sign) with E_pq|I> = sign|J>, E_pq = a+_p a_q of one spin.  Per string: the
+ * diagonal entries (o,o,I,+1) for occupied o ascending, then for occupied q
+ * ascending and empty p ascending; sign = (-1)^(occupied orbitals strictly
+ * between p and q), the parity of a+_p a_q on the occupation-number vector.
+ * EINVAL for norb outside 0..32, nelec outside 0..norb or a null out. */
+int mbefci_link_table(int32_t norb, int32_t nelec, int32_t* out);
+/* The same two tables built by the library's kernels into device memory of
+ * ctx's device (out: device [nstr] / [nstr][nlink][4]), on hip_stream. */
+int mbefci_strings_device(mbefci_ctx* ctx, int32_t norb, int32_t nelec, uint64_t* out,
+                          void* hip_stream);
+int mbefci_link_table_device(mbefci_ctx* ctx, int32_t norb, int32_t nelec, int32_t* out,
+                             void* hip_stream);
+/* Number of tuples of 1..max_order orbitals out of nexp: sum_n C(nexp, n),
+ * the CASCIs behind the order sums E^(1..max_order) of Eq. 1 (order n holds
+ * the C(nexp, n) increments of Eq. 2).  0 for invalid arguments. */
 int64_t mbefci_num_tuples(int32_t nexp, int32_t max_order);
 
 /* ---- one CASCI Hamiltonian in an active space ---------------------------
- * h1 device [n*n], eri device [n^4] (active-space integrals), e_core the
- * constant added to every diagonal element.  Determinant layout [Na][Nb]. */
+ * The Hamiltonian whose lowest eigenvalue is a CASCI energy of Eq. 1 / Eq. 2,
+ * H = sum h_pq E_pq + 1/2 sum (pq|rs) (E_pq E_rs - delta_qr E_ps) + e_core,
+ * on the determinants of the active space.  h1 device [n*n], eri device
+ * [n^4] (active-space integrals), e_core the constant added to every
+ * diagonal element.  Determinant layout [Na][Nb].  The sigma build is the
+ * string-driven Knowles-Handy / Olsen factorisation (the paper leaves the
+ * CASCI solver to its host program; this is the solver's own method). */
 /* diag: device [Na*Nb], H_II including e_core. */
 int mbefci_hdiag(mbefci_ctx* ctx, int32_t norb, int32_t nalpha, int32_t nbeta, const double* h1,
                  const double* eri, double e_core, double* diag, void* hip_stream);
@@ -209,19 +229,34 @@ int mbefci_sigma_noalloc(mbefci_ctx* ctx, int32_t norb, int32_t nalpha, int32_t 
                          const double* h1, const double* eri, double e_core, const double* c,
                          double* sigma, void* hip_stream);
 
-/* ---- batch of independent CASCIs of one shape ---------------------------
- * nprob problems, each with its own integrals: h1s[i] device [n*n], eris[i]
+/* ---- CASCI solves ---------------------------------------------------------
+ * A CASCI energy is the lowest eigenvalue of H above (the constituent CASCI
+ * calculations of Eq. 1; eps_T of Eq. 2 is the energy of the CASCI in
+ * R u T minus E_ref), found by a Davidson solve to opts.conv_tol.
+ *
+ * One CASCI: integrals h1 device [n*n], eri device [n^4], e_core; e_out host
+ * [1] the energy; ci_out device [Na*Nb] the normalised eigenvector, rdm1
+ * device [n*n] gamma_pq = <E_pq>, rdm2 device [n^4]
+ * Gamma_pqrs = <E_pq E_rs> - delta_qr gamma_ps symmetrised over the eight
+ * index permutations of (pq|rs) (the gradient convention: dE/dh = gamma,
+ * dE/d(pq|rs) = Gamma/2 for symmetric perturbations), each NULL if not
+ * wanted.  EINVAL if any of them is asked for with keep_ci = 0. */
+int mbefci_casci(mbefci_ctx* ctx, int32_t norb, int32_t nalpha, int32_t nbeta, const double* h1,
+                 const double* eri, double e_core, double* e_out, double* ci_out, double* rdm1,
+                 double* rdm2, void* hip_stream);
+/* A batch of nprob independent CASCIs of one shape, solved together (one
+ * Davidson iteration advances all of them): h1s[i] device [n*n], eris[i]
  * device [n^4] (host arrays of device pointers), e_core host [nprob].
  * e_out host [nprob]: lowest eigenvalues.  ci_out: NULL or host array of
- * nprob device pointers [Na*Nb] receiving the normalised eigenvectors. */
-int mbefci_casci(mbefci_ctx* ctx, int32_t nprob, int32_t norb, int32_t nalpha, int32_t nbeta,
-                 const double* const* h1s, const double* const* eris, const double* e_core,
-                 double* e_out, double* const* ci_out, mbefci_stats* stats, void* hip_stream);
-/* Spin-summed RDMs of the CI vectors kept by the last mbefci_casci on ctx:
- * rdm1s[i] device [n*n] gamma_pq = <E_pq>, rdm2s[i] device [n^4]
- * Gamma_pqrs = <E_pq E_rs> - delta_qr gamma_ps, symmetrised over the eight
- * index permutations of (pq|rs) (the gradient convention: dE/dh = gamma,
- * dE/d(pq|rs) = Gamma/2 for symmetric perturbations).  Either may be NULL. */
+ * nprob device pointers [Na*Nb] (entries may be NULL) receiving the
+ * normalised eigenvectors (EINVAL with keep_ci = 0). */
+int mbefci_casci_batch(mbefci_ctx* ctx, int32_t nprob, int32_t norb, int32_t nalpha,
+                       int32_t nbeta, const double* const* h1s, const double* const* eris,
+                       const double* e_core, double* e_out, double* const* ci_out,
+                       mbefci_stats* stats, void* hip_stream);
+/* RDMs (as for mbefci_casci) of the CI vectors kept by the last CASCI solve
+ * on ctx (mbefci_casci_batch or mbefci_casci): rdm1s[i] device [n*n],
+ * rdm2s[i] device [n^4]; either array may be NULL. */
 int mbefci_casci_rdm(mbefci_ctx* ctx, double* const* rdm1s, double* const* rdm2s,
                      void* hip_stream);
 

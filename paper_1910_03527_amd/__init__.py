@@ -9,11 +9,12 @@ Names mirror the C ABI without the ``mbefci_`` prefix:
 
 * ``Context``            -- mbefci_create / mbefci_destroy / options
 * ``num_strings``, ``num_links``, ``num_tuples``
-* ``Context.strings``, ``Context.link_table``  (device string / link tables)
-* ``Context.hdiag``, ``Context.sigma``         (one CASCI Hamiltonian)
-* ``Context.casci``                            (batch of same-shape CASCIs)
-* ``casci``                                    (one CASCI, optionally with its RDMs)
-* ``Context.casci_rdm``                        (their 1- and 2-RDMs)
+* ``strings``, ``link_table``                  (host string / link tables, no context)
+* ``Context.strings``, ``Context.link_table``  (the same tables built on the device)
+* ``Context.hdiag``, ``Context.sigma``, ``Context.sigma_noalloc``  (one CASCI Hamiltonian)
+* ``Context.casci``                            (mbefci_casci_batch: same-shape CASCIs)
+* ``Context.casci_one``, ``casci``             (mbefci_casci: one CASCI, its CI vector and RDMs)
+* ``Context.casci_rdm``                        (RDMs of the last CASCI solve)
 * ``Context.mbe_forward``, ``Context.mbe_backward``  (Eq. 1 / Eq. 2)
 * ``Context.mbe_screened``  (order-by-order expansion with the Eq. 4 screening)
 * ``partition``  (the Type-1/2/3 reference/expansion partitions)
@@ -27,11 +28,13 @@ from .binding import (  # noqa: F401
     Context,
     MbefciError,
     casci,
+    link_table,
     MBEEnergy,
     num_links,
     num_strings,
     num_tuples,
     partition,
+    strings,
     TYPE1,
     TYPE2,
     TYPE3,

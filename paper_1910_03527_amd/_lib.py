@@ -20,11 +20,12 @@ ERROR_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", ENOTCONV: "ENOTCONV", EDEVICE
 # every symbol include/mbefci.h declares
 EXPORTS = (
     "mbefci_default_opts", "mbefci_create", "mbefci_destroy", "mbefci_last_error",
-    "mbefci_set_opts", "mbefci_set_allocator", "mbefci_num_strings", "mbefci_num_links", "mbefci_strings",
-    "mbefci_link_table", "mbefci_num_tuples", "mbefci_hdiag", "mbefci_sigma",
-    "mbefci_sigma_noalloc", "mbefci_casci",
-    "mbefci_casci_rdm", "mbefci_mbe_forward", "mbefci_mbe_backward", "mbefci_mbe_screened",
-    "mbefci_screened_tuples", "mbefci_partition", "mbefci_time_kernels", "mbefci_probe_peaks",
+    "mbefci_set_opts", "mbefci_set_allocator", "mbefci_num_strings", "mbefci_num_links",
+    "mbefci_strings", "mbefci_link_table", "mbefci_strings_device", "mbefci_link_table_device",
+    "mbefci_num_tuples", "mbefci_hdiag", "mbefci_sigma", "mbefci_sigma_noalloc", "mbefci_casci",
+    "mbefci_casci_batch", "mbefci_casci_rdm", "mbefci_mbe_forward", "mbefci_mbe_backward",
+    "mbefci_mbe_screened", "mbefci_screened_tuples", "mbefci_partition", "mbefci_time_kernels",
+    "mbefci_probe_peaks",
 )
 
 
@@ -146,18 +147,24 @@ def load():
     L.mbefci_num_links.restype = i32
     L.mbefci_num_tuples.argtypes = [i32, i32]
     L.mbefci_num_tuples.restype = i64
-    L.mbefci_strings.argtypes = [vp, i32, i32, vp, vp]
+    L.mbefci_strings.argtypes = [i32, i32, vp]
     L.mbefci_strings.restype = ctypes.c_int
-    L.mbefci_link_table.argtypes = [vp, i32, i32, vp, vp]
+    L.mbefci_link_table.argtypes = [i32, i32, vp]
     L.mbefci_link_table.restype = ctypes.c_int
+    L.mbefci_strings_device.argtypes = [vp, i32, i32, vp, vp]
+    L.mbefci_strings_device.restype = ctypes.c_int
+    L.mbefci_link_table_device.argtypes = [vp, i32, i32, vp, vp]
+    L.mbefci_link_table_device.restype = ctypes.c_int
     L.mbefci_hdiag.argtypes = [vp, i32, i32, i32, vp, vp, dbl, vp, vp]
     L.mbefci_hdiag.restype = ctypes.c_int
     L.mbefci_sigma.argtypes = [vp, i32, i32, i32, vp, vp, dbl, vp, vp, vp]
     L.mbefci_sigma.restype = ctypes.c_int
     L.mbefci_sigma_noalloc.argtypes = [vp, i32, i32, i32, vp, vp, dbl, vp, vp, vp]
     L.mbefci_sigma_noalloc.restype = ctypes.c_int
-    L.mbefci_casci.argtypes = [vp, i32, i32, i32, i32, pvp, pvp, ctypes.POINTER(dbl),
+    L.mbefci_casci_batch.argtypes = [vp, i32, i32, i32, i32, pvp, pvp, ctypes.POINTER(dbl),
                                ctypes.POINTER(dbl), pvp, ctypes.POINTER(Stats), vp]
+    L.mbefci_casci_batch.restype = ctypes.c_int
+    L.mbefci_casci.argtypes = [vp, i32, i32, i32, vp, vp, dbl, ctypes.POINTER(dbl), vp, vp, vp, vp]
     L.mbefci_casci.restype = ctypes.c_int
     L.mbefci_casci_rdm.argtypes = [vp, pvp, pvp, vp]
     L.mbefci_casci_rdm.restype = ctypes.c_int

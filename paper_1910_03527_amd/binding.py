@@ -25,6 +25,28 @@ def num_tuples(nexp: int, max_order: int) -> int:
     return int(_lib.load().mbefci_num_tuples(nexp, max_order))
 
 
+def strings(norb: int, nelec: int) -> np.ndarray:
+    """The string bitmasks of nelec electrons in norb orbitals, ascending
+    (mbefci_strings: host, no context, no device)."""
+    n = num_strings(norb, nelec)
+    out = np.zeros(max(n, 1), dtype=np.uint64)
+    rc = _lib.load().mbefci_strings(norb, nelec, out.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise MbefciError(rc, "mbefci_strings failed")
+    return out[:n]
+
+
+def link_table(norb: int, nelec: int) -> np.ndarray:
+    """[nstr, nlink, 4] = (p, q, J, sign) single-excitation links
+    (mbefci_link_table: host, no context, no device)."""
+    n, nl = num_strings(norb, nelec), num_links(norb, nelec)
+    out = np.zeros((max(n, 1), max(nl, 1), 4), dtype=np.int32)
+    rc = _lib.load().mbefci_link_table(norb, nelec, out.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise MbefciError(rc, "mbefci_link_table failed")
+    return out[:n, :nl]
+
+
 def _dev_f64(t: torch.Tensor, shape, name: str) -> torch.Tensor:
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise ValueError(f"{name} must be a device tensor")
@@ -144,15 +166,16 @@ class Context:
     def strings(self, norb: int, nelec: int) -> torch.Tensor:
         n = num_strings(norb, nelec)
         out = torch.empty(max(n, 1), dtype=torch.int64, device=self._dev())
-        self._check(self._L.mbefci_strings(self._h, norb, nelec, ctypes.c_void_p(out.data_ptr()),
-                                           self._stream()))
+        self._check(self._L.mbefci_strings_device(self._h, norb, nelec,
+                                                  ctypes.c_void_p(out.data_ptr()), self._stream()))
         return out[:n]
 
     def link_table(self, norb: int, nelec: int) -> torch.Tensor:
         n, L = num_strings(norb, nelec), num_links(norb, nelec)
         out = torch.empty((max(n, 1), max(L, 1), 4), dtype=torch.int32, device=self._dev())
-        self._check(self._L.mbefci_link_table(self._h, norb, nelec,
-                                              ctypes.c_void_p(out.data_ptr()), self._stream()))
+        self._check(self._L.mbefci_link_table_device(self._h, norb, nelec,
+                                                     ctypes.c_void_p(out.data_ptr()),
+                                                     self._stream()))
         return out[:n, :L]
 
     # --------------------------------------------------- one Hamiltonian
@@ -219,7 +242,7 @@ class Context:
             cis = [torch.empty(nd, dtype=torch.float64, device=self._dev()) for _ in range(nprob)]
             cp = (ctypes.c_void_p * nprob)(*[t.data_ptr() for t in cis])
         st = _lib.Stats()
-        self._check(self._L.mbefci_casci(self._h, nprob, n, nalpha, nbeta,
+        self._check(self._L.mbefci_casci_batch(self._h, nprob, n, nalpha, nbeta,
                                          ctypes.cast(hp, ctypes.POINTER(ctypes.c_void_p)),
                                          ctypes.cast(gp, ctypes.POINTER(ctypes.c_void_p)), ec, eo,
                                          None if cp is None else
@@ -229,6 +252,28 @@ class Context:
         self._casci_shape = (nprob, n)
         e = list(eo)
         return (e, cis) if want_ci else e
+
+    def casci_one(self, h1, eri, nalpha: int, nbeta: int, e_core: float = 0.0,
+                  want_ci: bool = False, want_rdm: bool = False):
+        """One CASCI through mbefci_casci: the energy, and on request the CI
+        vector [Na*Nb] and (gamma [n, n], Gamma [n, n, n, n]) as device
+        tensors: returns a dict with keys e, ci, rdm1, rdm2."""
+        n = h1.shape[0]
+        _dev_f64(h1, (n, n), "h1")
+        _dev_f64(eri, (n, n, n, n), "eri")
+        nd = num_strings(n, nalpha) * num_strings(n, nbeta)
+        ci = torch.empty(nd, dtype=torch.float64, device=self._dev()) if want_ci else None
+        g1 = torch.empty((n, n), dtype=torch.float64, device=self._dev()) if want_rdm else None
+        g2 = torch.empty((n,) * 4, dtype=torch.float64, device=self._dev()) if want_rdm else None
+        e = ctypes.c_double()
+
+        def p(t):
+            return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+        self._check(self._L.mbefci_casci(self._h, n, nalpha, nbeta, p(h1), p(eri), float(e_core),
+                                         ctypes.byref(e), p(ci), p(g1), p(g2), self._stream()))
+        self._casci_shape = (1, n)
+        return {"e": e.value, "ci": ci, "rdm1": g1, "rdm2": g2}
 
     def casci_rdm(self, want_rdm2: bool = True):
         """(gamma [nprob, n, n], Gamma [nprob, n, n, n, n]) of the last casci."""
@@ -346,7 +391,7 @@ class Context:
 
 def casci(h1, eri, nalpha: int, nbeta: int, e_core: float = 0.0, want_rdm: bool = False,
           **opts):
-    """One CASCI on the device of ``h1`` (mbefci_casci with a batch of one):
+    """One CASCI on the device of ``h1`` (mbefci_casci):
     the lowest eigenvalue of the S_z sector (nalpha, nbeta) plus ``e_core``,
     and with ``want_rdm`` also (gamma [n, n], Gamma [n, n, n, n]) in the
     chemist convention E = sum h gamma + 1/2 sum (pq|rs) Gamma + e_core.
@@ -355,11 +400,8 @@ def casci(h1, eri, nalpha: int, nbeta: int, e_core: float = 0.0, want_rdm: bool 
     dev = h1.device.index if h1.device.index is not None else torch.cuda.current_device()
     ctx = Context(dev, **opts)
     try:
-        e = ctx.casci([h1], [eri], nalpha, nbeta, e_core=[e_core])[0]
-        if not want_rdm:
-            return e
-        g1, g2 = ctx.casci_rdm()
-        return e, g1[0], g2[0]
+        r = ctx.casci_one(h1, eri, nalpha, nbeta, e_core, want_rdm=want_rdm)
+        return (r["e"], r["rdm1"], r["rdm2"]) if want_rdm else r["e"]
     finally:
         ctx.close()
 

@@ -1206,7 +1206,84 @@ int64_t mbefci_num_tuples(int32_t nexp, int32_t max_order) {
   return s;
 }
 
-int mbefci_strings(mbefci_ctx* c, int32_t norb, int32_t nelec, uint64_t* out, void* stream) {
+// ---- integer layer on the host (no context, no device) -----------------------
+namespace {
+// Strings of nelec electrons in norb orbitals in ascending integer order: the
+// next larger integer with the same number of set bits (Gosper's method).
+// Returns false when the count exceeds the int32 addresses of the tables.
+bool host_strings(int norb, int nelec, std::vector<uint64_t>* out) {
+  const int64_t N = binom_host(norb, nelec);
+  if (N <= 0 || N > INT32_MAX) return false;
+  out->resize(N);
+  uint64_t v = nelec == 64 ? ~(uint64_t)0 : (((uint64_t)1 << nelec) - 1);
+  for (int64_t i = 0; i < N; ++i) {
+    (*out)[i] = v;
+    if (i + 1 < N) {
+      const uint64_t t = v | (v - 1);
+      v = (t + 1) | (((~t & (t + 1)) - 1) >> (__builtin_ctzll(v) + 1));
+    }
+  }
+  return true;
+}
+// address = sum_j C(o_j, j) over the occupied orbitals o_1 < o_2 < ...
+int64_t host_string_addr(uint64_t m) {
+  int64_t a = 0;
+  int j = 1;
+  for (; m; m &= m - 1, ++j) a += binom_host(__builtin_ctzll(m), j);
+  return a;
+}
+}  // namespace
+
+int mbefci_strings(int32_t norb, int32_t nelec, uint64_t* out) {
+  if (norb < 0 || norb > 64 || nelec < 0 || nelec > norb || !out) return MBEFCI_EINVAL;
+  try {
+    std::vector<uint64_t> s;
+    if (!host_strings(norb, nelec, &s)) return MBEFCI_EINVAL;
+    std::copy(s.begin(), s.end(), out);
+    return MBEFCI_OK;
+  } catch (const std::exception&) {
+    return MBEFCI_ENOMEM;
+  }
+}
+
+int mbefci_link_table(int32_t norb, int32_t nelec, int32_t* out) {
+  if (norb < 0 || norb > 32 || nelec < 0 || nelec > norb || !out) return MBEFCI_EINVAL;
+  try {
+    std::vector<uint64_t> s;
+    if (!host_strings(norb, nelec, &s)) return MBEFCI_EINVAL;
+    const int64_t L = (int64_t)nelec * (norb - nelec + 1);
+    for (size_t I = 0; I < s.size(); ++I) {
+      const uint64_t m = s[I];
+      int32_t* e = out + (int64_t)I * L * 4;
+      int idx = 0;
+      for (int o = 0; o < norb; ++o)  // E_oo I = I for occupied o
+        if (m >> o & 1) {
+          e[4 * idx] = o, e[4 * idx + 1] = o, e[4 * idx + 2] = (int32_t)I, e[4 * idx + 3] = 1;
+          ++idx;
+        }
+      for (int q = 0; q < norb; ++q) {
+        if (!(m >> q & 1)) continue;
+        for (int p = 0; p < norb; ++p) {
+          if (m >> p & 1) continue;
+          const uint64_t r = (m & ~((uint64_t)1 << q)) | ((uint64_t)1 << p);
+          const int lo = std::min(p, q), hi = std::max(p, q);
+          const uint64_t between = (((uint64_t)1 << hi) - 1) & ~((((uint64_t)1 << lo) << 1) - 1);
+          e[4 * idx] = p;
+          e[4 * idx + 1] = q;
+          e[4 * idx + 2] = (int32_t)host_string_addr(r);
+          e[4 * idx + 3] = (__builtin_popcountll(m & between) & 1) ? -1 : 1;
+          ++idx;
+        }
+      }
+    }
+    return MBEFCI_OK;
+  } catch (const std::exception&) {
+    return MBEFCI_ENOMEM;
+  }
+}
+
+int mbefci_strings_device(mbefci_ctx* c, int32_t norb, int32_t nelec, uint64_t* out,
+                          void* stream) {
   return guarded(c, [&] {
     if (norb < 0 || norb > 64 || nelec < 0 || nelec > norb || !out)
       throw Error(MBEFCI_EINVAL, "invalid string shape");
@@ -1217,7 +1294,8 @@ int mbefci_strings(mbefci_ctx* c, int32_t norb, int32_t nelec, uint64_t* out, vo
   });
 }
 
-int mbefci_link_table(mbefci_ctx* c, int32_t norb, int32_t nelec, int32_t* out, void* stream) {
+int mbefci_link_table_device(mbefci_ctx* c, int32_t norb, int32_t nelec, int32_t* out,
+                             void* stream) {
   return guarded(c, [&] {
     if (norb < 0 || norb > 32 || nelec < 0 || nelec > norb || !out)
       throw Error(MBEFCI_EINVAL, "invalid link-table shape");
@@ -1289,53 +1367,90 @@ int mbefci_sigma_noalloc(mbefci_ctx* c, int32_t n, int32_t na, int32_t nb, const
   return rc;
 }
 
-int mbefci_casci(mbefci_ctx* c, int32_t nprob, int32_t n, int32_t na, int32_t nb,
+namespace {
+// Solve a batch of same-shape CASCIs (the caller's StreamScope is active);
+// copies the CI vectors to ci_out[i] when given (needs keep_ci).
+void casci_batch(mbefci_ctx* c, int32_t nprob, int32_t n, int32_t na, int32_t nb,
                  const double* const* h1s, const double* const* eris, const double* e_core,
-                 double* e_out, double* const* ci_out, mbefci_stats* stats, void* stream) {
+                 double* e_out, double* const* ci_out, mbefci_stats* stats) {
+  auto t_start = std::chrono::steady_clock::now();
+  check_shape(n, na, nb);
+  if (nprob < 1 || !h1s || !eris || !e_core || !e_out)
+    throw Error(MBEFCI_EINVAL, "invalid batch arguments");
+  bool want_ci = false;
+  for (int i = 0; ci_out && i < nprob; ++i) want_ci |= ci_out[i] != nullptr;
+  if (want_ci && !c->opts.keep_ci)
+    throw Error(MBEFCI_EINVAL, "CI vectors requested with keep_ci = 0");
+  for (int i = 0; i < nprob; ++i) {
+    if (!h1s[i] || !eris[i]) throw Error(MBEFCI_EINVAL, "null integral pointer");
+    check_integrals(c, n, h1s[i], eris[i]);
+  }
+  casci_plan(c, nprob, n, na, nb, h1s, eris, e_core);
+  Plan& P = *c->plan;
+  mbefci_stats st{};
+  solve_plan(c, P, &st);
+  launch_item_energy(P.d_items, P.hams, P.st, P.nitem, P.f, c->stream);
+  std::vector<double> e(nprob);
+  HIPCHK(hipMemcpyAsync(e.data(), P.f, nprob * 8, hipMemcpyDeviceToHost, c->stream));
+  if (want_ci)
+    for (int i = 0; i < nprob; ++i)
+      if (ci_out[i])
+        HIPCHK(hipMemcpyAsync(ci_out[i], P.ci + P.items[i].off, P.items[i].ndet * 8,
+                              hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::copy(e.begin(), e.end(), e_out);
+  c->have_forward = true;
+  st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                          t_start).count();
+  if (stats) *stats = st;
+}
+
+// RDMs of the CI vectors kept by the last casci_batch (StreamScope active).
+void casci_rdms(mbefci_ctx* c, double* const* rdm1s, double* const* rdm2s) {
+  if (!c->plan || c->plan->is_mbe || !c->have_forward)
+    throw Error(MBEFCI_EINVAL, "the RDMs need a preceding CASCI solve on ctx");
+  if (!c->opts.keep_ci) throw Error(MBEFCI_EINVAL, "CI vectors were not kept (keep_ci = 0)");
+  Plan& P = *c->plan;
+  RdmOut R = rdm_pass(c, P);
+  for (int i = 0; i < P.nitem; ++i)
+    launch_casci_rdm_out(P.d_items, i, P.items[i].n, R.rdmp, R.roff, rdm1s ? rdm1s[i] : nullptr,
+                         rdm2s ? rdm2s[i] : nullptr, c->stream);
+  HIPCHK(hipGetLastError());
+}
+}  // namespace
+
+int mbefci_casci_batch(mbefci_ctx* c, int32_t nprob, int32_t n, int32_t na, int32_t nb,
+                       const double* const* h1s, const double* const* eris, const double* e_core,
+                       double* e_out, double* const* ci_out, mbefci_stats* stats, void* stream) {
   return guarded(c, [&] {
-    auto t_start = std::chrono::steady_clock::now();
-    check_shape(n, na, nb);
-    if (nprob < 1 || !h1s || !eris || !e_core || !e_out)
-      throw Error(MBEFCI_EINVAL, "invalid batch arguments");
     StreamScope sc(c, stream);
-    for (int i = 0; i < nprob; ++i) {
-      if (!h1s[i] || !eris[i]) throw Error(MBEFCI_EINVAL, "null integral pointer");
-      check_integrals(c, n, h1s[i], eris[i]);
+    casci_batch(c, nprob, n, na, nb, h1s, eris, e_core, e_out, ci_out, stats);
+    sc.done();
+  });
+}
+
+int mbefci_casci(mbefci_ctx* c, int32_t n, int32_t na, int32_t nb, const double* h1,
+                 const double* eri, double e_core, double* e_out, double* ci_out, double* rdm1,
+                 double* rdm2, void* stream) {
+  return guarded(c, [&] {
+    if (!c->opts.keep_ci && (ci_out || rdm1 || rdm2))
+      throw Error(MBEFCI_EINVAL, "CI vector or RDMs requested with keep_ci = 0");
+    StreamScope sc(c, stream);
+    double* const cis[1] = {ci_out};
+    casci_batch(c, 1, n, na, nb, &h1, &eri, &e_core, e_out, ci_out ? cis : nullptr, nullptr);
+    if (rdm1 || rdm2) {
+      double* const r1[1] = {rdm1};
+      double* const r2[1] = {rdm2};
+      casci_rdms(c, r1, r2);
     }
-    casci_plan(c, nprob, n, na, nb, h1s, eris, e_core);
-    Plan& P = *c->plan;
-    mbefci_stats st{};
-    solve_plan(c, P, &st);
-    launch_item_energy(P.d_items, P.hams, P.st, P.nitem, P.f, c->stream);
-    std::vector<double> e(nprob);
-    HIPCHK(hipMemcpyAsync(e.data(), P.f, nprob * 8, hipMemcpyDeviceToHost, c->stream));
-    if (ci_out && c->opts.keep_ci)
-      for (int i = 0; i < nprob; ++i)
-        if (ci_out[i])
-          HIPCHK(hipMemcpyAsync(ci_out[i], P.ci + P.items[i].off, P.items[i].ndet * 8,
-                                hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    std::copy(e.begin(), e.end(), e_out);
-    c->have_forward = true;
-    st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
-                                                            t_start).count();
-    if (stats) *stats = st;
     sc.done();
   });
 }
 
 int mbefci_casci_rdm(mbefci_ctx* c, double* const* rdm1s, double* const* rdm2s, void* stream) {
   return guarded(c, [&] {
-    if (!c->plan || c->plan->is_mbe || !c->have_forward)
-      throw Error(MBEFCI_EINVAL, "mbefci_casci_rdm needs a preceding mbefci_casci on ctx");
-    if (!c->opts.keep_ci) throw Error(MBEFCI_EINVAL, "CI vectors were not kept (keep_ci = 0)");
     StreamScope sc(c, stream);
-    Plan& P = *c->plan;
-    RdmOut R = rdm_pass(c, P);
-    for (int i = 0; i < P.nitem; ++i)
-      launch_casci_rdm_out(P.d_items, i, P.items[i].n, R.rdmp, R.roff, rdm1s ? rdm1s[i] : nullptr,
-                           rdm2s ? rdm2s[i] : nullptr, c->stream);
-    HIPCHK(hipGetLastError());
+    casci_rdms(c, rdm1s, rdm2s);
     sc.done();
   });
 }
