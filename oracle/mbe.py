@@ -33,19 +33,28 @@ def tuples(expansion, max_order):
     return out
 
 
+def _casci(h, g, e_const, occ, active, orbsym):
+    if orbsym is None:
+        return fci.casci(h, g, e_const, occ, active)
+    from . import sym
+    return sym.casci(h, g, e_const, occ, active, orbsym, 0)
+
+
 def _solve_one(args):
-    h, g, e_const, occ, active = args
+    h, g, e_const, occ, active, orbsym = args
     try:
         from threadpoolctl import threadpool_limits
         with threadpool_limits(1):
-            return fci.casci(h, g, e_const, occ, active)
+            return _casci(h, g, e_const, occ, active, orbsym)
     except ImportError:  # pragma: no cover
-        return fci.casci(h, g, e_const, occ, active)
+        return _casci(h, g, e_const, occ, active, orbsym)
 
 
-def tuple_energies(h, g, e_const, occ, ref, tups, workers=1):
-    """f(T) for T in ``tups`` (the empty tuple gives E_ref)."""
-    jobs = [(h, g, e_const, list(occ), sorted(set(ref) | set(t))) for t in tups]
+def tuple_energies(h, g, e_const, occ, ref, tups, workers=1, orbsym=None):
+    """f(T) for T in ``tups`` (the empty tuple gives E_ref).  With ``orbsym``
+    (irrep labels of the MOs) each CASCI is solved in the irrep of the
+    closed-shell reference determinant, the totally symmetric one."""
+    jobs = [(h, g, e_const, list(occ), sorted(set(ref) | set(t)), orbsym) for t in tups]
     if workers <= 1 or len(jobs) < 4:
         return [_solve_one(j) for j in jobs]
     with ProcessPoolExecutor(max_workers=workers) as ex:
@@ -84,7 +93,7 @@ def mbe(prob, max_order=None, workers=None):
         workers = os.cpu_count() or 1
     tups = tuples(prob.exp, k)
     energies = tuple_energies(prob.h1, prob.eri, prob.e_const, prob.occ, prob.ref,
-                              [()] + tups, workers)
+                              [()] + tups, workers, getattr(prob, "orbsym", None))
     f_ref = energies[0]
     f = dict(zip(tups, energies[1:]))
     eps, dinc = increments(f_ref, f)

@@ -56,6 +56,7 @@ __all__ = [
     "hubbard_site",
     "hubbard_mo",
     "synthetic",
+    "synthetic_sym",
     "pipek_mezey",
     "hubbard_pm",
     "lieb_wu_energy",
@@ -77,6 +78,7 @@ class Problem:
     ref: list               # reference space R (possibly empty)
     exp: list               # expansion space X (disjoint from R)
     max_order: int
+    orbsym: list = None     # point-group irrep label (0..7) per MO, or None
 
     @property
     def norb(self) -> int:
@@ -213,6 +215,33 @@ def synthetic(norb: int, seed: int, nchol: int = 120):
     lmat = np.zeros((nchol, norb, norb))
     for p in range(nchol):
         v = rng.standard_normal(len(sd0)) * sd0
+        lmat[p][iu0] = v
+        lmat[p][(iu0[1], iu0[0])] = v
+    flat = lmat.reshape(nchol, norb * norb)
+    g = (flat.T @ flat).reshape((norb,) * 4)
+    return h, g
+
+
+def synthetic_sym(norb: int, seed: int, orbsym, nchol: int = 120):
+    """Synthetic integrals that respect a point group with abelian irreps
+    labelled 0..7 (D2h and its subgroups; the product of two irreps is the
+    XOR of their labels): the same distributions as ``synthetic``, with h_pq
+    kept only where orbsym[p] == orbsym[q], and Cholesky-like vectors L^P of
+    irrep P % 8 kept only where orbsym[p] ^ orbsym[q] == P % 8, so that
+    (pq|rs) = sum_P L^P_pq L^P_rs vanishes unless the four irreps multiply to
+    the totally symmetric one.  ``orbsym``: [norb] labels 0..7."""
+    sym = np.asarray(orbsym, dtype=np.int64)
+    if sym.shape != (norb,) or np.any(sym < 0) or np.any(sym > 7):
+        raise ValueError("orbsym must hold norb labels in 0..7")
+    h, _ = synthetic(norb, seed, nchol=1)
+    h = np.where(sym[:, None] == sym[None, :], h, 0.0)
+    rng = np.random.default_rng(seed + 7919)
+    iu0 = np.triu_indices(norb, 0)
+    sd0 = 0.05 * np.exp(-np.abs(iu0[0] - iu0[1]) / 6.0)
+    pair_sym = sym[iu0[0]] ^ sym[iu0[1]]
+    lmat = np.zeros((nchol, norb, norb))
+    for p in range(nchol):
+        v = rng.standard_normal(len(sd0)) * sd0 * (pair_sym == p % 8)
         lmat[p][iu0] = v
         lmat[p][(iu0[1], iu0[0])] = v
     flat = lmat.reshape(nchol, norb * norb)
