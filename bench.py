@@ -105,30 +105,86 @@ def kernel_replay_cas14x8(args):
 
 
 def _kernel_rows(kt, workload):
-    """Per-kernel rates of one re-timed sigma sweep, with the measured HBM
-    rate where a counter record of that kernel and workload exists."""
+    """Per-kernel rates of one re-timed sigma sweep: algorithmic flops and
+    bytes over the launch time, and, where a counter record of that kernel and
+    workload exists, the counted bytes over the launch time.  The counters
+    (FETCH_SIZE + WRITE_SIZE) see what the L2 moves to and from the fabric,
+    hits in the last-level cache included, so that rate is not HBM traffic."""
     rows = []
     for k in kt:
         s = k["ms_per_launch"] * 1e-3
         tr = _traffic(k["name"], workload)
-        rows.append({"name": k["name"], "ms_per_launch": round(k["ms_per_launch"], 4),
+        rows.append({"name": k["name"], "launches": k["launches"],
+                     "ms_per_launch": round(k["ms_per_launch"], 4),
                      "tflops": round(k["flops"] / s / 1e12, 3),
                      "gbps": round(k["bytes"] / s / 1e9, 1),
-                     "gbps_hbm_measured": round(tr / s / 1e9, 1) if tr else None})
+                     "gbps_l2_fabric_counted": round(tr / s / 1e9, 1) if tr else None})
     return rows
 
 
-def _buckets(prob):
-    occ = set(prob.occ)
-    xo = sorted(p for p in prob.exp if p in occ)
-    xv = sorted(p for p in prob.exp if p not in occ)
-    out = []
-    for n in range(1, prob.max_order + 1):
-        for a in range(0, n + 1):
-            cnt = math.comb(len(xo), a) * math.comb(len(xv), n - a)
-            if cnt:
-                out.append((n, a, cnt, tuple(sorted(xo[:a] + xv[:n - a]))))
-    return out
+def _roofline(kt, workload):
+    """The roofline record of the dominant kernel of a re-timed sigma sweep."""
+    for k in kt:
+        k["tflops"] = k["flops"] / (k["ms_per_launch"] * 1e-3) / 1e12
+        k["gbps"] = k["bytes"] / (k["ms_per_launch"] * 1e-3) / 1e9
+    dom = max(kt, key=lambda k: k["ms_per_launch"] * k["launches"])
+    if dom["name"].startswith("sigma_dgemm"):
+        return {"kernel": dom["name"], "bound": "mfma", "achieved": round(dom["tflops"], 3),
+                "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(dom["tflops"] / FP64_MFMA_PEAK_TFLOPS, 4),
+                "traffic": _traffic(dom["name"], workload),
+                "ms_per_launch": dom["ms_per_launch"], "launches_per_sweep": dom["launches"],
+                "algorithmic_flops": dom["flops"], "algorithmic_bytes": dom["bytes"]}
+    return {"kernel": dom["name"], "bound": "hbm", "achieved": round(dom["gbps"], 1),
+            "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(dom["gbps"] / HBM_PEAK_GBPS, 4),
+            "traffic": _traffic(dom["name"], workload),
+            "ms_per_launch": dom["ms_per_launch"], "launches_per_sweep": dom["launches"],
+            "algorithmic_bytes": dom["bytes"]}
+
+
+def _sigma_build(kt, workload, copy_gbps):
+    """sigma-sweep totals: algorithmic bytes (c read, G written and read back,
+    sigma written) and flops over the summed kernel times, against the
+    published HBM peak and the copy rate measured in the same run; the counted
+    L2-fabric bytes beside them, which include last-level-cache hits and can
+    exceed what HBM delivers."""
+    sig_ms = sum(k["ms_per_launch"] * k["launches"] for k in kt)
+    sig_bytes = sum(k["bytes"] * k["launches"] for k in kt)
+    sig_flops = sum(k["flops"] * k["launches"] for k in kt)
+    meas = [(k, _traffic(k["name"], workload)) for k in kt]
+    meas = [(k, tr) for k, tr in meas if tr is not None]
+    meas_ms = sum(k["ms_per_launch"] * k["launches"] for k, _ in meas)
+    meas_bytes = sum(tr * k["launches"] for k, tr in meas)
+    gbps = sig_bytes / (sig_ms * 1e-3) / 1e9
+    return {"ms_per_sweep": round(sig_ms, 4),
+            "gbps": round(gbps, 1),
+            "frac_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4),
+            "frac_copy_measured": round(gbps / copy_gbps, 4) if copy_gbps else None,
+            "bytes_per_sweep_algorithmic": sig_bytes,
+            "tflops_mfma": round(sig_flops / (sig_ms * 1e-3) / 1e12, 3),
+            "gbps_l2_fabric_counted": (round(meas_bytes / (meas_ms * 1e-3) / 1e9, 1)
+                                       if meas else None),
+            "counted_kernels": [k["name"] for k, _ in meas],
+            "counted_share_of_sweep": (round(meas_ms / sig_ms, 4) if meas else None)}
+
+
+def _progress(msg):
+    """One line on stderr when a phase of the run ends."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    """The host CPU's model name (/proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def _oracle_job(args):
@@ -141,61 +197,73 @@ def _oracle_job(args):
         return e, time.perf_counter() - t0
 
 
-def _oracle_sigma_job(args):
-    """Oracle sigma rows of one CAS(14e,14o) instance: `nrow` sampled rows of
-    H c for a seeded random c; returns the seconds per row."""
-    seed, nrow = args
+def _cas14_sigma(workers):
+    """One oracle sigma = H c of CAS(14e,14o) instance 1 (11,778,624
+    determinants) with the matrix-free Slater-Condon operator on `workers`
+    threads: (setup seconds, sigma seconds)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
     import workloads as W
-    from oracle import fci
+    from oracle import direct, fci
     p = W.problem("cas14", 0)
     a = fci.string_masks(range(14), 7)
-    rng = np.random.default_rng(seed)
-    c = rng.standard_normal(len(a) * len(a))
-    c /= np.linalg.norm(c)
-    rows = np.sort(rng.choice(len(c), nrow, replace=False))
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        fci.sigma_rows(p.h1, p.eri, 0.0, a, a, c, rows)
-        return (time.perf_counter() - t0) / nrow
+        H = direct.DirectHamiltonian(p.h1, p.eri, 0.0, a, a, threads=workers)
+        t1 = time.perf_counter()
+        c = np.random.default_rng(0).standard_normal(H.n)
+        t2 = time.perf_counter()
+        H.matvec(c)
+        t3 = time.perf_counter()
+        H.close()
+    return t1 - t0, t3 - t2
 
 
-def cpu_baseline(prob, nsolve, workers):
-    """The CPU oracle (Slater-Condon CASCI, single-threaded per CASCI) on the
-    reference CASCI plus the first tuple of every bucket, run in parallel;
-    whole-workload rate extrapolated by bucket counts."""
+def cpu_baseline(prob, workers, stride, with_cas14=True):
+    """The CPU oracle (Slater-Condon CASCI, one thread per CASCI) on every
+    `stride`-th tuple of the workload's lexicographic tuple list plus the
+    reference CASCI (stride 1: the whole list), in a process pool of `workers`
+    processes, largest CASCIs submitted first.  The rate is the CASCIs solved
+    over the wall time of the pool: measured on that sample, not scaled."""
     from concurrent.futures import ProcessPoolExecutor
-    bks = _buckets(prob)
-    tups = [()] + [b[3] for b in bks]
-    jobs = [(prob.h1, prob.eri, prob.e_const, list(prob.occ), sorted(set(prob.ref) | set(t)))
-            for t in tups]
+    tl = list(itertools.chain.from_iterable(
+        itertools.combinations(sorted(prob.exp), n) for n in range(1, prob.max_order + 1)))
+    tups = [()] + tl[::stride]
+    occ = set(prob.occ)
+
+    def ndet(t):
+        act = set(prob.ref) | set(t)
+        return math.comb(len(act), len(occ & act)) ** 2
+
+    order = sorted(range(len(tups)), key=lambda i: -ndet(tups[i]))
+    jobs = [(prob.h1, prob.eri, prob.e_const, list(prob.occ),
+             sorted(set(prob.ref) | set(tups[i]))) for i in order]
     t0 = time.perf_counter()
     with ProcessPoolExecutor(max_workers=workers) as ex:
         res = list(ex.map(_oracle_job, jobs))
-        wall = time.perf_counter() - t0
-        # one sigma of the CAS(14e,14o) workload: sampled rows, extrapolated
-        nrow = 512
-        per_row = list(ex.map(_oracle_sigma_job, [(s, nrow) for s in range(workers)]))
-    core_s = res[0][1] + sum(b[2] * r[1] for b, r in zip(bks, res[1:]))
-    sig_core_s = 11778624 * sum(per_row) / len(per_row)
-    return {
-        "value": nsolve / (core_s / workers),
+    wall = time.perf_counter() - t0
+    energies = {tups[i]: r[0] for i, r in zip(order, res)}
+    core_s = sum(r[1] for r in res)
+    out = {
+        "value": round(len(tups) / wall, 3),
         "unit": "CASCI solves/s",
         "cores": workers,
         "kind": "oracle",
-        "sample": (f"reference CASCI + first tuple of each of {len(bks)} (order, n_occ) buckets "
-                   f"({len(tups)} CASCIs, {wall:.1f} s wall on {workers} processes, one thread "
-                   f"each); whole workload = sum over buckets of count x sampled time = "
-                   f"{core_s:.0f} core-s, spread over {workers} cores"),
-        "core_seconds_estimate": core_s,
-        "cas14_sigma": {
-            "core_seconds_per_sigma_estimate": sig_core_s,
-            "seconds_per_sigma_on_cores": sig_core_s / workers,
-            "sample": (f"{nrow} rows of H c per process, {workers} processes (seeded random c), "
-                       "x 11,778,624 rows"),
-        },
-    }, dict(zip(tups, [r[0] for r in res]))
+        "cpu": cpu_model(),
+        "sample": (f"every {stride}th tuple of the {len(tl)}-tuple lexicographic list plus the "
+                   f"reference CASCI: {len(tups)} CASCIs ({sum(ndet(t) for t in tups)} "
+                   f"determinants), {wall:.1f} s wall on {workers} processes of one thread, "
+                   f"{core_s:.0f} core-s"),
+        "wall_s": round(wall, 2),
+        "core_seconds": round(core_s, 1),
+    }
+    if with_cas14:
+        setup, sig = _cas14_sigma(workers)
+        out["cas14_sigma"] = {
+            "seconds_per_sigma": round(sig, 2), "setup_s": round(setup, 2), "threads": workers,
+            "sample": "one whole sigma = H c of CAS(14,14) instance 1 (11,778,624 rows), "
+                      "matrix-free Slater-Condon oracle"}
+    return out, energies
 
 
 def main():
@@ -207,6 +275,10 @@ def main():
     ap.add_argument("--per-launch-steps", type=int, default=1)
     ap.add_argument("--reps", type=int, default=5, help="kernel re-timing repetitions")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-stride", type=int, default=8,
+                    help="CPU baseline: the oracle solves every N-th tuple (plus the reference)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="CPU baseline over the whole tuple list (same as --cpu-stride 1)")
     ap.add_argument("--no-screened", action="store_true",
                     help="skip the screened-expansion measurement")
     ap.add_argument("--no-lattice", action="store_true",
@@ -236,13 +308,13 @@ def main():
     if args.kernel_replay and args.workload == "cas14x8":
         return kernel_replay_cas14x8(args)
     prob = W.problem(args.workload)
-    nsolve_expected = 1 + sum(math.comb(len(prob.exp), n) for n in range(1, prob.max_order + 1))
     # the oracle runs first, in worker processes forked before this process
     # touches the GPU
     cb = fo = None
     if not args.no_cpu_baseline:
         workers = max(1, min(16, os.cpu_count() or 1))
-        cb, fo = cpu_baseline(prob, nsolve_expected, workers)
+        cb, fo = cpu_baseline(prob, workers, 1 if args.cpu_full else max(1, args.cpu_stride))
+        _progress(f"cpu baseline: {cb['value']} CASCI/s on {workers} cores")
 
     dev = torch.device("cuda", 0)
     h1 = torch.as_tensor(prob.h1, dtype=torch.float64, device=dev)
@@ -294,6 +366,7 @@ def main():
     stats = dict(ctx.last_stats)
     nsolve = int(stats["ntuples"])
     value = nsolve / (ms / 1e3)
+    _progress(f"{args.workload}: {ms:.2f} ms per step, {value:.1f} CASCI/s")
 
     # one CASCI per launch sequence, same kernels, same tolerance
     per_launch = None
@@ -315,30 +388,14 @@ def main():
 
     # sigma kernels re-timed on the library stream (HIP events)
     kt = ctx.time_kernels(args.reps)
-    for k in kt:
-        k["tflops"] = k["flops"] / (k["ms_per_launch"] * 1e-3) / 1e12
-        k["gbps"] = k["bytes"] / (k["ms_per_launch"] * 1e-3) / 1e9
-    dom = max(kt, key=lambda k: k["ms_per_launch"] * k["launches"])
-    if dom["name"].startswith("sigma_dgemm"):
-        roof = {"kernel": dom["name"], "bound": "mfma", "achieved": round(dom["tflops"], 3),
-                "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(dom["tflops"] / FP64_MFMA_PEAK_TFLOPS, 4),
-                "traffic": _traffic(dom["name"], args.workload),
-                "ms_per_launch": dom["ms_per_launch"], "launches_per_sweep": dom["launches"],
-                "algorithmic_flops": dom["flops"], "algorithmic_bytes": dom["bytes"]}
-    else:
-        roof = {"kernel": dom["name"], "bound": "hbm", "achieved": round(dom["gbps"], 1),
-                "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(dom["gbps"] / HBM_PEAK_GBPS, 4),
-                "traffic": _traffic(dom["name"], args.workload),
-                "ms_per_launch": dom["ms_per_launch"], "launches_per_sweep": dom["launches"],
-                "algorithmic_bytes": dom["bytes"]}
+    roof = _roofline(kt, args.workload)
     # the device's attainable peaks measured beside the published ones
     # (mbefci_probe_peaks: FP64 MFMA chains from registers, a 256 MiB copy)
     peaks = ctx.probe_peaks()
     measured = peaks["fp64_mfma_tflops"] if roof["bound"] == "mfma" else peaks["copy_gbps"]
     roof["peak_measured"] = round(measured, 3)
     roof["frac_of_measured"] = round(roof["achieved"] / measured, 4)
+    _progress(f"kernels re-timed; roofline {roof['kernel']} frac {roof['frac']}")
     # the screened order-by-order driver (Eq. 4 thresholds with the paper's
     # parameters) on the vacuum-reference Hubbard-16 expansion, in a context
     # of its own (it replaces the context's cached plan)
@@ -374,6 +431,7 @@ def main():
                         "sigma_calls": ss["sigma_calls"], "max_iters": ss["max_iters"]}
         finally:
             sctx.close()
+        _progress("screened expansion done")
 
     # the paper's Type-3 lattice workload: a 22-site Hubbard chain (U/t = 2) in
     # Pipek-Mezey orbitals, vacuum reference, screened expansion to order 8
@@ -435,6 +493,7 @@ def main():
                 "e_per_site_above_tdl": rl["e_total"] / lp.norb - e_tdl}
         finally:
             lctx.close()
+        _progress("lattices done")
 
     # the other workload configurations, each warm, in contexts of their own
     configs = None
@@ -471,9 +530,31 @@ def main():
                                  "ncasci": int(sc["ntuples"]), "max_order": cp.max_order,
                                  "sigma_calls": sc["sigma_calls"], "e_total": rc["e_total"]}
                 if name == "synthetic40":
-                    configs[name]["kernels"] = _kernel_rows(cctx.time_kernels(2), name)
+                    kc = cctx.time_kernels(2)
+                    configs[name]["kernels"] = _kernel_rows(kc, name)
+                    configs[name]["roofline"] = _roofline(kc, name)
+                    configs[name]["sigma_build"] = _sigma_build(kc, name, peaks["copy_gbps"])
+                    if args.per_launch_steps > 0:
+                        # one CASCI per launch sequence, same kernels and tolerance
+                        cctx.set_opts(mode=PER_LAUNCH)
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        rpl = cctx.mbe_forward(ch, cg, cp.occ, cp.ref, cp.exp, cp.max_order,
+                                               cp.e_const, want_increments=True)
+                        torch.cuda.synchronize()
+                        mpl = (time.perf_counter() - t0) * 1e3
+                        cctx.set_opts(mode=BATCHED)
+                        rb = cctx.mbe_forward(ch, cg, cp.occ, cp.ref, cp.exp, cp.max_order,
+                                              cp.e_const, want_increments=True)
+                        configs[name]["per_launch"] = {
+                            "value": round(sc["ntuples"] / (mpl / 1e3), 2),
+                            "ms_per_forward": round(mpl, 1),
+                            "batched_speedup_forward": round(mpl / mc, 2),
+                            "max_abs_energy_diff_vs_batched": float(np.max(np.abs(
+                                np.array(rpl["energies"]) - np.array(rb["energies"]))))}
             finally:
                 cctx.close()
+            _progress(f"config {name} done")
         # 8 x CAS(14e,14o): one batched solve plus the RDMs, and the sigma
         # kernels of that batch re-timed
         probs = [W.problem("cas14", i) for i in range(8)]
@@ -495,18 +576,11 @@ def main():
                 "step": "forward + RDMs", "ndet_each": 11778624,
                 "sigma_calls": sc["sigma_calls"], "max_iters": sc["max_iters"],
                 "energies": ec,
-                "kernels": _kernel_rows(kc, "cas14x8")}
+                "kernels": _kernel_rows(kc, "cas14x8"),
+                "roofline": _roofline(kc, "cas14x8"),
+                "sigma_build": _sigma_build(kc, "cas14x8", peaks["copy_gbps"])}
         finally:
             cctx.close()
-
-    sig_ms = sum(k["ms_per_launch"] * k["launches"] for k in kt)
-    sig_bytes = sum(k["bytes"] * k["launches"] for k in kt)
-    sig_flops = sum(k["flops"] * k["launches"] for k in kt)
-    # measured HBM traffic (rocprofv3 records) of the sigma kernels that have one
-    meas = [(k, _traffic(k["name"], args.workload)) for k in kt]
-    meas = [(k, tr) for k, tr in meas if tr is not None]
-    meas_ms = sum(k["ms_per_launch"] * k["launches"] for k, _ in meas)
-    meas_bytes = sum(tr * k["launches"] for k, tr in meas)
 
     out = {
         "metric": METRIC,
@@ -532,16 +606,7 @@ def main():
         "solver": {"sigma_calls": stats["sigma_calls"], "max_iters": stats["max_iters"],
                    "graph_launches": stats["graph_launches"], "ms_solve": stats["ms_solve"],
                    "ms_autotune_once": stats["ms_tune"], "e_total": res["e_total"]},
-        "sigma_build": {"ms_per_sweep": round(sig_ms, 4),
-                        "gbps_algorithmic": round(sig_bytes / (sig_ms * 1e-3) / 1e9, 1),
-                        "frac_hbm": round(sig_bytes / (sig_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                        "tflops_mfma": round(sig_flops / (sig_ms * 1e-3) / 1e12, 3),
-                        "gbps_hbm_measured": (round(meas_bytes / (meas_ms * 1e-3) / 1e9, 1)
-                                              if meas else None),
-                        "frac_hbm_measured": (round(meas_bytes / (meas_ms * 1e-3) / 1e9
-                                                    / HBM_PEAK_GBPS, 4) if meas else None),
-                        "measured_kernels": [k["name"] for k, _ in meas],
-                        "measured_share_of_sweep": (round(meas_ms / sig_ms, 4) if meas else None)},
+        "sigma_build": _sigma_build(kt, args.workload, peaks["copy_gbps"]),
         "kernels": [{k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in k.items()}
                     for k in kt],
         "roofline": roof,
@@ -557,6 +622,7 @@ def main():
         diffs = [abs(res["energies"][idx[t]] - e) for t, e in fo.items() if t]
         diffs.append(abs(res["e_ref"] - fo[()]))
         cb["gpu_vs_oracle_max_abs_energy_diff"] = max(diffs)
+        cb["gpu_vs_oracle_casci_compared"] = len(fo)
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
