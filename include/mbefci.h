@@ -117,6 +117,12 @@ typedef struct {
   int32_t nexp;            /* |X|                                                    */
   const int32_t* exp;      /* host [nexp]: expansion space X, disjoint from R        */
   int32_t max_order;       /* k, 0..nexp (0: only the reference CASCI)               */
+  const int32_t* orbsym;   /* host [M] point-group irreps 0..7 of the MOs (D2h or a
+                              subgroup, product = XOR), or NULL.  With irreps every
+                              CASCI is solved in the totally symmetric irrep (that of
+                              the closed-shell reference determinant) on the
+                              point-group blocked path; supported by
+                              mbefci_mbe_screened only (EUNSUPPORTED elsewhere)     */
 } mbefci_problem;
 
 typedef struct {
@@ -259,6 +265,38 @@ int mbefci_casci_batch(mbefci_ctx* ctx, int32_t nprob, int32_t norb, int32_t nal
  * rdm2s[i] device [n^4]; either array may be NULL. */
 int mbefci_casci_rdm(mbefci_ctx* ctx, double* const* rdm1s, double* const* rdm2s,
                      void* hip_stream);
+
+/* ---- point-group blocked CASCIs ---------------------------------------------
+ * The paper's Cr2 expansion solves its CASCIs with D2h symmetry (Fig. 3
+ * discussion: the largest, 2.07e7 determinants "with D2h symmetry").  Orbital
+ * irreps of D2h or a subgroup are labels 0..7 whose product is their XOR; a
+ * string's irrep is the XOR of its occupied orbitals' labels, a determinant's
+ * the XOR of its two strings'.  A CASCI of irrep G holds only the determinants
+ * of irrep G.  Layout of its CI vector: the strings of each spin sorted by
+ * (irrep, bitmask); blocks over the alpha irreps a = 0..7 in order, block a =
+ * [alpha strings of irrep a][beta strings of irrep a^G] row-major.  Sigma runs
+ * one FP64-MFMA contraction per pair class s (pairs p >= q with irr(p)^irr(q)
+ * = s) on the determinants of irrep G^s.  RDMs are not available for these
+ * CASCIs (mbefci_casci_rdm returns EUNSUPPORTED). */
+/* Host, no context: determinants of irrep wfnsym of norb orbitals with
+ * irreps orbsym [norb] (0..7) and nalpha / nbeta electrons; EINVAL (negative)
+ * for invalid arguments. */
+int64_t mbefci_sym_ndet(int32_t norb, int32_t nalpha, int32_t nbeta, const int32_t* orbsym,
+                        int32_t wfnsym);
+/* A batch of same-shape CASCIs in irrep wfnsym (as mbefci_casci_batch; orbsym
+ * host [norb] irreps of the active orbitals).  ci_out[i]: device
+ * [mbefci_sym_ndet(...)] in the layout above.  EINVAL when the irrep has no
+ * determinant. */
+int mbefci_casci_sym(mbefci_ctx* ctx, int32_t nprob, int32_t norb, int32_t nalpha,
+                     int32_t nbeta, const int32_t* orbsym, int32_t wfnsym,
+                     const double* const* h1s, const double* const* eris, const double* e_core,
+                     double* e_out, double* const* ci_out, mbefci_stats* stats,
+                     void* hip_stream);
+/* sigma = H c (e_core included) on the determinants of irrep wfnsym: c, sigma
+ * device [mbefci_sym_ndet(...)] in the layout above. */
+int mbefci_sigma_sym(mbefci_ctx* ctx, int32_t norb, int32_t nalpha, int32_t nbeta,
+                     const int32_t* orbsym, int32_t wfnsym, const double* h1, const double* eri,
+                     double e_core, const double* c, double* sigma, void* hip_stream);
 
 /* ---- many-body expansion -------------------------------------------------
  * Solves E_ref (CASCI of R) and the CASCI of R u T for every tuple T of

@@ -100,13 +100,16 @@ def screened_mbe(prob, t_init, m_init, a, max_order=None, workers=None):
     if workers is None:
         workers = os.cpu_count() or 1
     occ = set(prob.occ)
-    f_ref = _mbe.tuple_energies(prob.h1, prob.eri, prob.e_const, prob.occ, prob.ref, [()], 1)[0]
+    osym = getattr(prob, "orbsym", None)
+    f_ref = _mbe.tuple_energies(prob.h1, prob.eri, prob.e_const, prob.occ, prob.ref, [()], 1,
+                                osym)[0]
     inc = {}
     e_order = [0.0] * kmax
     per_order = [[] for _ in range(kmax)]
     k, level = first_level(prob.exp, occ, prob.ref)
     while k <= kmax and level:
-        f = _mbe.tuple_energies(prob.h1, prob.eri, prob.e_const, prob.occ, prob.ref, level, workers)
+        f = _mbe.tuple_energies(prob.h1, prob.eri, prob.e_const, prob.occ, prob.ref, level, workers,
+                                osym)
         cur = {}
         for t, ft in zip(level, f):
             d = ft - f_ref

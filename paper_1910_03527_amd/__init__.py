@@ -15,6 +15,7 @@ Names mirror the C ABI without the ``mbefci_`` prefix:
 * ``Context.casci``                            (mbefci_casci_batch: same-shape CASCIs)
 * ``Context.casci_one``, ``casci``             (mbefci_casci: one CASCI, its CI vector and RDMs)
 * ``Context.casci_rdm``                        (RDMs of the last CASCI solve)
+* ``sym_ndet``, ``Context.casci_sym``, ``Context.sigma_sym``  (point-group blocked CASCIs)
 * ``Context.mbe_forward``, ``Context.mbe_backward``  (Eq. 1 / Eq. 2)
 * ``Context.mbe_screened``  (order-by-order expansion with the Eq. 4 screening)
 * ``partition``  (the Type-1/2/3 reference/expansion partitions)
@@ -35,6 +36,7 @@ from .binding import (  # noqa: F401
     num_tuples,
     partition,
     strings,
+    sym_ndet,
     TYPE1,
     TYPE2,
     TYPE3,

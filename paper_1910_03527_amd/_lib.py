@@ -23,7 +23,8 @@ EXPORTS = (
     "mbefci_set_opts", "mbefci_set_allocator", "mbefci_num_strings", "mbefci_num_links",
     "mbefci_strings", "mbefci_link_table", "mbefci_strings_device", "mbefci_link_table_device",
     "mbefci_num_tuples", "mbefci_hdiag", "mbefci_sigma", "mbefci_sigma_noalloc", "mbefci_casci",
-    "mbefci_casci_batch", "mbefci_casci_rdm", "mbefci_mbe_forward", "mbefci_mbe_backward",
+    "mbefci_casci_batch", "mbefci_casci_rdm", "mbefci_sym_ndet", "mbefci_casci_sym",
+    "mbefci_sigma_sym", "mbefci_mbe_forward", "mbefci_mbe_backward",
     "mbefci_mbe_screened", "mbefci_screened_tuples", "mbefci_partition", "mbefci_time_kernels",
     "mbefci_probe_peaks",
 )
@@ -68,6 +69,7 @@ class Problem(ctypes.Structure):
         ("nexp", ctypes.c_int32),
         ("exp", ctypes.POINTER(ctypes.c_int32)),
         ("max_order", ctypes.c_int32),
+        ("orbsym", ctypes.POINTER(ctypes.c_int32)),
     ]
 
 
@@ -166,6 +168,15 @@ def load():
     L.mbefci_casci_batch.restype = ctypes.c_int
     L.mbefci_casci.argtypes = [vp, i32, i32, i32, vp, vp, dbl, ctypes.POINTER(dbl), vp, vp, vp, vp]
     L.mbefci_casci.restype = ctypes.c_int
+    pi32 = ctypes.POINTER(i32)
+    L.mbefci_sym_ndet.argtypes = [i32, i32, i32, pi32, i32]
+    L.mbefci_sym_ndet.restype = ctypes.c_int64
+    L.mbefci_casci_sym.argtypes = [vp, i32, i32, i32, i32, pi32, i32, pvp, pvp,
+                                   ctypes.POINTER(dbl), ctypes.POINTER(dbl), pvp,
+                                   ctypes.POINTER(Stats), vp]
+    L.mbefci_casci_sym.restype = ctypes.c_int
+    L.mbefci_sigma_sym.argtypes = [vp, i32, i32, i32, pi32, i32, vp, vp, dbl, vp, vp, vp]
+    L.mbefci_sigma_sym.restype = ctypes.c_int
     L.mbefci_casci_rdm.argtypes = [vp, pvp, pvp, vp]
     L.mbefci_casci_rdm.restype = ctypes.c_int
     L.mbefci_mbe_forward.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(dbl),

@@ -47,6 +47,14 @@ def link_table(norb: int, nelec: int) -> np.ndarray:
     return out[:n, :nl]
 
 
+def sym_ndet(norb: int, nalpha: int, nbeta: int, orbsym, wfnsym: int = 0) -> int:
+    """Determinants of irrep ``wfnsym`` (mbefci_sym_ndet: host, no context)."""
+    nd = int(_lib.load().mbefci_sym_ndet(norb, nalpha, nbeta, _i32(orbsym), int(wfnsym)))
+    if nd < 0:
+        raise MbefciError(nd, "mbefci_sym_ndet failed")
+    return nd
+
+
 def _dev_f64(t: torch.Tensor, shape, name: str) -> torch.Tensor:
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise ValueError(f"{name} must be a device tensor")
@@ -320,16 +328,21 @@ class Context:
 
     def mbe_screened(self, h1, eri, occ, ref, exp, max_order: int, t_init: float = 1e-10,
                      m_init: int = 3, a: float = 5.0, e_const: float = 0.0,
-                     want_tuples: bool = False):
+                     want_tuples: bool = False, orbsym=None):
         """Screened order-by-order expansion (mbefci_mbe_screened).  Returns
         dict(e_ref, e_order [k], e_total, n_order [k]) and, with want_tuples,
-        per_order: list over orders of (tuples int32 [n][order], increments)."""
+        per_order: list over orders of (tuples int32 [n][order], increments).
+        ``orbsym``: point-group irreps (0..7) of the MOs, or None; with them
+        every CASCI is solved in the totally symmetric irrep on the blocked
+        path."""
         M = h1.shape[0]
         _dev_f64(h1, (M, M), "h1")
         _dev_f64(eri, (M, M, M, M), "eri")
         occ_a, ref_a, exp_a = _i32(occ), _i32(ref), _i32(exp)
+        sym_a = _i32(orbsym) if orbsym is not None else None
         pb = _lib.Problem(M, h1.data_ptr(), eri.data_ptr(), float(e_const), len(occ), occ_a,
-                          len(ref), ref_a, len(exp), exp_a, int(max_order))
+                          len(ref), ref_a, len(exp), exp_a, int(max_order),
+                          ctypes.cast(sym_a, ctypes.POINTER(ctypes.c_int32)) if sym_a else None)
         sc = _lib.Screen(float(t_init), float(a), int(m_init), 0)
         e_ref = ctypes.c_double()
         e_tot = ctypes.c_double()
@@ -355,6 +368,57 @@ class Context:
                 arr = np.frombuffer(tu, dtype=np.int32, count=n * k).reshape(n, k).copy()
                 per.append((arr, list(inc)[:n]))
             out["per_order"] = per
+        return out
+
+    # ---------------------------------------------- point-group blocked
+    def casci_sym(self, h1s, eris, nalpha: int, nbeta: int, orbsym, wfnsym: int = 0,
+                  e_core=None, want_ci: bool = False):
+        """Lowest eigenvalues of a batch of same-shape CASCIs in irrep
+        ``wfnsym`` (mbefci_casci_sym); with ``want_ci`` also the CI vectors in
+        the blocked layout of include/mbefci.h."""
+        if isinstance(h1s, torch.Tensor) and h1s.dim() == 2:
+            h1s, eris = [h1s], [eris]
+        nprob = len(h1s)
+        n = h1s[0].shape[0]
+        for i in range(nprob):
+            _dev_f64(h1s[i], (n, n), f"h1[{i}]")
+            _dev_f64(eris[i], (n, n, n, n), f"eri[{i}]")
+        nd = sym_ndet(n, nalpha, nbeta, orbsym, wfnsym)
+        ecore = [0.0] * nprob if e_core is None else [float(x) for x in e_core]
+        hp = (ctypes.c_void_p * nprob)(*[t.data_ptr() for t in h1s])
+        gp = (ctypes.c_void_p * nprob)(*[t.data_ptr() for t in eris])
+        ec = (ctypes.c_double * nprob)(*ecore)
+        eo = (ctypes.c_double * nprob)()
+        cis = cp = None
+        if want_ci:
+            cis = [torch.empty(max(nd, 1), dtype=torch.float64, device=self._dev())
+                   for _ in range(nprob)]
+            cp = (ctypes.c_void_p * nprob)(*[t.data_ptr() for t in cis])
+        st = _lib.Stats()
+        self._check(self._L.mbefci_casci_sym(
+            self._h, nprob, n, nalpha, nbeta, _i32(orbsym), int(wfnsym),
+            ctypes.cast(hp, ctypes.POINTER(ctypes.c_void_p)),
+            ctypes.cast(gp, ctypes.POINTER(ctypes.c_void_p)), ec, eo,
+            None if cp is None else ctypes.cast(cp, ctypes.POINTER(ctypes.c_void_p)),
+            ctypes.byref(st), self._stream()))
+        self.last_stats = st.as_dict()
+        e = list(eo)
+        return (e, [t[:nd] for t in cis]) if want_ci else e
+
+    def sigma_sym(self, h1, eri, nalpha: int, nbeta: int, orbsym, wfnsym: int, c,
+                  e_core: float = 0.0) -> torch.Tensor:
+        """sigma = H c on the determinants of irrep ``wfnsym`` (blocked layout;
+        mbefci_sigma_sym)."""
+        n = h1.shape[0]
+        _dev_f64(h1, (n, n), "h1")
+        _dev_f64(eri, (n, n, n, n), "eri")
+        nd = sym_ndet(n, nalpha, nbeta, orbsym, wfnsym)
+        _dev_f64(c, (nd,), "c")
+        out = torch.empty(nd, dtype=torch.float64, device=self._dev())
+        self._check(self._L.mbefci_sigma_sym(
+            self._h, n, nalpha, nbeta, _i32(orbsym), int(wfnsym), ctypes.c_void_p(h1.data_ptr()),
+            ctypes.c_void_p(eri.data_ptr()), float(e_core), ctypes.c_void_p(c.data_ptr()),
+            ctypes.c_void_p(out.data_ptr()), self._stream()))
         return out
 
     def time_kernels(self, reps: int = 5):

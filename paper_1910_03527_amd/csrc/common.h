@@ -48,6 +48,32 @@ __device__ inline T ldc(const T* p) {
   return *(const __attribute__((address_space(4))) T*)p;
 }
 
+// Point-group blocking (abelian groups: D2h and its subgroups).  Irreps are
+// labels 0..7 whose product is their XOR; a string's irrep is the XOR of its
+// occupied orbitals' labels.  The strings of each spin are sorted by (irrep,
+// bitmask), and the CI vector of irrep G holds only the determinants of that
+// irrep: blocks over the alpha irreps a = 0..7, block a = [nac[a]][nbc[a^G]]
+// (alpha strings of irrep a times beta strings of irrep a^G) at offset
+// blk[a].  A one-body operator E_pq changes the irrep by the pair class
+// s = irr(p)^irr(q), and the pair-space matrix W couples only pairs of one
+// class, so sigma splits into one contraction per class s on the
+// determinants of irrep G^s: G_s = W_s D+_s.  Pairs are listed class by class
+// (positions cls0[s] .. cls0[s+1]-1), and G_s is stored per alpha irrep a' of
+// the irrep-G^s space as [nac[a']][npair_s][nbc[a'^G^s]] at gofs[s][a'].
+constexpr int kIrreps = 8;
+struct SymInfo {
+  int32_t wfn;                       // irrep G of the solved state
+  int32_t npair;                     // pairs in all classes (n(n+1)/2)
+  int32_t na0[kIrreps], nac[kIrreps];  // first sorted alpha string of each irrep, count
+  int32_t nb0[kIrreps], nbc[kIrreps];  // the same for beta strings
+  int64_t blk[kIrreps + 1];          // CI block offsets (blk[8] = determinants of irrep G)
+  int32_t cls0[kIrreps + 1];         // class-sorted pair positions of class s
+  int32_t pair_of[kMaxPair];         // class-sorted position -> pair index a(a+1)/2+b
+  int8_t cls_of[kMaxPair];           // class-sorted position -> its class
+  int64_t gofs[kIrreps][kIrreps];    // G_s block of alpha irrep a', from the item's G
+  int64_t gsize;                     // doubles of all G_s blocks
+};
+
 // One CASCI problem inside a batch.
 struct Item {
   int32_t n, na, nb, npair;
@@ -68,7 +94,30 @@ struct Item {
   const uint64_t* strB;   // [Nb] beta string bitmasks
   const int32_t* pairA;   // [Na][npair] pair table (see pack_pair_entry)
   const int32_t* pairB;   // [npair][Nb] the same for beta strings, pair-major
+  // point-group blocked CASCI (null: the plain [Na][Nb] layout).  Then strA,
+  // strB are sorted by (irrep, bitmask); links and pair tables hold string
+  // indices local to their irrep and class-sorted pair positions; linkA
+  // [Na][La], linkB [Nb][Lb], pairA [Na][npair], pairB [npair][Nb]; ndet is
+  // the number of determinants of irrep sym->wfn.
+  const SymInfo* sym;
 };
+
+// The alpha and beta strings of determinant K of item I, in either layout.
+__host__ __device__ inline void det_strings(const Item& I, int64_t K, uint64_t& ma,
+                                            uint64_t& mb) {
+  if (!I.sym) {
+    ma = I.strA[K / I.Nb];
+    mb = I.strB[K % I.Nb];
+    return;
+  }
+  const SymInfo& S = *I.sym;
+  int a = 0;
+  while (a < kIrreps - 1 && K >= S.blk[a + 1]) ++a;
+  const int b = a ^ S.wfn;
+  const int64_t loc = K - S.blk[a];
+  ma = I.strA[S.na0[a] + loc / S.nbc[b]];
+  mb = I.strB[S.nb0[b] + loc % S.nbc[b]];
+}
 
 // Pair table entry of string K and orbital pair (a >= b): the single
 // excitation among E_ab K, E_ba K that does not vanish (at most one does for

@@ -324,8 +324,8 @@ __global__ void k_hdiag(const Item* __restrict__ items, const Work* __restrict__
   const int64_t K = (int64_t)wk.begin * blockDim.x + threadIdx.x;
   if (K >= I.ndet) return;
   const ItemHam& H = hams[I.ham];
-  const int Ka = (int)(K / I.Nb), Kb = (int)(K % I.Nb);
-  const uint64_t ma = I.strA[Ka], mb = I.strB[Kb];
+  uint64_t ma, mb;
+  det_strings(I, K, ma, mb);
   double e = 0.0;
   for (uint64_t x = ma; x; x &= x - 1) {
     int p = __builtin_ctzll(x);
@@ -840,6 +840,174 @@ __global__ void __launch_bounds__(256) k_sigma_gather(const Item* __restrict__ i
     acc0 += link_sign(e0) * ldg(Grow + link_pair(e0) * Gs + link_addr(e0));
   }
   Sarena[(int64_t)vs * ntot + I.off + (int64_t)Ka * Nb + Kb] = acc0 + acc1;
+}
+
+// ------------------------------------------------- point-group blocked sigma
+// The contraction of one pair class s on the determinants of irrep G^s:
+// G_s = W_s D+_s on FP64 MFMA.  A work unit is (item, class s, alpha irrep
+// a' of the irrep-G^s space) and a range of tiles of that block; a tile is
+// one alpha string ka (local to irrep a') and kSymTile consecutive beta
+// strings of irrep b' = a'^G^s, numbered column-major (tile = block * nac[a']
+// + ka) so a unit stays inside one beta block.  D+ rows are the class's
+// pairs, zero-padded to NPC.  The alpha half of a D+ entry reads c in CI
+// block a'^s (beta irrep b', rows of nbc[b']), the beta half in block a'
+// (rows of nbc[a'^G]).  Work.pad_ = s * 8 + a'.
+constexpr int kSymTile = 32;
+
+template <int NPC>
+__global__ void __launch_bounds__(256) k_sigma_sym_dgemm(
+    const Item* __restrict__ items, const Work* __restrict__ work,
+    const double* __restrict__ warena, const double* __restrict__ V, int64_t ntot,
+    double* __restrict__ Garena, const DavState* __restrict__ st, int slot) {
+  constexpr int TN = kSymTile;
+  constexpr int KS = NPC / 4;       // MFMA k-steps
+  constexpr int NRB = NPC / 16;     // 16-row blocks of G_s
+  constexpr int RBW = (NRB + 3) / 4;
+  constexpr int NCB = TN / 16;
+  constexpr int LDT = TN + 1;
+  __shared__ double Ds[NPC * LDT];
+  __shared__ int32_t pl[NPC];       // class pair -> pair index (W row / column)
+
+  const Work wk = work[blockIdx.x];
+  const Item& I = items[wk.item];
+  const DavState& S = st[wk.item];
+  if (!item_active(S, slot)) return;
+  const SymInfo& Y = *I.sym;
+  const int vs = vec_slot(S, slot);
+  const double* __restrict__ c = V + (int64_t)vs * ntot + I.off;
+  const int s = wk.pad_ >> 3, ap = wk.pad_ & 7;
+  const int G = Y.wfn;
+  const int bp = ap ^ G ^ s;          // beta irrep of the tile
+  const int nps = Y.cls0[s + 1] - Y.cls0[s];
+  const int j0 = Y.cls0[s];
+  const int NA = Y.nac[ap], NB = Y.nbc[bp];
+  const int NBa = Y.nbc[ap ^ G];      // row length of CI block a'
+  const double* __restrict__ csrcA = c + Y.blk[ap ^ s];  // block a'^s: rows of NB
+  const double* __restrict__ csrcB = c + Y.blk[ap];      // block a': rows of NBa
+  const int32_t* __restrict__ pA = I.pairA + (int64_t)Y.na0[ap] * Y.npair + j0;
+  const int32_t* __restrict__ pB = I.pairB + (int64_t)j0 * I.Nb + Y.nb0[bp];
+  double* __restrict__ G_s = Garena + I.goff + Y.gofs[s][ap];
+  const int kpad = I.kpad;
+  const double* __restrict__ W = warena + I.woff;
+
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int i = t; i < NPC; i += 256) pl[i] = i < nps ? Y.pair_of[j0 + i] : -1;
+  __syncthreads();
+  const int wrot = (wave + (int)blockIdx.x) & 3;
+  double wreg[RBW][KS];
+#pragma unroll
+  for (int r = 0; r < RBW; ++r) {
+    const int rb = wrot + 4 * r;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int row = rb * 16 + (lane & 15), col = ks * 4 + (lane >> 4);
+      wreg[r][ks] = (rb < NRB && row < nps && col < nps)
+                        ? ldg(W + (int64_t)pl[row] * kpad + pl[col]) : 0.0;
+    }
+  }
+  const int blk = wk.begin / NA;
+  const int kb0 = blk * TN;
+  for (int tile = wk.begin; tile < wk.end; ++tile) {
+    const int ka = tile - blk * NA;
+    // D+ tile [NPC][TN]: class pair i, column kb0 + col
+    for (int x = t; x < NPC * TN; x += 256) {
+      const int i = x / TN, col = x % TN, kb = kb0 + col;
+      double v = 0.0;
+      if (i < nps && kb < NB) {
+        const int32_t ea = ldg(pA + (int64_t)ka * Y.npair + i);
+        if (ea) {
+          const double cv = ldg(csrcA + (int64_t)((ea >> 1) - 1) * NB + kb);
+          v += (ea & 1) ? -cv : cv;
+        }
+        const int32_t eb = ldg(pB + (int64_t)i * I.Nb + kb);
+        if (eb) {
+          const double cv = ldg(csrcB + (int64_t)ka * NBa + ((eb >> 1) - 1));
+          v += (eb & 1) ? -cv : cv;
+        }
+      }
+      Ds[i * LDT + col] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RBW; ++r) {
+      const int rb = wrot + 4 * r;
+      if (rb >= NRB) continue;
+      double4_t acc[NCB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[cb] = (double4_t){0.0, 0.0, 0.0, 0.0};
+      const double* bbase = Ds + (lane >> 4) * LDT + (lane & 15);
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(wreg[r][ks], bbase[ks * 4 * LDT + cb * 16],
+                                                         acc[cb], 0, 0, 0);
+      }
+      double* __restrict__ Grow = G_s + (int64_t)ka * nps * NB;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int kc = kb0 + cb * 16 + (lane & 15);
+        if (kc < NB) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            // register v of lane l: row l/16 + 4v, column l%16 of the block
+            const int row = rb * 16 + (lane >> 4) + 4 * v;
+            if (row < nps) Grow[(int64_t)row * NB + kc] = acc[cb][v];
+          }
+        }
+      }
+    }
+    __syncthreads();  // every MFMA read of Ds is done before the next tile's build
+  }
+}
+
+// sigma_I = sum over links of I of sign * G_s[K], blocked layout: one thread per
+// determinant I = (a, ia, ib) of irrep G (b = a^G).  An alpha link of ia
+// (class-sorted pair j of class s, string Ja local to irrep a^s) reads G_s in
+// block a^s, row (Ja, j - cls0[s]), column ib; a beta link of ib (string Jb
+// local to irrep b^s) reads G_s in block a, row (ia, j - cls0[s]), column Jb.
+// Work units: 256 consecutive determinants of one item (Work.begin).
+__global__ void __launch_bounds__(256) k_sigma_sym_gather(const Item* __restrict__ items,
+                                                          const Work* __restrict__ work,
+                                                          const double* __restrict__ Garena,
+                                                          double* __restrict__ Sarena,
+                                                          int64_t ntot,
+                                                          const DavState* __restrict__ st,
+                                                          int slot) {
+  const Work wk = work[blockIdx.x];
+  const Item& I = items[wk.item];
+  const DavState& S = st[wk.item];
+  if (!item_active(S, slot)) return;
+  const int64_t K = (int64_t)wk.begin * blockDim.x + threadIdx.x;
+  if (K >= I.ndet) return;
+  const SymInfo& Y = *I.sym;
+  const int vs = vec_slot(S, slot);
+  const int G = Y.wfn;
+  int a = 0;
+  while (a < kIrreps - 1 && K >= Y.blk[a + 1]) ++a;
+  const int b = a ^ G;
+  const int64_t loc = K - Y.blk[a];
+  const int ia = (int)(loc / Y.nbc[b]), ib = (int)(loc % Y.nbc[b]);
+  const double* __restrict__ Gi = Garena + I.goff;
+  double acc = 0.0;
+  const uint32_t* __restrict__ la = I.linkA + (int64_t)(Y.na0[a] + ia) * I.La;
+  for (int l = 0; l < I.La; ++l) {
+    const uint32_t e = ldg(la + l);
+    const int j = link_pair(e), s = Y.cls_of[j];
+    const int nps = Y.cls0[s + 1] - Y.cls0[s];
+    const int a2 = a ^ s;
+    acc += link_sign(e) * ldg(Gi + Y.gofs[s][a2] +
+                              ((int64_t)link_addr(e) * nps + (j - Y.cls0[s])) * Y.nbc[b] + ib);
+  }
+  const uint32_t* __restrict__ lb = I.linkB + (int64_t)(Y.nb0[b] + ib) * I.Lb;
+  for (int l = 0; l < I.Lb; ++l) {
+    const uint32_t e = ldg(lb + l);
+    const int j = link_pair(e), s = Y.cls_of[j];
+    const int nps = Y.cls0[s + 1] - Y.cls0[s];
+    acc += link_sign(e) * ldg(Gi + Y.gofs[s][a] +
+                              ((int64_t)ia * nps + (j - Y.cls0[s])) * Y.nbc[b ^ s] + link_addr(e));
+  }
+  Sarena[(int64_t)vs * ntot + I.off + K] = acc;
 }
 
 // ---------------------------------------------------------------- Davidson
@@ -1868,8 +2036,10 @@ __global__ void __launch_bounds__(NT) k_pspace_eigen(
   const ItemHam& H = hams[I.ham];
   for (int k = t; k < n; k += NT) {
     const int e = idx[k];  // an address of this item: 0 <= e < ndet
-    sa[k] = I.strA[e / I.Nb];
-    sb[k] = I.strB[e % I.Nb];
+    uint64_t ma, mb;
+    det_strings(I, e, ma, mb);
+    sa[k] = ma;
+    sb[k] = mb;
   }
   __syncthreads();
   auto L = [](int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; };
@@ -2828,6 +2998,33 @@ bool launch_sigma_dgemm(int n, int tn, const Item* items, const Work* work, int 
       return sigma_dgemm_n<128>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
     default: return false;
   }
+}
+
+int sym_npc(int npair_class) { return npair_class <= 0 ? 0 : (npair_class + 15) / 16 * 16; }
+
+bool launch_sigma_sym_dgemm(int npc, const Item* items, const Work* work, int nwork,
+                            const double* warena, const double* V, int64_t ntot, double* G,
+                            const DavState* st, int slot, hipStream_t s) {
+  if (nwork <= 0) return true;
+  switch (npc) {
+#define MBEFCI_CASE(P)                                                                        \
+  case P:                                                                                     \
+    hipLaunchKernelGGL((k_sigma_sym_dgemm<P>), dim3(nwork), dim3(256), 0, s, items, work,     \
+                       warena, V, ntot, G, st, slot);                                         \
+    return true;
+    MBEFCI_CASE(16) MBEFCI_CASE(32) MBEFCI_CASE(48) MBEFCI_CASE(64) MBEFCI_CASE(80)
+    MBEFCI_CASE(96) MBEFCI_CASE(112)
+#undef MBEFCI_CASE
+    default: return false;
+  }
+}
+
+void launch_sigma_sym_gather(const Item* items, const Work* work, int nwork, const double* G,
+                             double* Sv, int64_t ntot, const DavState* st, int slot,
+                             hipStream_t s) {
+  if (nwork > 0)
+    hipLaunchKernelGGL(k_sigma_sym_gather, dim3(nwork), dim3(256), 0, s, items, work, G, Sv, ntot,
+                       st, slot);
 }
 
 void launch_sigma_gather(const Item* items, const Work* work, int nwork, const double* G,

@@ -28,6 +28,17 @@ bool launch_sigma_dgemm(int n, int tn, const Item* items, const Work* work, int 
                         const DavState* st, int slot, hipStream_t s);
 void launch_sigma_gather(const Item* items, const Work* work, int nwork, const double* G,
                          double* Sv, int64_t ntot, const DavState* st, int slot, hipStream_t s);
+// point-group blocked sigma (items with a SymInfo): the per-class contraction
+// (npc = the class's pair count rounded up to 16, sym_npc; work units carry
+// class and alpha irrep in Work.pad_ = s * 8 + a') and the gather (work units
+// of 256 consecutive determinants)
+int sym_npc(int npair_class);
+bool launch_sigma_sym_dgemm(int npc, const Item* items, const Work* work, int nwork,
+                            const double* warena, const double* V, int64_t ntot, double* G,
+                            const DavState* st, int slot, hipStream_t s);
+void launch_sigma_sym_gather(const Item* items, const Work* work, int nwork, const double* G,
+                             double* Sv, int64_t ntot, const DavState* st, int slot,
+                             hipStream_t s);
 void launch_fill(double* p, int64_t n, double v, hipStream_t s);
 // peak probes: FP64 MFMA chains (256-thread blocks; flops of one launch from
 // probe_mfma_flops) and a copy of n doubles (n even, 16-byte aligned)

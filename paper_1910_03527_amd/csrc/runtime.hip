@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -65,6 +66,24 @@ struct StringTab {
   int32_t* pairT = nullptr;
 };
 
+// Tables of a point-group blocked CASCI shape (n, na, nb, the irreps of the
+// active orbitals, the target irrep): strings sorted by (irrep, bitmask),
+// links and pair tables with irrep-local string indices and class-sorted pair
+// positions, and the SymInfo record (see common.h).  One device block.
+struct SymTab {
+  int n = 0, na = 0, nb = 0, wfn = 0, La = 0, Lb = 0;
+  int64_t Na = 0, Nb = 0, ndet = 0, gsize = 0;
+  void* block = nullptr;
+  uint64_t* strA = nullptr;
+  uint64_t* strB = nullptr;
+  uint32_t* linkA = nullptr;  // [Na][La]
+  uint32_t* linkB = nullptr;  // [Nb][Lb]
+  int32_t* pairA = nullptr;   // [Na][npair]
+  int32_t* pairB = nullptr;   // [npair][Nb]
+  SymInfo* info = nullptr;    // device copy
+  SymInfo host{};
+};
+
 // One kernel-shape group of a plan: items with the same active size n share
 // the sigma contraction kernel (its pair dimension is a template parameter).
 struct Group {
@@ -92,6 +111,21 @@ struct Plan {
   std::vector<int> chunk_lo, chunk_hi, block_lo, block_hi, seg_lo, seg_hi;
   std::vector<Group> groups;
   std::vector<int> item_group;
+  // point-group blocked items: their tables (null for plain items), the
+  // per-class contraction work per padded class size, and the gather work
+  // (256-determinant blocks) with each item's ranges
+  struct SymGroup {
+    int npc = 0;
+    std::vector<Work> tiles;
+    std::vector<int> item_lo, item_hi;
+    Work* d_tiles = nullptr;
+  };
+  std::vector<const SymTab*> item_symtab;
+  std::vector<SymGroup> sym_groups;
+  std::vector<Work> sym_blocks;
+  std::vector<int> sym_blk_lo, sym_blk_hi;
+  Work* d_sym_blocks = nullptr;
+  bool has_sym = false;
   int nitem = 0, nchunk = 0, nblock = 0, nseg = 0;
   int64_t ntot = 0, gtot = 0, wtot = 0;
   int nsingle = 0;
@@ -157,6 +191,7 @@ struct mbefci_ctx {
   hipStream_t stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr, t0 = nullptr, t1 = nullptr;
   std::map<std::pair<int, int>, StringTab> tabs;
+  std::map<std::string, SymTab> symtabs;
   std::map<std::string, DevBuf> bufs;
   // workspace allocator of the caller (mbefci_set_allocator), or hipMalloc
   void* (*alloc_fn)(size_t, void*) = nullptr;
@@ -266,6 +301,187 @@ const StringTab& string_tab(mbefci_ctx* c, int n, int ne) {
   return c->tabs[key] = t;
 }
 
+// Tables of a point-group blocked CASCI shape, built on the host (integer
+// work) and cached per shape on the context.  osym: irreps of the n active
+// orbitals (0..7); wfn: the target irrep.
+const SymTab& sym_tab(mbefci_ctx* c, int n, int na, int nb, const int* osym, int wfn) {
+  std::string key = std::to_string(n) + "," + std::to_string(na) + "," + std::to_string(nb) +
+                    "," + std::to_string(wfn) + ":";
+  for (int t = 0; t < n; ++t) key += (char)('0' + osym[t]);
+  auto it = c->symtabs.find(key);
+  if (it != c->symtabs.end()) return it->second;
+  SymTab T;
+  T.n = n;
+  T.na = na;
+  T.nb = nb;
+  T.wfn = wfn;
+  SymInfo& Y = T.host;
+  std::memset(&Y, 0, sizeof(Y));
+  Y.wfn = wfn;
+  const int npair = n * (n + 1) / 2;
+  Y.npair = npair;
+  auto irrep = [&](uint64_t m) {
+    int x = 0;
+    for (; m; m &= m - 1) x ^= osym[__builtin_ctzll(m)];
+    return x;
+  };
+  auto addr = [](uint64_t m) {
+    int64_t a = 0;
+    int j = 1;
+    for (; m; m &= m - 1, ++j) a += binom_host(__builtin_ctzll(m), j);
+    return a;
+  };
+  // strings of one spin sorted by (irrep, bitmask); local index per address
+  struct Spin {
+    std::vector<uint64_t> sorted;
+    std::vector<int32_t> local;  // by address
+    int32_t off[kIrreps], cnt[kIrreps];
+  };
+  auto make_spin = [&](int ne) {
+    Spin S;
+    const int64_t N = binom_host(n, ne);
+    std::vector<uint64_t> all(N);
+    uint64_t v = ne == 0 ? 0 : (((uint64_t)1 << ne) - 1);
+    for (int64_t i = 0; i < N; ++i) {
+      all[i] = v;
+      if (i + 1 < N) {
+        const uint64_t t = v | (v - 1);
+        v = (t + 1) | (((~t & (t + 1)) - 1) >> (__builtin_ctzll(v) + 1));
+      }
+    }
+    for (int a = 0; a < kIrreps; ++a) S.cnt[a] = 0;
+    for (uint64_t m : all) ++S.cnt[irrep(m)];
+    int32_t o = 0;
+    for (int a = 0; a < kIrreps; ++a) {
+      S.off[a] = o;
+      o += S.cnt[a];
+    }
+    S.sorted.resize(N);
+    S.local.resize(N);
+    int32_t fill[kIrreps] = {0};
+    for (int64_t i = 0; i < N; ++i) {  // ascending bitmask within each irrep
+      const int a = irrep(all[i]);
+      S.sorted[S.off[a] + fill[a]] = all[i];
+      S.local[i] = fill[a]++;
+    }
+    return S;
+  };
+  const Spin A = make_spin(na), B = make_spin(nb);
+  T.Na = (int64_t)A.sorted.size();
+  T.Nb = (int64_t)B.sorted.size();
+  for (int a = 0; a < kIrreps; ++a) {
+    Y.na0[a] = A.off[a];
+    Y.nac[a] = A.cnt[a];
+    Y.nb0[a] = B.off[a];
+    Y.nbc[a] = B.cnt[a];
+  }
+  Y.blk[0] = 0;
+  for (int a = 0; a < kIrreps; ++a)
+    Y.blk[a + 1] = Y.blk[a] + (int64_t)Y.nac[a] * Y.nbc[a ^ wfn];
+  T.ndet = Y.blk[kIrreps];
+  // pairs class by class (ascending pair index within a class)
+  std::vector<int> pos_of(npair), pa(npair), pb(npair);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b <= a; ++b) {
+      pa[a * (a + 1) / 2 + b] = a;
+      pb[a * (a + 1) / 2 + b] = b;
+    }
+  int j = 0;
+  for (int cls = 0; cls < kIrreps; ++cls) {
+    Y.cls0[cls] = j;
+    for (int p = 0; p < npair; ++p)
+      if ((osym[pa[p]] ^ osym[pb[p]]) == cls) {
+        Y.pair_of[j] = p;
+        Y.cls_of[j] = (int8_t)cls;
+        pos_of[p] = j++;
+      }
+  }
+  Y.cls0[kIrreps] = j;
+  // G_s blocks: class s, alpha irrep a' of the irrep-G^s space
+  int64_t g = 0;
+  for (int cls = 0; cls < kIrreps; ++cls) {
+    const int nps = Y.cls0[cls + 1] - Y.cls0[cls];
+    for (int ap = 0; ap < kIrreps; ++ap) {
+      Y.gofs[cls][ap] = g;
+      g += (int64_t)Y.nac[ap] * nps * Y.nbc[ap ^ wfn ^ cls];
+    }
+  }
+  Y.gsize = g;
+  T.gsize = g;
+  // links and pair tables of one spin, in sorted string order
+  auto make_tables = [&](const Spin& S, int ne, std::vector<uint32_t>& link,
+                         std::vector<int32_t>& pair, bool pair_major) {
+    const int64_t N = (int64_t)S.sorted.size();
+    const int L = ne * (n - ne + 1);
+    link.assign(N * L, 0u);
+    pair.assign(N * npair, 0);
+    for (int64_t k = 0; k < N; ++k) {
+      const uint64_t m = S.sorted[k];
+      const int32_t self = S.local[addr(m)];
+      uint32_t* e = link.data() + k * L;
+      int idx = 0;
+      for (int o = 0; o < n; ++o)
+        if (m >> o & 1) e[idx++] = pack_link(self, pos_of[o * (o + 1) / 2 + o], 1);
+      for (int q = 0; q < n; ++q) {
+        if (!(m >> q & 1)) continue;
+        for (int p = 0; p < n; ++p) {
+          if (m >> p & 1) continue;
+          const uint64_t r = (m & ~((uint64_t)1 << q)) | ((uint64_t)1 << p);
+          const int lo = std::min(p, q), hi = std::max(p, q);
+          const uint64_t between = (((uint64_t)1 << hi) - 1) & ~((((uint64_t)1 << lo) << 1) - 1);
+          const int sg = (__builtin_popcountll(m & between) & 1) ? -1 : 1;
+          e[idx++] = pack_link(S.local[addr(r)], pos_of[pair_index(p, q)], sg);
+        }
+      }
+      for (int jj = 0; jj < npair; ++jj) {
+        const int p = Y.pair_of[jj], a = pa[p], b = pb[p];
+        int32_t v = 0;
+        const bool ia = m >> a & 1, ib = m >> b & 1;
+        if (a == b) {
+          if (ia) v = pack_pair_entry(self, 1);
+        } else if (ia != ib) {
+          const int q = ia ? a : b, pp = ia ? b : a;
+          const uint64_t r = (m & ~((uint64_t)1 << q)) | ((uint64_t)1 << pp);
+          const uint64_t between = (((uint64_t)1 << a) - 1) & ~((((uint64_t)1 << b) << 1) - 1);
+          const int sg = (__builtin_popcountll(m & between) & 1) ? -1 : 1;
+          v = pack_pair_entry(S.local[addr(r)], sg);
+        }
+        if (pair_major) pair[(int64_t)jj * N + k] = v;
+        else pair[k * npair + jj] = v;
+      }
+    }
+    return L;
+  };
+  std::vector<uint32_t> lA, lB;
+  std::vector<int32_t> pA, pB;
+  T.La = make_tables(A, na, lA, pA, false);
+  T.Lb = make_tables(B, nb, lB, pB, true);
+  // one device block: strings, links, pair tables, SymInfo (256-byte aligned parts)
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t o_sa = 0, o_sb = o_sa + al(8 * T.Na), o_la = o_sb + al(8 * T.Nb),
+               o_lb = o_la + al(4 * lA.size() + 4), o_pa = o_lb + al(4 * lB.size() + 4),
+               o_pb = o_pa + al(4 * pA.size() + 4), o_in = o_pb + al(4 * pB.size() + 4),
+               total = o_in + al(sizeof(SymInfo));
+  HIPCHK(hipMalloc(&T.block, total));
+  char* base = (char*)T.block;
+  T.strA = (uint64_t*)(base + o_sa);
+  T.strB = (uint64_t*)(base + o_sb);
+  T.linkA = (uint32_t*)(base + o_la);
+  T.linkB = (uint32_t*)(base + o_lb);
+  T.pairA = (int32_t*)(base + o_pa);
+  T.pairB = (int32_t*)(base + o_pb);
+  T.info = (SymInfo*)(base + o_in);
+  // synchronous copies: the host vectors end with this call
+  HIPCHK(hipMemcpy(T.strA, A.sorted.data(), 8 * T.Na, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(T.strB, B.sorted.data(), 8 * T.Nb, hipMemcpyHostToDevice));
+  if (!lA.empty()) HIPCHK(hipMemcpy(T.linkA, lA.data(), 4 * lA.size(), hipMemcpyHostToDevice));
+  if (!lB.empty()) HIPCHK(hipMemcpy(T.linkB, lB.data(), 4 * lB.size(), hipMemcpyHostToDevice));
+  if (!pA.empty()) HIPCHK(hipMemcpy(T.pairA, pA.data(), 4 * pA.size(), hipMemcpyHostToDevice));
+  if (!pB.empty()) HIPCHK(hipMemcpy(T.pairB, pB.data(), 4 * pB.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(T.info, &Y, sizeof(SymInfo), hipMemcpyHostToDevice));
+  return c->symtabs[key] = T;
+}
+
 int tile_for(mbefci_ctx* c, int n) {
   if (c->opts.tile == 32 || c->opts.tile == 64 || c->opts.tile == 128)
     return (n >= 13 && c->opts.tile == 128) ? 64 : c->opts.tile;
@@ -363,7 +579,7 @@ int64_t build_passes(mbefci_ctx* c, Plan& P) {
     };
     for (int i = 0; i < P.nitem; ++i) {
       Item& I = P.items[i];
-      if (I.ndet <= 1) continue;
+      if (I.ndet <= 1 || I.sym) continue;
       const int64_t gb = (int64_t)I.npair * I.Na * g_stride(I.Nb);
       if (gpass > 0 && (((gpass + 15) & ~(int64_t)15) + gb) * 8 > cap) close(i);
       gpass = (gpass + 15) & ~(int64_t)15;  // a 128-byte line
@@ -377,6 +593,77 @@ int64_t build_passes(mbefci_ctx* c, Plan& P) {
     }
     close(P.nitem);
     return gmax;
+  }
+}
+
+// Work of the point-group blocked items: per item, class s and alpha irrep
+// a', tiles of one alpha string x kSymTile beta strings (16 alpha strings per
+// unit, never crossing a beta block) in the group of the class's padded size;
+// gather blocks of 256 determinants; G blocks after the plain items' region
+// (`gtot` in, grown).
+void build_sym_work(Plan& P, int64_t& gtot) {
+  constexpr int TN = 32, TPW = 16;
+  P.sym_groups.clear();
+  P.sym_blocks.clear();
+  P.sym_blk_lo.assign(P.nitem, 0);
+  P.sym_blk_hi.assign(P.nitem, 0);
+  P.has_sym = false;
+  std::map<int, int> grp;
+  for (int i = 0; i < P.nitem; ++i) {
+    Item& I = P.items[i];
+    const SymTab* sy = (int)P.item_symtab.size() > i ? P.item_symtab[i] : nullptr;
+    if (!sy) continue;
+    P.has_sym = true;
+    P.sym_blk_lo[i] = (int)P.sym_blocks.size();
+    if (I.ndet <= 1) {
+      P.sym_blk_hi[i] = P.sym_blk_lo[i];
+      continue;
+    }
+    gtot = (gtot + 15) & ~(int64_t)15;
+    I.goff = gtot;
+    gtot += sy->gsize;
+    const SymInfo& Y = sy->host;
+    for (int cls = 0; cls < kIrreps; ++cls) {
+      const int nps = Y.cls0[cls + 1] - Y.cls0[cls];
+      if (nps == 0) continue;
+      const int npc = sym_npc(nps);
+      if (!grp.count(npc)) {
+        grp[npc] = (int)P.sym_groups.size();
+        Plan::SymGroup g;
+        g.npc = npc;
+        g.item_lo.assign(P.nitem, 0);
+        g.item_hi.assign(P.nitem, 0);
+        P.sym_groups.push_back(g);
+      }
+      (void)TN;
+    }
+    const int64_t nblk = (I.ndet + 255) / 256;
+    for (int64_t k = 0; k < nblk; ++k) P.sym_blocks.push_back(Work{i, (int32_t)k, (int32_t)k + 1, 0});
+    P.sym_blk_hi[i] = (int)P.sym_blocks.size();
+  }
+  // tiles item by item inside each group, so every item has one range per group
+  for (auto& g : P.sym_groups) {
+    for (int i = 0; i < P.nitem; ++i) {
+      const SymTab* sy = (int)P.item_symtab.size() > i ? P.item_symtab[i] : nullptr;
+      g.item_lo[i] = (int)g.tiles.size();
+      if (sy && P.items[i].ndet > 1) {
+        const SymInfo& Y = sy->host;
+        for (int cls = 0; cls < kIrreps; ++cls) {
+          const int nps = Y.cls0[cls + 1] - Y.cls0[cls];
+          if (nps == 0 || sym_npc(nps) != g.npc) continue;
+          for (int ap = 0; ap < kIrreps; ++ap) {
+            const int NA = Y.nac[ap], NB = Y.nbc[ap ^ Y.wfn ^ cls];
+            if (NA == 0 || NB == 0) continue;
+            const int nbk = (NB + TN - 1) / TN;
+            for (int bk = 0; bk < nbk; ++bk)
+              for (int a = 0; a < NA; a += TPW)
+                g.tiles.push_back(Work{i, bk * NA + a, bk * NA + std::min(a + TPW, NA),
+                                       cls * 8 + ap});
+          }
+        }
+      }
+      g.item_hi[i] = (int)g.tiles.size();
+    }
   }
 }
 
@@ -408,20 +695,40 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
     Item& I = P.items[i];
     if (I.n > 14) throw Error(MBEFCI_EUNSUPPORTED, "active space of " + std::to_string(I.n) +
                                                        " orbitals exceeds the compiled kernels (14)");
-    const StringTab& ta = string_tab(c, I.n, I.na);
-    const StringTab& tb = string_tab(c, I.n, I.nb);
-    I.Na = (int32_t)ta.N;
-    I.Nb = (int32_t)tb.N;
-    I.La = ta.L;
-    I.Lb = tb.L;
-    I.linkA = ta.link;
-    I.linkB = tb.link;
-    I.linkBT = tb.linkT;
-    I.strA = ta.str;
-    I.strB = tb.str;
-    I.pairA = ta.pair;
-    I.pairB = tb.pairT;
-    I.ndet = (int64_t)I.Na * I.Nb;
+    const SymTab* sy = (int)P.item_symtab.size() > i ? P.item_symtab[i] : nullptr;
+    if (sy) {
+      I.Na = (int32_t)sy->Na;
+      I.Nb = (int32_t)sy->Nb;
+      I.La = sy->La;
+      I.Lb = sy->Lb;
+      I.linkA = sy->linkA;
+      I.linkB = sy->linkB;
+      I.linkBT = nullptr;
+      I.strA = sy->strA;
+      I.strB = sy->strB;
+      I.pairA = sy->pairA;
+      I.pairB = sy->pairB;
+      I.sym = sy->info;
+      I.ndet = sy->ndet;
+      if (I.ndet < 1)
+        throw Error(MBEFCI_EINVAL, "no determinant of the requested irrep in a CASCI space");
+    } else {
+      const StringTab& ta = string_tab(c, I.n, I.na);
+      const StringTab& tb = string_tab(c, I.n, I.nb);
+      I.Na = (int32_t)ta.N;
+      I.Nb = (int32_t)tb.N;
+      I.La = ta.L;
+      I.Lb = tb.L;
+      I.linkA = ta.link;
+      I.linkB = tb.link;
+      I.linkBT = tb.linkT;
+      I.strA = ta.str;
+      I.strB = tb.str;
+      I.pairA = ta.pair;
+      I.pairB = tb.pairT;
+      I.sym = nullptr;
+      I.ndet = (int64_t)I.Na * I.Nb;
+    }
     I.npair = I.n * (I.n + 1) / 2;
     I.kpad = (I.npair + 15) / 16 * 16;
     I.off = off;
@@ -431,7 +738,7 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
     if (I.ndet > 1) {
       goff = (goff + 15) & ~(int64_t)15;  // a 128-byte line
       I.goff = goff;
-      goff += (int64_t)I.npair * I.Na * g_stride(I.Nb);
+      goff += sy ? sy->gsize : (int64_t)I.npair * I.Na * g_stride(I.Nb);
       I.woff = woff;
       woff += (int64_t)I.kpad * I.kpad;
     } else {
@@ -451,12 +758,12 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
     for (int k = 0; k < nbk; ++k) P.blocks.push_back(Work{i, k, k + 1, 0});
     P.block_hi[i] = (int)P.blocks.size();
     P.seg_lo[i] = (int)P.segs.size();
-    if (I.ndet > 1) {
+    if (I.ndet > 1 && !sy) {
       const int nsg = I.Na * ((I.Nb + 63) / 64);
       for (int b = 0; b * 4 < nsg; ++b) P.segs.push_back(Work{i, b, nsg, 0});
     }
     P.seg_hi[i] = (int)P.segs.size();
-    if (I.ndet > 1) {
+    if (I.ndet > 1 && !sy) {
       if (!group_of_n.count(I.n)) {
         group_of_n[I.n] = (int)P.groups.size();
         Group g;
@@ -472,6 +779,7 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
   }
   for (size_t gi = 0; gi < P.groups.size(); ++gi) build_tiles(P, (int)gi);
   goff = build_passes(c, P);
+  build_sym_work(P, goff);
   P.ntot = std::max<int64_t>(off, 64);
   P.gtot = goff;
   P.wtot = woff;
@@ -537,6 +845,15 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
   for (size_t g = 0; g < P.groups.size(); ++g)
     P.groups[g].d_tiles =
         arena<Work>(c, "tiles" + std::to_string(g), P.groups[g].tiles.size(), &grown);
+  for (size_t g = 0; g < P.sym_groups.size(); ++g) {
+    P.sym_groups[g].d_tiles = arena<Work>(c, "symtiles" + std::to_string(g),
+                                          std::max<size_t>(P.sym_groups[g].tiles.size(), 1), &grown);
+    upload(c, P.sym_groups[g].d_tiles, P.sym_groups[g].tiles);
+  }
+  if (P.has_sym) {
+    P.d_sym_blocks = arena<Work>(c, "symblocks", std::max<size_t>(P.sym_blocks.size(), 1), &grown);
+    upload(c, P.d_sym_blocks, P.sym_blocks);
+  }
   upload(c, P.d_items, P.items);
   upload(c, P.d_chunks, P.chunks);
   upload(c, P.d_blocks, P.blocks);
@@ -560,14 +877,31 @@ View single(const Plan& P, int i) {
 }
 
 // One launch of the sigma sweep: kind 0 = contraction of group `group`,
-// kind 1 = gather; work-list range [lo, lo + cnt).
+// kind 1 = gather, kind 2 = blocked contraction of sym group `group`, kind 3 =
+// blocked gather; work-list range [lo, lo + cnt).
 struct SigmaLaunch {
   int kind, group, lo, cnt;
 };
 
+void sym_launches(const Plan& P, int item, std::vector<SigmaLaunch>& out) {
+  for (size_t g = 0; g < P.sym_groups.size(); ++g) {
+    const auto& sg = P.sym_groups[g];
+    const int lo = item >= 0 ? sg.item_lo[item] : 0;
+    const int hi = item >= 0 ? sg.item_hi[item] : (int)sg.tiles.size();
+    if (hi > lo) out.push_back({2, (int)g, lo, hi - lo});
+  }
+  const int lo = item >= 0 ? P.sym_blk_lo[item] : 0;
+  const int hi = item >= 0 ? P.sym_blk_hi[item] : (int)P.sym_blocks.size();
+  if (hi > lo) out.push_back({3, -1, lo, hi - lo});
+}
+
 std::vector<SigmaLaunch> sigma_launches(const Plan& P, const View& v) {
   std::vector<SigmaLaunch> out;
   if (v.item >= 0) {
+    if (P.items[v.item].sym) {
+      sym_launches(P, v.item, out);
+      return out;
+    }
     const int g = P.item_group[v.item];
     if (g < 0) return out;
     out.push_back({0, g, P.groups[g].item_lo[v.item],
@@ -575,6 +909,7 @@ std::vector<SigmaLaunch> sigma_launches(const Plan& P, const View& v) {
     out.push_back({1, -1, v.seg_lo, v.nseg});
     return out;
   }
+  if (P.has_sym) sym_launches(P, -1, out);
   for (const Pass& ps : P.passes) {
     bool any = false;
     for (size_t g = 0; g < P.groups.size(); ++g)
@@ -593,9 +928,18 @@ void sigma_launch(mbefci_ctx* c, Plan& P, const SigmaLaunch& L, int slot) {
     if (!launch_sigma_dgemm(g.n, g.tn, P.d_items, g.d_tiles + L.lo, L.cnt, P.W, P.V, P.ntot, P.G,
                             P.st, slot, c->stream))
       throw Error(MBEFCI_EUNSUPPORTED, "no sigma kernel for n=" + std::to_string(g.n));
-  } else {
+  } else if (L.kind == 1) {
     launch_sigma_gather(P.d_items, P.d_segs + L.lo, L.cnt, P.G, P.S, P.ntot, P.st, slot,
                         c->stream);
+  } else if (L.kind == 2) {
+    const auto& sg = P.sym_groups[L.group];
+    if (!launch_sigma_sym_dgemm(sg.npc, P.d_items, sg.d_tiles + L.lo, L.cnt, P.W, P.V, P.ntot,
+                                P.G, P.st, slot, c->stream))
+      throw Error(MBEFCI_EUNSUPPORTED, "no blocked sigma kernel for " + std::to_string(sg.npc) +
+                                           " pairs in a class");
+  } else {
+    launch_sigma_sym_gather(P.d_items, P.d_sym_blocks + L.lo, L.cnt, P.G, P.S, P.ntot, P.st, slot,
+                            c->stream);
   }
 }
 
@@ -902,6 +1246,10 @@ void parse_problem(const mbefci_problem* pb, std::vector<int>& role, std::vector
   }
   if (pb->nref + pb->max_order > 14)
     throw Error(MBEFCI_EUNSUPPORTED, "|R| + max_order exceeds the compiled 14 active orbitals");
+  if (pb->orbsym)
+    for (int o = 0; o < M; ++o)
+      if (pb->orbsym[o] < 0 || pb->orbsym[o] >= kIrreps)
+        throw Error(MBEFCI_EINVAL, "orbital irreps must be in 0..7");
 }
 
 MbeSpaces make_spaces(int M, const std::vector<int>& role, const std::vector<int>& occ) {
@@ -953,10 +1301,19 @@ void check_shape(int n, int na, int nb) {
 }
 
 // Build a plan of `nprob` identical-shape CASCIs and fold their Hamiltonians.
+void check_orbsym(int n, const int32_t* orbsym, int wfn) {
+  if (wfn < 0 || wfn >= kIrreps) throw Error(MBEFCI_EINVAL, "target irrep must be in 0..7");
+  for (int t = 0; t < n; ++t)
+    if (orbsym[t] < 0 || orbsym[t] >= kIrreps)
+      throw Error(MBEFCI_EINVAL, "orbital irreps must be in 0..7");
+}
+
 void casci_plan(mbefci_ctx* c, int nprob, int n, int na, int nb, const double* const* h1s,
-                const double* const* eris, const double* ecore) {
+                const double* const* eris, const double* ecore, const int32_t* orbsym = nullptr,
+                int wfn = 0) {
   check_shape(n, na, nb);
   if (n > 14) throw Error(MBEFCI_EUNSUPPORTED, "active space exceeds 14 orbitals");
+  if (orbsym) check_orbsym(n, orbsym, wfn);
   if (c->plan && c->plan->graph) HIPCHK(hipGraphExecDestroy(c->plan->graph));
   c->plan.reset(new Plan());
   Plan& P = *c->plan;
@@ -966,6 +1323,10 @@ void casci_plan(mbefci_ctx* c, int nprob, int n, int na, int nb, const double* c
     I.na = na;
     I.nb = nb;
     P.items.push_back(I);
+  }
+  if (orbsym) {
+    std::vector<int> os(orbsym, orbsym + n);
+    P.item_symtab.assign(nprob, &sym_tab(c, n, na, nb, os.data(), wfn));
   }
   finalize_plan(c, P, c->opts.nguess);
   const double** d_h = arena<const double*>(c, "hptr", nprob);
@@ -991,6 +1352,8 @@ struct RdmOut {
 };
 
 RdmOut rdm_pass(mbefci_ctx* c, Plan& P) {
+  if (P.has_sym)
+    throw Error(MBEFCI_EUNSUPPORTED, "RDMs of point-group blocked CASCIs are not available");
   const int TN = 64;
   std::vector<std::vector<Work>> gwork(P.groups.size());
   std::vector<int32_t> wlo(P.nitem, 0), whi(P.nitem, 0);
@@ -1132,6 +1495,8 @@ void mbefci_destroy(mbefci_ctx* c) {
     if (kv.second.pair) (void)hipFree(kv.second.pair);
     if (kv.second.pairT) (void)hipFree(kv.second.pairT);
   }
+  for (auto& kv : c->symtabs)
+    if (kv.second.block) (void)hipFree(kv.second.block);
   for (auto& kv : c->bufs) release_buf(c, kv.second);
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_out) (void)hipEventDestroy(c->ev_out);
@@ -1372,7 +1737,8 @@ namespace {
 // copies the CI vectors to ci_out[i] when given (needs keep_ci).
 void casci_batch(mbefci_ctx* c, int32_t nprob, int32_t n, int32_t na, int32_t nb,
                  const double* const* h1s, const double* const* eris, const double* e_core,
-                 double* e_out, double* const* ci_out, mbefci_stats* stats) {
+                 double* e_out, double* const* ci_out, mbefci_stats* stats,
+                 const int32_t* orbsym = nullptr, int wfn = 0) {
   auto t_start = std::chrono::steady_clock::now();
   check_shape(n, na, nb);
   if (nprob < 1 || !h1s || !eris || !e_core || !e_out)
@@ -1385,7 +1751,7 @@ void casci_batch(mbefci_ctx* c, int32_t nprob, int32_t n, int32_t na, int32_t nb
     if (!h1s[i] || !eris[i]) throw Error(MBEFCI_EINVAL, "null integral pointer");
     check_integrals(c, n, h1s[i], eris[i]);
   }
-  casci_plan(c, nprob, n, na, nb, h1s, eris, e_core);
+  casci_plan(c, nprob, n, na, nb, h1s, eris, e_core, orbsym, wfn);
   Plan& P = *c->plan;
   mbefci_stats st{};
   solve_plan(c, P, &st);
@@ -1455,6 +1821,69 @@ int mbefci_casci_rdm(mbefci_ctx* c, double* const* rdm1s, double* const* rdm2s, 
   });
 }
 
+int64_t mbefci_sym_ndet(int32_t norb, int32_t nalpha, int32_t nbeta, const int32_t* orbsym,
+                        int32_t wfnsym) {
+  if (norb < 0 || norb > 64 || nalpha < 0 || nbeta < 0 || nalpha > norb || nbeta > norb ||
+      !orbsym || wfnsym < 0 || wfnsym >= kIrreps)
+    return MBEFCI_EINVAL;
+  for (int t = 0; t < norb; ++t)
+    if (orbsym[t] < 0 || orbsym[t] >= kIrreps) return MBEFCI_EINVAL;
+  // strings per irrep, by dynamic programming over the orbitals
+  auto count = [&](int ne, int64_t* out) {
+    std::vector<std::array<int64_t, kIrreps>> dp(ne + 1);
+    for (auto& r : dp) r.fill(0);
+    dp[0][0] = 1;
+    for (int t = 0; t < norb; ++t)
+      for (int k = std::min(ne, t + 1); k >= 1; --k)
+        for (int a = 0; a < kIrreps; ++a) dp[k][a ^ orbsym[t]] += dp[k - 1][a];
+    for (int a = 0; a < kIrreps; ++a) out[a] = dp[ne][a];
+  };
+  int64_t A[kIrreps], B[kIrreps];
+  count(nalpha, A);
+  count(nbeta, B);
+  int64_t nd = 0;
+  for (int a = 0; a < kIrreps; ++a) nd += A[a] * B[a ^ wfnsym];
+  return nd;
+}
+
+int mbefci_casci_sym(mbefci_ctx* c, int32_t nprob, int32_t n, int32_t na, int32_t nb,
+                     const int32_t* orbsym, int32_t wfnsym, const double* const* h1s,
+                     const double* const* eris, const double* e_core, double* e_out,
+                     double* const* ci_out, mbefci_stats* stats, void* stream) {
+  return guarded(c, [&] {
+    if (!orbsym) throw Error(MBEFCI_EINVAL, "null orbital irreps");
+    StreamScope sc(c, stream);
+    casci_batch(c, nprob, n, na, nb, h1s, eris, e_core, e_out, ci_out, stats, orbsym, wfnsym);
+    sc.done();
+  });
+}
+
+int mbefci_sigma_sym(mbefci_ctx* c, int32_t n, int32_t na, int32_t nb, const int32_t* orbsym,
+                     int32_t wfnsym, const double* h1, const double* eri, double e_core,
+                     const double* cvec, double* sig, void* stream) {
+  return guarded(c, [&] {
+    check_shape(n, na, nb);
+    if (!h1 || !eri || !cvec || !sig || !orbsym) throw Error(MBEFCI_EINVAL, "null pointer");
+    StreamScope sc(c, stream);
+    check_integrals(c, n, h1, eri);
+    casci_plan(c, 1, n, na, nb, &h1, &eri, &e_core, orbsym, wfnsym);
+    Plan& P = *c->plan;
+    const int64_t nd = P.items[0].ndet;
+    if (nd > 1) {
+      HIPCHK(hipMemcpyAsync(P.V, cvec, nd * 8, hipMemcpyDeviceToDevice, c->stream));
+      launch_state_single(P.st, c->stream);
+      sigma(c, P, whole(P), 0);
+      launch_axpy_out(sig, P.S, cvec, e_core, nd, c->stream);
+    } else {
+      launch_hdiag(P.d_items, P.d_blocks, P.nblock, P.hams, P.diag, c->stream);
+      launch_diag_times(sig, P.diag, cvec, e_core, 1, c->stream);
+    }
+    HIPCHK(hipGetLastError());
+    c->have_forward = false;
+    sc.done();
+  });
+}
+
 int mbefci_mbe_forward(mbefci_ctx* c, const mbefci_problem* pb, double* e_ref, double* e_order,
                        double* e_total, double* tuple_incr, double* tuple_energy,
                        mbefci_stats* stats, void* stream) {
@@ -1465,6 +1894,9 @@ int mbefci_mbe_forward(mbefci_ctx* c, const mbefci_problem* pb, double* e_ref, d
     const int M = pb->norb;
     std::vector<int> role, occ;
     parse_problem(pb, role, occ);
+    if (pb->orbsym)
+      throw Error(MBEFCI_EUNSUPPORTED, "orbital irreps: use mbefci_mbe_screened (t_init = 0 "
+                                       "gives the full expansion)");
     StreamScope sc(c, stream);
     check_integrals(c, M, pb->h1, pb->eri);
 
@@ -1727,6 +2159,17 @@ int mbefci_mbe_screened(mbefci_ctx* c, const mbefci_problem* pb, const mbefci_sc
           I.n = sp.nR + __builtin_popcountll(m);
           I.na = I.nb = sp.nocc_ref + __builtin_popcountll(m & occx);
           P.items.push_back(I);
+          if (pb->orbsym) {
+            // point-group blocked CASCI in the irrep of the closed-shell
+            // reference determinant (totally symmetric); active orbitals
+            // ascending, as the set-up kernel takes them
+            uint64_t a = m;
+            for (int r = 0; r < sp.nR; ++r) a |= (uint64_t)1 << sp.R[r];
+            int os[kMaxActive];
+            int t = 0;
+            for (uint64_t x = a; x; x &= x - 1) os[t++] = pb->orbsym[__builtin_ctzll(x)];
+            P.item_symtab.push_back(&sym_tab(c, I.n, I.na, I.nb, os, 0));
+          }
         }
         finalize_plan(c, P, c->opts.nguess);
         uint64_t* d_masks = arena<uint64_t>(c, "scr_items", masks.size());
@@ -1962,7 +2405,7 @@ int mbefci_time_kernels(mbefci_ctx* c, int32_t reps, mbefci_kernel_time* out, in
         bytes = 8.0 * (1.0 + np) * nd;  // c read once, G written once
         name = (g.tn < 0 ? "sigma_dgemm_flat<n=" : "sigma_dgemm<n=") + std::to_string(g.n) +
                ",tile=" + std::to_string(g.tn < 0 ? -g.tn : g.tn) + ">";
-      } else {
+      } else if (L.kind == 1) {
         for (int w = L.lo; w < L.lo + L.cnt; ++w)
           if (P.segs[w].begin == 0) {
             const Item& I = P.items[P.segs[w].item];
@@ -1970,6 +2413,32 @@ int mbefci_time_kernels(mbefci_ctx* c, int32_t reps, mbefci_kernel_time* out, in
             bytes += 8.0 * (I.npair + 1.0) * I.ndet;  // G read once, sigma written once
           }
         name = "sigma_gather";
+      } else if (L.kind == 2) {
+        // per work unit: its tiles' determinants of the class's irrep space
+        const auto& sg = P.sym_groups[L.group];
+        for (int w = L.lo; w < L.lo + L.cnt; ++w) {
+          const Work& wk = sg.tiles[w];
+          const SymInfo& Y = P.item_symtab[wk.item]->host;
+          const int cls = wk.pad_ >> 3, ap = wk.pad_ & 7;
+          const double nps = Y.cls0[cls + 1] - Y.cls0[cls];
+          const int NA = Y.nac[ap], NB = Y.nbc[ap ^ Y.wfn ^ cls];
+          const int bk = wk.begin / NA;
+          const double cols = std::min(32, NB - bk * 32);
+          const double d = (wk.end - wk.begin) * cols;
+          nd += d;
+          flops += 2.0 * nps * nps * d;
+          bytes += 8.0 * (1.0 + nps) * d;
+        }
+        name = "sigma_sym_dgemm<npc=" + std::to_string(sg.npc) + ">";
+      } else {
+        for (int w = L.lo; w < L.lo + L.cnt; ++w)
+          if (P.sym_blocks[w].begin == 0) {
+            const Item& I = P.items[P.sym_blocks[w].item];
+            const SymInfo& Y = P.item_symtab[P.sym_blocks[w].item]->host;
+            nd += (double)I.ndet;
+            bytes += 8.0 * ((double)Y.gsize + I.ndet);  // G read once, sigma written once
+          }
+        name = "sigma_sym_gather";
       }
       if (!agg.count(name)) {
         order.push_back(name);

@@ -91,6 +91,21 @@ def test_host_integer_layer_rejects_bad_shapes(lib):
     assert lib.mbefci_strings(64, 32, buf) == _lib.EINVAL  # more than 2^31 - 1 strings
 
 
+def test_sym_ndet_matches_oracle_sectors(lib):
+    """mbefci_sym_ndet (host, no context) against the oracle's sector sizes,
+    and the paper's Cr2 CASCI size (CAS(16,16), two orbitals per D2h irrep:
+    2.07e7 determinants, Fig. 3 discussion)."""
+    from oracle import sym
+    from paper_1910_03527_amd import sym_ndet
+    for n, na, nb, osym in [(6, 3, 3, [0, 1, 2, 3, 0, 1]), (7, 3, 4, [1, 4, 4, 7, 0, 2, 3]),
+                            (8, 4, 4, [0, 5, 3, 6, 0, 1, 7, 2]), (5, 0, 2, [3, 3, 1, 0, 6])]:
+        dims = sym.sector_dims(n, na, nb, osym)
+        assert [sym_ndet(n, na, nb, osym, g) for g in range(8)] == dims
+    assert sym_ndet(16, 8, 8, [p // 2 for p in range(16)], 0) == 20708900
+    bad = (ctypes.c_int32 * 4)(0, 1, 8, 0)
+    assert lib.mbefci_sym_ndet(4, 2, 2, bad, 0) == _lib.EINVAL
+
+
 def test_struct_layouts_match_header(tmp_path):
     """ctypes layouts equal the C compiler's layout of include/mbefci.h."""
     import shutil
