@@ -134,6 +134,72 @@ def test_hubbard12_gradient_finite_differences(ctx, hub12_grad):
         assert abs(an - fd) <= 1e-6 * abs(fd) + 1e-8, (an, fd)
 
 
+def _orbits(M):
+    """Unique elements of a symmetric M x M matrix and of an 8-fold symmetric
+    M^4 tensor, each with the index arrays of all its symmetric copies."""
+    hs = []
+    for p in range(M):
+        for q in range(p, M):
+            hs.append(sorted({(p, q), (q, p)}))
+    pairs = [(p, q) for p in range(M) for q in range(p, M)]
+    gs = []
+    for i, (p, q) in enumerate(pairs):
+        for (r, s) in pairs[i:]:
+            gs.append(sorted({(p, q, r, s), (q, p, r, s), (p, q, s, r), (q, p, s, r),
+                              (r, s, p, q), (s, r, p, q), (r, s, q, p), (s, r, q, p)}))
+    return hs, gs
+
+
+def test_hubbard12_gradient_fd_every_element(ctx, hub12_grad):
+    """Central differences (step 1e-5) along every unique element of h (78)
+    and of (pq|rs) (3,081 orbits of the 8-fold symmetry), each perturbed in all
+    its symmetric copies, against the analytic dL/d(element) summed over the
+    copies.  Per element: |an - fd| <= 1e-6 |fd| + 1e-7.  The floor is the FD
+    noise: L adds the energies of 2,510 CASCIs with alternating binomial
+    weights (Eq. 2), so its rounding is about 1e-12 E_h, and divided by the
+    step that is 1e-7; elements that vanish by the chain's reflection
+    symmetry show only that noise.  Over all elements the normwise relative
+    error must stay below 1e-6."""
+    _log("hubbard12 FD over every unique element")
+    p, gvec, dh, dg = hub12_grad
+    M = p.norb
+    step = 1e-5
+    h0 = _dev(p.h1)
+    g0 = _dev(p.eri)
+
+    def loss(h, g):
+        r = ctx.mbe_forward(h, g, p.occ, p.ref, p.exp, p.max_order, p.e_const)
+        return gvec[0] * r["e_ref"] + float(np.dot(gvec[1:], r["e_order"]))
+
+    hs, gs = _orbits(M)
+    assert len(hs) == 78 and len(gs) == 3081
+    an_all, fd_all = [], []
+    for kind, orbits, base, grad in (("h", hs, h0, dh), ("g", gs, g0, dg)):
+        for k, orbit in enumerate(orbits):
+            idx = tuple(torch.tensor(x, device="cuda") for x in zip(*orbit))
+            xp, xm = base.clone(), base.clone()
+            xp[idx] += step
+            xm[idx] -= step
+            if kind == "h":
+                fd = (loss(xp, g0) - loss(xm, g0)) / (2 * step)
+            else:
+                fd = (loss(h0, xp) - loss(h0, xm)) / (2 * step)
+            an = float(sum(grad[e] for e in orbit))
+            an_all.append(an)
+            fd_all.append(fd)
+            assert abs(an - fd) <= 1e-6 * abs(fd) + 1e-7, (kind, orbit[0], an, fd)
+            if kind == "g" and k % 1000 == 0:
+                _log("  orbit", k, "of", len(orbits))
+    an_all, fd_all = np.array(an_all), np.array(fd_all)
+    rel = np.linalg.norm(an_all - fd_all) / np.linalg.norm(fd_all)
+    big = np.abs(fd_all) > 1e-2
+    _log("  normwise relative error", rel, "; largest relative error of the",
+         int(big.sum()), "elements above 1e-2:",
+         float(np.max(np.abs(an_all - fd_all)[big] / np.abs(fd_all[big]))),
+         "; largest |an - fd| of the others:", float(np.max(np.abs(an_all - fd_all)[~big])))
+    assert rel < 1e-6
+
+
 def test_euler_identity(ctx, hub12_grad):
     """L is homogeneous of degree one in (h, g): <h, dL/dh> + <g, dL/dg> = L."""
     p, gvec, dh, dg = hub12_grad
