@@ -218,3 +218,25 @@ def test_blocked_sigma_cas14_equals_plain_sigma():
     err = float(np.max(np.abs(s_bl[pos] - s_full[idx])))
     _log("  max |blocked - plain|", err)
     assert err < 1e-12 * max(1.0, float(np.max(np.abs(s_full))))
+
+
+def test_blocked_cas14_lowest_irrep_equals_plain_energy():
+    """Full size: the lowest of the eight blocked CAS(14,14) energies equals
+    the plain solver's lowest eigenvalue of the same D2h-symmetric
+    Hamiltonian (the sectors partition the spectrum)."""
+    from paper_1910_03527_amd import Context, sym_ndet
+    p = W.problem("cas14_d2h", 0)
+    osym = p.orbsym
+    ctx = Context(0, conv_tol=1e-7)
+    try:
+        hd, gd = _dev(p.h1), _dev(p.eri)
+        e_plain = ctx.casci([hd], [gd], 7, 7)[0]
+        eg = []
+        for G in range(8):
+            if sym_ndet(14, 7, 7, osym, G) == 0:
+                continue
+            eg.append((ctx.casci_sym([hd], [gd], 7, 7, osym, G)[0], G))
+    finally:
+        ctx.close()
+    _log("  plain", e_plain, "blocked per irrep", eg)
+    assert abs(min(eg)[0] - e_plain) < 1e-9

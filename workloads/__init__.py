@@ -22,6 +22,9 @@ Workloads (all FP64, chemist-order integrals, 0-based orbital indices):
 * ``cas14``      -- 8 synthetic CAS(14e,14o) instances, M=14, seeds 1..8, the
   whole space active (11,778,624 determinants each: the size of the paper's
   largest Hubbard CASCI).
+* ``cas14_d2h``   -- 8 CAS(14e,14o) instances of the same size whose integrals
+  respect D2h (``synthetic_sym``, two orbitals per irrep 0..6, seeds
+  101..108), for the point-group blocked path.
 * ``hubbardN_pm`` (``hubbardN_pm_uU``) -- 1D Hubbard, N sites, open, t=1, U=2
   (or U), half filling, in Pipek-Mezey localised orbitals: the paper's Type-3
   lattice runs (22, 34 and 46 sites, U/t <= 3), empty reference space, every
@@ -281,6 +284,15 @@ def problem(name: str, instance: int = 0) -> Problem:
         h, g = synthetic(14, instance + 1)
         occ = list(range(7))
         return Problem(f"cas14[{instance}]", h, g, 0.0, occ, list(range(14)), [], 0)
+    if name == "cas14_d2h":
+        # the same size with D2h-symmetric integrals: two orbitals per irrep
+        # (irreps 0..6), seeds 101..108
+        if not 0 <= instance < 8:
+            raise ValueError("cas14_d2h has instances 0..7 (seeds 101..108)")
+        osym = [p // 2 for p in range(14)]
+        h, g = synthetic_sym(14, 101 + instance, osym)
+        return Problem(f"cas14_d2h[{instance}]", h, g, 0.0, list(range(7)), list(range(14)), [],
+                       0, orbsym=osym)
     pm = re.fullmatch(r"hubbard(\d+)_pm(?:_u(\d+(?:\.\d+)?))?", name)
     if pm:
         n = int(pm.group(1))
