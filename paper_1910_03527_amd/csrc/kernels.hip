@@ -846,24 +846,27 @@ __global__ void __launch_bounds__(256) k_sigma_gather(const Item* __restrict__ i
 // The contraction of one pair class s on the determinants of irrep G^s:
 // G_s = W_s D+_s on FP64 MFMA.  A work unit is (item, class s, alpha irrep
 // a' of the irrep-G^s space) and a range of tiles of that block; a tile is
-// one alpha string ka (local to irrep a') and kSymTile consecutive beta
-// strings of irrep b' = a'^G^s, numbered column-major (tile = block * nac[a']
-// + ka) so a unit stays inside one beta block.  D+ rows are the class's
-// pairs, zero-padded to NPC.  The alpha half of a D+ entry reads c in CI
-// block a'^s (beta irrep b', rows of nbc[b']), the beta half in block a'
-// (rows of nbc[a'^G]).  Work.pad_ = s * 8 + a'.
-constexpr int kSymTile = 32;
+// one alpha string ka (local to irrep a') and TN consecutive beta strings of
+// irrep b' = a'^G^s, numbered column-major (tile = block * nac[a'] + ka) so
+// a unit stays inside one beta block.  D+ rows are the class's pairs,
+// zero-padded to NPC.  The alpha half of a D+ entry reads c in CI block a'^s
+// (beta irrep b', rows of nbc[b']), the beta half in block a' (rows of
+// nbc[a'^G]).  Work.pad_ = s * 8 + a'.  Classes of up to 48 pairs take
+// 64-column tiles with one 16-column block per wave (every wave busy however
+// few row blocks the class has); larger ones 32-column tiles with row blocks
+// dealt over the waves.
+int sym_tile(int npc) { return npc <= 48 ? 64 : 32; }
 
-template <int NPC>
+template <int NPC, int TN>
 __global__ void __launch_bounds__(256) k_sigma_sym_dgemm(
     const Item* __restrict__ items, const Work* __restrict__ work,
     const double* __restrict__ warena, const double* __restrict__ V, int64_t ntot,
     double* __restrict__ Garena, const DavState* __restrict__ st, int slot) {
-  constexpr int TN = kSymTile;
   constexpr int KS = NPC / 4;       // MFMA k-steps
   constexpr int NRB = NPC / 16;     // 16-row blocks of G_s
-  constexpr int RBW = (NRB + 3) / 4;
   constexpr int NCB = TN / 16;
+  constexpr bool COL = NCB == 4;    // wave w computes column block w, every row block
+  constexpr int RBW = COL ? NRB : (NRB + 3) / 4;
   constexpr int LDT = TN + 1;
   __shared__ double Ds[NPC * LDT];
   __shared__ int32_t pl[NPC];       // class pair -> pair index (W row / column)
@@ -897,7 +900,7 @@ __global__ void __launch_bounds__(256) k_sigma_sym_dgemm(
   double wreg[RBW][KS];
 #pragma unroll
   for (int r = 0; r < RBW; ++r) {
-    const int rb = wrot + 4 * r;
+    const int rb = COL ? r : wrot + 4 * r;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int row = rb * 16 + (lane & 15), col = ks * 4 + (lane >> 4);
@@ -928,31 +931,57 @@ __global__ void __launch_bounds__(256) k_sigma_sym_dgemm(
       Ds[i * LDT + col] = v;
     }
     __syncthreads();
+    double* __restrict__ Grows = G_s + (int64_t)ka * nps * NB;
+    if constexpr (COL) {
+      // this wave: columns kb0 + 16 wave .. + 15, every row block
+      const double* bbase = Ds + (lane >> 4) * LDT + wave * 16 + (lane & 15);
+      double4_t acc[NRB];
 #pragma unroll
-    for (int r = 0; r < RBW; ++r) {
-      const int rb = wrot + 4 * r;
-      if (rb >= NRB) continue;
-      double4_t acc[NCB];
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) acc[cb] = (double4_t){0.0, 0.0, 0.0, 0.0};
-      const double* bbase = Ds + (lane >> 4) * LDT + (lane & 15);
+      for (int r = 0; r < NRB; ++r) acc[r] = (double4_t){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
+        const double bv = bbase[ks * 4 * LDT];
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(wreg[r][ks], bbase[ks * 4 * LDT + cb * 16],
-                                                         acc[cb], 0, 0, 0);
+        for (int r = 0; r < NRB; ++r)
+          acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(wreg[r][ks], bv, acc[r], 0, 0, 0);
       }
-      double* __restrict__ Grow = G_s + (int64_t)ka * nps * NB;
+      const int kc = kb0 + wave * 16 + (lane & 15);
+      if (kc < NB) {
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
-        const int kc = kb0 + cb * 16 + (lane & 15);
-        if (kc < NB) {
+        for (int r = 0; r < NRB; ++r)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             // register v of lane l: row l/16 + 4v, column l%16 of the block
-            const int row = rb * 16 + (lane >> 4) + 4 * v;
-            if (row < nps) Grow[(int64_t)row * NB + kc] = acc[cb][v];
+            const int row = r * 16 + (lane >> 4) + 4 * v;
+            if (row < nps) Grows[(int64_t)row * NB + kc] = acc[r][v];
+          }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < RBW; ++r) {
+        const int rb = wrot + 4 * r;
+        if (rb >= NRB) continue;
+        double4_t acc[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[cb] = (double4_t){0.0, 0.0, 0.0, 0.0};
+        const double* bbase = Ds + (lane >> 4) * LDT + (lane & 15);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+            acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(wreg[r][ks],
+                                                           bbase[ks * 4 * LDT + cb * 16], acc[cb],
+                                                           0, 0, 0);
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const int kc = kb0 + cb * 16 + (lane & 15);
+          if (kc < NB) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = rb * 16 + (lane >> 4) + 4 * v;
+              if (row < nps) Grows[(int64_t)row * NB + kc] = acc[cb][v];
+            }
           }
         }
       }
@@ -966,6 +995,8 @@ __global__ void __launch_bounds__(256) k_sigma_sym_dgemm(
 // (class-sorted pair j of class s, string Ja local to irrep a^s) reads G_s in
 // block a^s, row (Ja, j - cls0[s]), column ib; a beta link of ib (string Jb
 // local to irrep b^s) reads G_s in block a, row (ia, j - cls0[s]), column Jb.
+// The class tables are staged in LDS; beta links come from the link-major
+// table linkBT [Lb][Nb] (consecutive threads read consecutive entries).
 // Work units: 256 consecutive determinants of one item (Work.begin).
 __global__ void __launch_bounds__(256) k_sigma_sym_gather(const Item* __restrict__ items,
                                                           const Work* __restrict__ work,
@@ -974,40 +1005,49 @@ __global__ void __launch_bounds__(256) k_sigma_sym_gather(const Item* __restrict
                                                           int64_t ntot,
                                                           const DavState* __restrict__ st,
                                                           int slot) {
+  __shared__ int8_t cls_of[kMaxPair];
+  __shared__ int32_t cls0[kIrreps + 1];
+  __shared__ int32_t nbc[kIrreps];
+  __shared__ int64_t gofs[kIrreps][kIrreps];
   const Work wk = work[blockIdx.x];
   const Item& I = items[wk.item];
   const DavState& S = st[wk.item];
-  if (!item_active(S, slot)) return;
-  const int64_t K = (int64_t)wk.begin * blockDim.x + threadIdx.x;
-  if (K >= I.ndet) return;
+  if (!item_active(S, slot)) return;  // uniform over the block (one item)
   const SymInfo& Y = *I.sym;
+  const int t = threadIdx.x;
+  for (int j = t; j < Y.npair; j += 256) cls_of[j] = Y.cls_of[j];
+  if (t <= kIrreps) cls0[t] = Y.cls0[t];
+  if (t < kIrreps) nbc[t] = Y.nbc[t];
+  if (t < kIrreps * kIrreps) gofs[t >> 3][t & 7] = Y.gofs[t >> 3][t & 7];
+  __syncthreads();
+  const int64_t K = (int64_t)wk.begin * blockDim.x + t;
+  if (K >= I.ndet) return;
   const int vs = vec_slot(S, slot);
   const int G = Y.wfn;
   int a = 0;
   while (a < kIrreps - 1 && K >= Y.blk[a + 1]) ++a;
   const int b = a ^ G;
   const int64_t loc = K - Y.blk[a];
-  const int ia = (int)(loc / Y.nbc[b]), ib = (int)(loc % Y.nbc[b]);
+  const int ia = (int)(loc / nbc[b]), ib = (int)(loc % nbc[b]);
   const double* __restrict__ Gi = Garena + I.goff;
-  double acc = 0.0;
+  double acc0 = 0.0, acc1 = 0.0;
   const uint32_t* __restrict__ la = I.linkA + (int64_t)(Y.na0[a] + ia) * I.La;
   for (int l = 0; l < I.La; ++l) {
     const uint32_t e = ldg(la + l);
-    const int j = link_pair(e), s = Y.cls_of[j];
-    const int nps = Y.cls0[s + 1] - Y.cls0[s];
-    const int a2 = a ^ s;
-    acc += link_sign(e) * ldg(Gi + Y.gofs[s][a2] +
-                              ((int64_t)link_addr(e) * nps + (j - Y.cls0[s])) * Y.nbc[b] + ib);
+    const int j = link_pair(e), s = cls_of[j];
+    const int c0 = cls0[s], nps = cls0[s + 1] - c0;
+    acc0 += link_sign(e) * ldg(Gi + gofs[s][a ^ s] +
+                               ((int64_t)link_addr(e) * nps + (j - c0)) * nbc[b] + ib);
   }
-  const uint32_t* __restrict__ lb = I.linkB + (int64_t)(Y.nb0[b] + ib) * I.Lb;
+  const uint32_t* __restrict__ lb = I.linkBT + Y.nb0[b] + ib;  // link l: lb[l * Nb]
   for (int l = 0; l < I.Lb; ++l) {
-    const uint32_t e = ldg(lb + l);
-    const int j = link_pair(e), s = Y.cls_of[j];
-    const int nps = Y.cls0[s + 1] - Y.cls0[s];
-    acc += link_sign(e) * ldg(Gi + Y.gofs[s][a] +
-                              ((int64_t)ia * nps + (j - Y.cls0[s])) * Y.nbc[b ^ s] + link_addr(e));
+    const uint32_t e = ldg(lb + (int64_t)l * I.Nb);
+    const int j = link_pair(e), s = cls_of[j];
+    const int c0 = cls0[s], nps = cls0[s + 1] - c0;
+    acc1 += link_sign(e) * ldg(Gi + gofs[s][a] +
+                               ((int64_t)ia * nps + (j - c0)) * nbc[b ^ s] + link_addr(e));
   }
-  Sarena[(int64_t)vs * ntot + I.off + K] = acc;
+  Sarena[(int64_t)vs * ntot + I.off + K] = acc0 + acc1;
 }
 
 // ---------------------------------------------------------------- Davidson
@@ -3007,13 +3047,13 @@ bool launch_sigma_sym_dgemm(int npc, const Item* items, const Work* work, int nw
                             const DavState* st, int slot, hipStream_t s) {
   if (nwork <= 0) return true;
   switch (npc) {
-#define MBEFCI_CASE(P)                                                                        \
+#define MBEFCI_CASE(P, T)                                                                     \
   case P:                                                                                     \
-    hipLaunchKernelGGL((k_sigma_sym_dgemm<P>), dim3(nwork), dim3(256), 0, s, items, work,     \
+    hipLaunchKernelGGL((k_sigma_sym_dgemm<P, T>), dim3(nwork), dim3(256), 0, s, items, work,  \
                        warena, V, ntot, G, st, slot);                                         \
     return true;
-    MBEFCI_CASE(16) MBEFCI_CASE(32) MBEFCI_CASE(48) MBEFCI_CASE(64) MBEFCI_CASE(80)
-    MBEFCI_CASE(96) MBEFCI_CASE(112)
+    MBEFCI_CASE(16, 64) MBEFCI_CASE(32, 64) MBEFCI_CASE(48, 64) MBEFCI_CASE(64, 32)
+    MBEFCI_CASE(80, 32) MBEFCI_CASE(96, 32) MBEFCI_CASE(112, 32)
 #undef MBEFCI_CASE
     default: return false;
   }

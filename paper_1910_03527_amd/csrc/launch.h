@@ -33,6 +33,7 @@ void launch_sigma_gather(const Item* items, const Work* work, int nwork, const d
 // class and alpha irrep in Work.pad_ = s * 8 + a') and the gather (work units
 // of 256 consecutive determinants)
 int sym_npc(int npair_class);
+int sym_tile(int npc);  // beta strings per tile of the class's contraction
 bool launch_sigma_sym_dgemm(int npc, const Item* items, const Work* work, int nwork,
                             const double* warena, const double* V, int64_t ntot, double* G,
                             const DavState* st, int slot, hipStream_t s);

@@ -78,6 +78,7 @@ struct SymTab {
   uint64_t* strB = nullptr;
   uint32_t* linkA = nullptr;  // [Na][La]
   uint32_t* linkB = nullptr;  // [Nb][Lb]
+  uint32_t* linkBT = nullptr; // [Lb][Nb] (link-major: coalesced per-thread reads)
   int32_t* pairA = nullptr;   // [Na][npair]
   int32_t* pairB = nullptr;   // [npair][Nb]
   SymInfo* info = nullptr;    // device copy
@@ -456,12 +457,15 @@ const SymTab& sym_tab(mbefci_ctx* c, int n, int na, int nb, const int* osym, int
   std::vector<int32_t> pA, pB;
   T.La = make_tables(A, na, lA, pA, false);
   T.Lb = make_tables(B, nb, lB, pB, true);
+  std::vector<uint32_t> lBT(lB.size());
+  for (int64_t k = 0; k < T.Nb; ++k)
+    for (int l = 0; l < T.Lb; ++l) lBT[(int64_t)l * T.Nb + k] = lB[k * T.Lb + l];
   // one device block: strings, links, pair tables, SymInfo (256-byte aligned parts)
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t o_sa = 0, o_sb = o_sa + al(8 * T.Na), o_la = o_sb + al(8 * T.Nb),
                o_lb = o_la + al(4 * lA.size() + 4), o_pa = o_lb + al(4 * lB.size() + 4),
-               o_pb = o_pa + al(4 * pA.size() + 4), o_in = o_pb + al(4 * pB.size() + 4),
-               total = o_in + al(sizeof(SymInfo));
+               o_pb = o_pa + al(4 * pA.size() + 4), o_lt = o_pb + al(4 * pB.size() + 4),
+               o_in = o_lt + al(4 * lBT.size() + 4), total = o_in + al(sizeof(SymInfo));
   HIPCHK(hipMalloc(&T.block, total));
   char* base = (char*)T.block;
   T.strA = (uint64_t*)(base + o_sa);
@@ -470,6 +474,7 @@ const SymTab& sym_tab(mbefci_ctx* c, int n, int na, int nb, const int* osym, int
   T.linkB = (uint32_t*)(base + o_lb);
   T.pairA = (int32_t*)(base + o_pa);
   T.pairB = (int32_t*)(base + o_pb);
+  T.linkBT = (uint32_t*)(base + o_lt);
   T.info = (SymInfo*)(base + o_in);
   // synchronous copies: the host vectors end with this call
   HIPCHK(hipMemcpy(T.strA, A.sorted.data(), 8 * T.Na, hipMemcpyHostToDevice));
@@ -478,6 +483,8 @@ const SymTab& sym_tab(mbefci_ctx* c, int n, int na, int nb, const int* osym, int
   if (!lB.empty()) HIPCHK(hipMemcpy(T.linkB, lB.data(), 4 * lB.size(), hipMemcpyHostToDevice));
   if (!pA.empty()) HIPCHK(hipMemcpy(T.pairA, pA.data(), 4 * pA.size(), hipMemcpyHostToDevice));
   if (!pB.empty()) HIPCHK(hipMemcpy(T.pairB, pB.data(), 4 * pB.size(), hipMemcpyHostToDevice));
+  if (!lBT.empty())
+    HIPCHK(hipMemcpy(T.linkBT, lBT.data(), 4 * lBT.size(), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(T.info, &Y, sizeof(SymInfo), hipMemcpyHostToDevice));
   return c->symtabs[key] = T;
 }
@@ -602,7 +609,7 @@ int64_t build_passes(mbefci_ctx* c, Plan& P) {
 // gather blocks of 256 determinants; G blocks after the plain items' region
 // (`gtot` in, grown).
 void build_sym_work(Plan& P, int64_t& gtot) {
-  constexpr int TN = 32, TPW = 16;
+  constexpr int TPW = 16;
   P.sym_groups.clear();
   P.sym_blocks.clear();
   P.sym_blk_lo.assign(P.nitem, 0);
@@ -635,7 +642,6 @@ void build_sym_work(Plan& P, int64_t& gtot) {
         g.item_hi.assign(P.nitem, 0);
         P.sym_groups.push_back(g);
       }
-      (void)TN;
     }
     const int64_t nblk = (I.ndet + 255) / 256;
     for (int64_t k = 0; k < nblk; ++k) P.sym_blocks.push_back(Work{i, (int32_t)k, (int32_t)k + 1, 0});
@@ -654,6 +660,7 @@ void build_sym_work(Plan& P, int64_t& gtot) {
           for (int ap = 0; ap < kIrreps; ++ap) {
             const int NA = Y.nac[ap], NB = Y.nbc[ap ^ Y.wfn ^ cls];
             if (NA == 0 || NB == 0) continue;
+            const int TN = sym_tile(g.npc);
             const int nbk = (NB + TN - 1) / TN;
             for (int bk = 0; bk < nbk; ++bk)
               for (int a = 0; a < NA; a += TPW)
@@ -703,7 +710,7 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
       I.Lb = sy->Lb;
       I.linkA = sy->linkA;
       I.linkB = sy->linkB;
-      I.linkBT = nullptr;
+      I.linkBT = sy->linkBT;
       I.strA = sy->strA;
       I.strB = sy->strB;
       I.pairA = sy->pairA;
@@ -2422,8 +2429,9 @@ int mbefci_time_kernels(mbefci_ctx* c, int32_t reps, mbefci_kernel_time* out, in
           const int cls = wk.pad_ >> 3, ap = wk.pad_ & 7;
           const double nps = Y.cls0[cls + 1] - Y.cls0[cls];
           const int NA = Y.nac[ap], NB = Y.nbc[ap ^ Y.wfn ^ cls];
+          const int TN = sym_tile(sg.npc);
           const int bk = wk.begin / NA;
-          const double cols = std::min(32, NB - bk * 32);
+          const double cols = std::min(TN, NB - bk * TN);
           const double d = (wk.end - wk.begin) * cols;
           nd += d;
           flops += 2.0 * nps * nps * d;
