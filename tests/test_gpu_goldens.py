@@ -26,14 +26,12 @@ import numpy as np
 import pytest
 
 import workloads as W
+from golden_io import read_mbe_golden as read_golden
 from oracle import mbe
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
-
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-
 
 def _log(*a):
     print(*a, flush=True)
@@ -42,25 +40,6 @@ def _log(*a):
 
 def _dev(x):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
-
-
-def read_golden(name):
-    """(fingerprint, f_ref, {tuple: f}) from tests/golden/mbe_<name>.txt."""
-    fp = None
-    f_ref = None
-    f = {}
-    with open(os.path.join(GOLDEN, f"mbe_{name}.txt")) as fh:
-        for line in fh:
-            if line.startswith("# fingerprint"):
-                fp = [float(x) for x in line.split()[2:]]
-            if line.startswith("#") or not line.strip():
-                continue
-            key, val = line.split()
-            if key == "-":
-                f_ref = float(val)
-            else:
-                f[tuple(int(x) for x in key.split(","))] = float(val)
-    return fp, f_ref, f
 
 
 def _fingerprint(p):

@@ -204,7 +204,10 @@ def test_mbe_deterministic(ctx):
 def test_large_casci_batched_equals_per_launch():
     """CASCIs above 16,384 determinants select their P-space in chunks; in
     per-launch mode each CASCI is a view of its own.  Both modes give
-    bitwise the same energies (same kernels, same work per CASCI)."""
+    bitwise the same energies (same kernels, same work per CASCI), and both
+    CAS(12,12) energies equal the oracle's matrix-free Lanczos values of
+    tests/golden/casci_large.txt to 1e-9 E_h."""
+    from golden_io import read_large_goldens
     from paper_1910_03527_amd import Context, PER_LAUNCH
     probs = [W.synthetic(12, s) for s in (21, 22)]   # CAS(12e,12o): 853,776 determinants
     hs = [_dev(h) for h, _ in probs]
@@ -221,3 +224,6 @@ def test_large_casci_batched_equals_per_launch():
     finally:
         b.close()
     assert max(abs(x - y) for x, y in zip(ea, eb)) < 1e-10
+    golden = read_large_goldens()
+    for e, key in zip(ea, ("cas12_21", "cas12_22")):
+        assert abs(e - golden[key]) < 1e-9, (key, e, golden[key])

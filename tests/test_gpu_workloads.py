@@ -6,11 +6,13 @@ configuration bench.py times (needs an MI355X).
   tuple of every (order, occupied-count) bucket are solved by the oracle one
   by one; energies must agree to 1e-9 Eh.  The whole expansion must satisfy
   the order-sum identity against the reported increments.
-* 8 x CAS(14e,14o) (11,778,624 determinants each): too large for the oracle
-  to diagonalise, so each GPU eigenpair is checked row by row against the
-  oracle's Slater-Condon rows (sigma_I = E c_I on sampled determinants), and
-  the RDMs against the invariants tr gamma = N, sum_pr Gamma_pprr = N(N-1) and
-  E = sum h gamma + 1/2 sum g Gamma.
+* 8 x CAS(14e,14o) (11,778,624 determinants each): the energies of the
+  instances in ``tests/golden/casci_large.txt`` (the oracle's matrix-free
+  Slater-Condon Lanczos, ``make_casci_goldens.py``) to 1e-9 E_h; every GPU
+  eigenpair row by row against the oracle's Slater-Condon rows (sigma_I =
+  E c_I on sampled determinants), and the RDMs against the invariants
+  tr gamma = N, sum_pr Gamma_pprr = N(N-1) and E = sum h gamma + 1/2 sum g
+  Gamma.
 """
 import itertools
 import math
@@ -22,6 +24,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from golden_io import read_large_goldens
 from oracle import fci
 
 pytestmark = pytest.mark.gpu
@@ -106,6 +109,13 @@ def test_cas14_batch_eigenpairs_and_rdms():
         g2 = g2.cpu().numpy()
     finally:
         ctx.close()
+    golden = read_large_goldens()
+    for i in range(8):
+        key = f"cas14_{i}"
+        if key in golden:
+            _log("  instance", i, "GPU", e[i], "oracle", golden[key])
+            assert abs(e[i] - golden[key]) < 1e-9, (i, e[i], golden[key])
+    assert "cas14_0" in golden
     a = fci.string_masks(range(14), 7)
     rng = np.random.default_rng(7)
     for i, p in enumerate(probs):
