@@ -842,6 +842,48 @@ __global__ void __launch_bounds__(256) k_sigma_gather(const Item* __restrict__ i
   Sarena[(int64_t)vs * ntot + I.off + (int64_t)Ka * Nb + Kb] = acc0 + acc1;
 }
 
+// ------------------------------------------------------ input validation
+// Finiteness and permutational symmetry of the MO integrals, on the device
+// (no host copy of the M^4 tensor): each element is compared with its
+// partners h_qp, and (qp|rs), (pq|sr), (rs|pq), to 1e-12 times the larger of
+// 1 and the two magnitudes.  Bits of *flags (integer atomics): 1 h not finite,
+// 2 h not symmetric, 4 eri not finite, 8 eri lacks the 8-fold symmetry.
+__global__ void k_check_integrals(const double* __restrict__ h1, const double* __restrict__ eri,
+                                  int M, int* flags) {
+  const int64_t n1 = (int64_t)M * M, n2 = n1 * n1;
+  int f = 0;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n1 + n2;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    auto close = [](double a, double b) {
+      const double sc = fmax(1.0, fmax(fabs(a), fabs(b)));
+      return fabs(a - b) <= 1e-12 * sc;
+    };
+    if (x < n1) {
+      const int p = (int)(x / M), q = (int)(x % M);
+      const double a = h1[x];
+      if (!isfinite(a)) f |= 1;
+      else if (!close(a, h1[(int64_t)q * M + p])) f |= 2;
+    } else {
+      const int64_t y = x - n1;
+      const int s = (int)(y % M), r = (int)(y / M % M), q = (int)(y / n1 % M), p = (int)(y / n1 / M);
+      const double a = eri[y];
+      auto at = [&](int i, int j, int k, int l) { return eri[(((int64_t)i * M + j) * M + k) * M + l]; };
+      if (!isfinite(a)) f |= 4;
+      else if (!close(a, at(q, p, r, s)) || !close(a, at(p, q, s, r)) || !close(a, at(r, s, p, q)))
+        f |= 8;
+    }
+  }
+  if (f) atomicOr(flags, f);
+}
+
+void launch_check_integrals(const double* h1, const double* eri, int M, int* flags,
+                            hipStream_t s) {
+  const int64_t n = (int64_t)M * M * (1 + (int64_t)M * M);
+  int64_t b = (n + 255) / 256;
+  if (b > 4096) b = 4096;
+  hipLaunchKernelGGL(k_check_integrals, dim3((int)b), dim3(256), 0, s, h1, eri, M, flags);
+}
+
 // ------------------------------------------------- point-group blocked sigma
 // The contraction of one pair class s on the determinants of irrep G^s:
 // G_s = W_s D+_s on FP64 MFMA.  A work unit is (item, class s, alpha irrep

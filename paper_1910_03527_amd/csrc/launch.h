@@ -40,6 +40,10 @@ bool launch_sigma_sym_dgemm(int npc, const Item* items, const Work* work, int nw
 void launch_sigma_sym_gather(const Item* items, const Work* work, int nwork, const double* G,
                              double* Sv, int64_t ntot, const DavState* st, int slot,
                              hipStream_t s);
+// finiteness and 8-fold symmetry of h1 [M*M], eri [M^4]: bits of *flags
+// (which must be zero beforehand) as documented at the kernel
+void launch_check_integrals(const double* h1, const double* eri, int M, int* flags,
+                            hipStream_t s);
 void launch_fill(double* p, int64_t n, double v, hipStream_t s);
 // peak probes: FP64 MFMA chains (256-thread blocks; flops of one launch from
 // probe_mfma_flops) and a copy of n doubles (n even, 16-byte aligned)

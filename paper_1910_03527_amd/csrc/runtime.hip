@@ -1175,37 +1175,22 @@ void solve_plan(mbefci_ctx* c, Plan& P, mbefci_stats* stats) {
 }
 
 // ------------------------------------------------------------ validation
+// Validate the MO integrals on the device (finite, h symmetric, (pq|rs)
+// 8-fold symmetric to 1e-12 relative); the flags word is read back before
+// anything is solved.
 void check_integrals(mbefci_ctx* c, int M, const double* h1, const double* eri) {
   if (!c->opts.validate) return;
-  const size_t n1 = (size_t)M * M, n2 = n1 * n1;
-  std::vector<double> h(n1), g(n2);
-  HIPCHK(hipMemcpyAsync(h.data(), h1, n1 * 8, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipMemcpyAsync(g.data(), eri, n2 * 8, hipMemcpyDeviceToHost, c->stream));
+  int* d_flags = arena<int>(c, "check_flags", 1);
+  HIPCHK(hipMemsetAsync(d_flags, 0, sizeof(int), c->stream));
+  launch_check_integrals(h1, eri, M, d_flags, c->stream);
+  HIPCHK(hipGetLastError());
+  int flags = 0;
+  HIPCHK(hipMemcpyAsync(&flags, d_flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  double scale = 0.0;
-  for (double x : h) {
-    if (!std::isfinite(x)) throw Error(MBEFCI_EINVAL, "h1 holds a non-finite value");
-    scale = std::max(scale, std::fabs(x));
-  }
-  for (double x : g) {
-    if (!std::isfinite(x)) throw Error(MBEFCI_EINVAL, "eri holds a non-finite value");
-    scale = std::max(scale, std::fabs(x));
-  }
-  const double tol = 1e-12 * std::max(1.0, scale);
-  for (int p = 0; p < M; ++p)
-    for (int q = 0; q < M; ++q)
-      if (std::fabs(h[p * M + q] - h[q * M + p]) > tol)
-        throw Error(MBEFCI_EINVAL, "h1 is not symmetric");
-  auto G = [&](int p, int q, int r, int s) { return g[(((size_t)p * M + q) * M + r) * M + s]; };
-  for (int p = 0; p < M; ++p)
-    for (int q = 0; q < M; ++q)
-      for (int r = 0; r < M; ++r)
-        for (int s = 0; s < M; ++s) {
-          double v = G(p, q, r, s);
-          if (std::fabs(v - G(q, p, r, s)) > tol || std::fabs(v - G(p, q, s, r)) > tol ||
-              std::fabs(v - G(r, s, p, q)) > tol)
-            throw Error(MBEFCI_EINVAL, "eri lacks the 8-fold permutational symmetry");
-        }
+  if (flags & 1) throw Error(MBEFCI_EINVAL, "h1 holds a non-finite value");
+  if (flags & 4) throw Error(MBEFCI_EINVAL, "eri holds a non-finite value");
+  if (flags & 2) throw Error(MBEFCI_EINVAL, "h1 is not symmetric");
+  if (flags & 8) throw Error(MBEFCI_EINVAL, "eri lacks the 8-fold permutational symmetry");
 }
 
 struct StreamScope {  // order the library stream after the caller's and back

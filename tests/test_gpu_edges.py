@@ -102,6 +102,10 @@ def _bad_problems():
     hn[0, 1] += 1e-6                      # not symmetric
     gn = g.copy()
     gn[1, 2, 3, 4] = np.nan               # not finite
+    ga = g.copy()
+    ga[0, 1, 2, 3] += 1e-6                # one element without its 8-fold partners
+    hi = h1.copy()
+    hi[2, 2] = np.inf                     # not finite
     big = list(range(8))
     return [
         ("overlap", (h1, g, occ, [0, 1], [1, 2, 3], 2), "EINVAL"),
@@ -110,6 +114,8 @@ def _bad_problems():
         ("dup_occ", (h1, g, [0, 0, 1], [], [2, 3], 1), "EINVAL"),
         ("asym_h", (hn, g, occ, [], big, 2), "EINVAL"),
         ("nan_eri", (h1, gn, occ, [], big, 2), "EINVAL"),
+        ("asym_eri", (h1, ga, occ, [], big, 2), "EINVAL"),
+        ("inf_h", (hi, g, occ, [], big, 2), "EINVAL"),
     ]
 
 
