@@ -135,8 +135,6 @@ hipError_t noalloc_init(int device) {
   return hipSuccess;
 }
 
-size_t noalloc_capacity() { return kScratchBytes; }
-
 // sigma = H c (e_core included) of the CASCI (n, na, nb) with active-space
 // integrals h1 [n*n] and eri [n^4] (device), c and sigma device [Na*Nb], on
 // stream s of `device` (current).  Returns MBEFCI_OK, or an error code with
