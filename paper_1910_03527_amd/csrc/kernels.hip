@@ -385,9 +385,15 @@ constexpr int64_t binom_c(int n, int k) {
 // With 32-column tiles of up to 10 orbitals the pair-table entries stay in
 // registers and the kernel is compiled for four waves per SIMD (128 registers
 // per lane, accumulators included), which those shapes reach without
-// spilling; larger shapes take the registers they need.
-template <int NACT, int TN>
-__global__ void __launch_bounds__(256, (TN == 32 && NACT <= 10) ? 4 : 1) k_sigma_dgemm(
+// spilling; larger shapes take the registers they need.  Active spaces of
+// 11 or more orbitals run larger workgroups, since their LDS holds one or two
+// workgroups per CU: 512 threads (two waves per SIMD) for 11-12 orbitals,
+// 1024 (four per SIMD) for 13-14, where waves split a tile's output blocks
+// by row block and column half.
+constexpr int dgemm_threads(int nact) { return nact >= 13 ? 1024 : nact >= 11 ? 512 : 256; }
+
+template <int NACT, int TN, int NT = dgemm_threads(NACT)>
+__global__ void __launch_bounds__(NT, (NT == 256 && TN == 32 && NACT <= 10) ? 4 : 1) k_sigma_dgemm(
     const Item* __restrict__ items, const Work* __restrict__ work,
     const double* __restrict__ warena, const double* __restrict__ V, int64_t ntot,
     double* __restrict__ Garena, const DavState* __restrict__ st, int slot) {
@@ -396,15 +402,19 @@ __global__ void __launch_bounds__(256, (TN == 32 && NACT <= 10) ? 4 : 1) k_sigma
   constexpr int KS = (NP + 3) / 4;       // MFMA k-steps (4 pair rows per step)
   constexpr int KR = KS * 4;             // D+ rows held in LDS (zero beyond NP)
   constexpr int NRB = KPAD / 16;         // 16-row blocks of G
-  constexpr int RBW = (NRB + 3) / 4;     // row blocks per wave
+  constexpr int NW = NT / 64;            // waves per workgroup
   constexpr int NCB = TN / 16;           // 16-column blocks per tile
-  constexpr int NSUB = 256 / TN;         // row groups of the gather
+  constexpr int NCG = (NW >= 16 && NCB % 2 == 0) ? 2 : 1;  // column groups of waves
+  constexpr int NRG = NW / NCG;          // row groups of waves
+  constexpr int NCBW = NCB / NCG;        // column blocks per wave
+  constexpr int RBW = (NRB + NRG - 1) / NRG;  // row blocks per wave
+  constexpr int NSUB = NT / TN;          // row groups of the D+ build
   constexpr int NPER = (NP + NSUB - 1) / NSUB;
   constexpr int LDT = TN + 1;            // padded LDS row (doubles)
   constexpr int CMAX = (int)binom_c(NACT, NACT / 2);  // largest string count for NACT
-  constexpr int CPT = (CMAX + 255) / 256;             // c-row doubles per thread
-  constexpr int TPT = (NP * TN + 255) / 256;          // beta-table entries per thread
-  constexpr bool EREG = TN == 32 && NACT <= 10;  // the launch-bounds rule
+  constexpr int CPT = (CMAX + NT - 1) / NT;           // c-row doubles per thread
+  constexpr int TPT = (NP * TN + NT - 1) / NT;        // beta-table entries per thread
+  constexpr bool EREG = NT == 256 && TN == 32 && NACT <= 10;  // the launch-bounds rule
   __shared__ double Ds[KR * LDT];
   __shared__ int32_t Tb[EREG ? 1 : NP * TN];
   __shared__ double Cr[CMAX];
@@ -431,24 +441,26 @@ __global__ void __launch_bounds__(256, (TN == 32 && NACT <= 10) ? 4 : 1) k_sigma
   const int Kbc = Kb < Nb ? Kb : Nb - 1;
   const double* __restrict__ ca = c + Kbc;  // alpha source of D+: ca[Ja * Nb]
 
-  // Row blocks rb = wrot + 4r of this wave.  When the 16-row blocks of G do
-  // not come in multiples of four some waves have one block fewer; rotating
-  // the assignment by workgroup spreads those idle slots over the SIMDs.
-  const int wrot = (wave + (int)blockIdx.x) & 3;
+  // Row blocks rb = wrot + NRG r and column blocks cg NCBW .. of this wave.
+  // When the 16-row blocks of G do not come in multiples of NRG some waves
+  // have one block fewer; rotating the assignment by workgroup spreads those
+  // idle slots over the SIMDs.
+  const int cg = NCG == 1 ? 0 : wave / NRG;
+  const int wrot = ((NCG == 1 ? wave : wave % NRG) + (int)blockIdx.x) % NRG;
   // W rows of this wave's row blocks, as MFMA A operands: lane l holds
   // W[rb*16 + l%16][ks*4 + l/16] (B operand: lane l holds D+[ks*4 + l/16][l%16])
   double wreg[RBW][KS];
   const double* __restrict__ W = warena + I.woff;
 #pragma unroll
   for (int r = 0; r < RBW; ++r) {
-    const int rb = wrot + 4 * r;
+    const int rb = wrot + NRG * r;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
       wreg[r][ks] = (rb < NRB) ? ldg(W + (rb * 16 + (lane & 15)) * KPAD + ks * 4 + (lane >> 4))
                                : 0.0;
   }
   // This thread's beta pair-table entries: slot i is pair sub + NSUB i of
-  // column col (x = t + 256 i has x / TN = sub + NSUB i and x % TN = col),
+  // column col (x = t + NT i has x / TN = sub + NSUB i and x % TN = col),
   // the slots it writes in every tile's D+.  Then the zero padding rows of D+.
   static_assert(TPT == NPER, "one pair-table entry per D+ slot of a thread");
   int32_t eb[NPER];
@@ -460,9 +472,9 @@ __global__ void __launch_bounds__(256, (TN == 32 && NACT <= 10) ? 4 : 1) k_sigma
   if constexpr (!EREG) {
 #pragma unroll
     for (int i = 0; i < NPER; ++i)
-      if (sub + NSUB * i < NP) Tb[t + 256 * i] = eb[i];
+      if (sub + NSUB * i < NP) Tb[t + NT * i] = eb[i];
   }
-  for (int x = NP * LDT + t; x < KR * LDT; x += 256) Ds[x] = 0.0;
+  for (int x = NP * LDT + t; x < KR * LDT; x += NT) Ds[x] = 0.0;
 
   // Software pipeline over the tiles of the work unit: the alpha pair-table
   // entries of tile i+1 are loaded while tile i builds D+, and the c row and
@@ -494,7 +506,7 @@ __global__ void __launch_bounds__(256, (TN == 32 && NACT <= 10) ? 4 : 1) k_sigma
     for (int i = 0; i < NPER; ++i) ga[i] = ea[i] ? ldg(ca + ((ea[i] >> 1) - 1) * Nb) : 0.0;
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
-      const int x = t + 256 * j;
+      const int x = t + NT * j;
       cr[j] = x < Nb ? ldg(c + ka * Nb + x) : 0.0;
     }
   };
@@ -506,7 +518,7 @@ __global__ void __launch_bounds__(256, (TN == 32 && NACT <= 10) ? 4 : 1) k_sigma
     const bool more = tile + 1 < wk.end;
 #pragma unroll
     for (int j = 0; j < CPT; ++j)
-      if (t + 256 * j < Nb) Cr[t + 256 * j] = cr[j];
+      if (t + NT * j < Nb) Cr[t + NT * j] = cr[j];
     int32_t en[NPER];
     if (more) {
       load_entries(Ka + 1, en);
@@ -521,7 +533,7 @@ __global__ void __launch_bounds__(256, (TN == 32 && NACT <= 10) ? 4 : 1) k_sigma
       if (ab < NP) {
         int32_t e;
         if constexpr (EREG) e = eb[i];
-        else e = Tb[t + 256 * i];
+        else e = Tb[t + NT * i];
         const int jb = e ? (e >> 1) - 1 : 0;
         const double fa = ea[i] ? ((ea[i] & 1) ? -keep : keep) : 0.0;
         const double fb = e ? ((e & 1) ? -keep : keep) : 0.0;
@@ -536,43 +548,43 @@ __global__ void __launch_bounds__(256, (TN == 32 && NACT <= 10) ? 4 : 1) k_sigma
     }
 #pragma unroll
     for (int r = 0; r < RBW; ++r) {
-      const int rb = wrot + 4 * r;
+      const int rb = wrot + NRG * r;
       if (rb >= NRB) continue;
-      double4_t acc[NCB];
+      double4_t acc[NCBW];
 #pragma unroll
-      for (int cb2 = 0; cb2 < NCB; ++cb2) acc[cb2] = (double4_t){0.0, 0.0, 0.0, 0.0};
+      for (int cb2 = 0; cb2 < NCBW; ++cb2) acc[cb2] = (double4_t){0.0, 0.0, 0.0, 0.0};
       // B operands double-buffered in registers: the LDS reads of k-step
       // ks+1 are issued before the MFMAs of k-step ks
-      double bq[2][NCB];
-      const double* bbase = Ds + (lane >> 4) * LDT + (lane & 15);
+      double bq[2][NCBW];
+      const double* bbase = Ds + (lane >> 4) * LDT + cg * NCBW * 16 + (lane & 15);
 #pragma unroll
-      for (int cb2 = 0; cb2 < NCB; ++cb2) bq[0][cb2] = bbase[cb2 * 16];
+      for (int cb2 = 0; cb2 < NCBW; ++cb2) bq[0][cb2] = bbase[cb2 * 16];
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         if (ks + 1 < KS) {
 #pragma unroll
-          for (int cb2 = 0; cb2 < NCB; ++cb2)
+          for (int cb2 = 0; cb2 < NCBW; ++cb2)
             bq[(ks + 1) & 1][cb2] = bbase[(ks + 1) * 4 * LDT + cb2 * 16];
         }
 #pragma unroll
-        for (int cb2 = 0; cb2 < NCB; ++cb2)
+        for (int cb2 = 0; cb2 < NCBW; ++cb2)
           acc[cb2] = __builtin_amdgcn_mfma_f64_16x16x4f64(wreg[r][ks], bq[ks & 1][cb2], acc[cb2],
                                                           0, 0, 0);
       }
       // instruction order for the scheduler: the first B reads, then per
       // k-step the next step's B reads (0x100: LDS read) ahead of this
       // step's MFMAs (0x008)
-      __builtin_amdgcn_sched_group_barrier(0x100, NCB, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, NCBW, 0);
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        if (ks + 1 < KS) __builtin_amdgcn_sched_group_barrier(0x100, NCB, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, NCB, 0);
+        if (ks + 1 < KS) __builtin_amdgcn_sched_group_barrier(0x100, NCBW, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, NCBW, 0);
       }
       const int Gs = g_stride(Nb);  // row stride of G
       double* __restrict__ Grow = G + (int64_t)Ka * NP * Gs;
 #pragma unroll
-      for (int cb2 = 0; cb2 < NCB; ++cb2) {
-        const int Kc = Kb0 + cb2 * 16 + (lane & 15);
+      for (int cb2 = 0; cb2 < NCBW; ++cb2) {
+        const int Kc = Kb0 + (cg * NCBW + cb2) * 16 + (lane & 15);
         if (Kc < Gs) {  // the row's padding too (zero: D+ is zero there), whole lines
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
@@ -3024,8 +3036,8 @@ template <int NACT, int TN>
 static void sigma_dgemm_t(const Item* items, const Work* work, int nwork, const double* warena,
                           const double* V, int64_t ntot, double* G, const DavState* st, int slot,
                           hipStream_t s) {
-  hipLaunchKernelGGL((k_sigma_dgemm<NACT, TN>), dim3(nwork), dim3(256), 0, s, items, work, warena,
-                     V, ntot, G, st, slot);
+  hipLaunchKernelGGL((k_sigma_dgemm<NACT, TN>), dim3(nwork), dim3(dgemm_threads(NACT)), 0, s, items,
+                     work, warena, V, ntot, G, st, slot);
 }
 
 template <int TN>
