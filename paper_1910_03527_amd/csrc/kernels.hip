@@ -390,10 +390,18 @@ constexpr int64_t binom_c(int n, int k) {
 // workgroups per CU: 512 threads (two waves per SIMD) for 11-12 orbitals,
 // 1024 (four per SIMD) for 13-14, where waves split a tile's output blocks
 // by row block and column half.
-constexpr int dgemm_threads(int nact) { return nact >= 13 ? 1024 : nact >= 11 ? 512 : 256; }
+// Active spaces of 8 or 9 orbitals have three 16-row blocks of G (36 or 45
+// pairs padded to 48): their workgroups have three waves, one row block
+// each, so that every wave of the CU issues MFMAs.
+constexpr int dgemm_threads(int nact) {
+  return nact >= 13 ? 1024 : nact >= 11 ? 512 : (nact == 8 || nact == 9) ? 192 : 256;
+}
+constexpr bool dgemm_reg_entries(int nact, int tn, int nt) {
+  return (nt == 256 || nt == 192) && tn == 32 && nact <= 10;
+}
 
 template <int NACT, int TN, int NT = dgemm_threads(NACT)>
-__global__ void __launch_bounds__(NT, (NT == 256 && TN == 32 && NACT <= 10) ? 4 : 1) k_sigma_dgemm(
+__global__ void __launch_bounds__(NT, dgemm_reg_entries(NACT, TN, NT) ? 4 : 1) k_sigma_dgemm(
     const Item* __restrict__ items, const Work* __restrict__ work,
     const double* __restrict__ warena, const double* __restrict__ V, int64_t ntot,
     double* __restrict__ Garena, const DavState* __restrict__ st, int slot) {
@@ -414,7 +422,7 @@ __global__ void __launch_bounds__(NT, (NT == 256 && TN == 32 && NACT <= 10) ? 4 
   constexpr int CMAX = (int)binom_c(NACT, NACT / 2);  // largest string count for NACT
   constexpr int CPT = (CMAX + NT - 1) / NT;           // c-row doubles per thread
   constexpr int TPT = (NP * TN + NT - 1) / NT;        // beta-table entries per thread
-  constexpr bool EREG = NT == 256 && TN == 32 && NACT <= 10;  // the launch-bounds rule
+  constexpr bool EREG = dgemm_reg_entries(NACT, TN, NT);  // the launch-bounds rule
   __shared__ double Ds[KR * LDT];
   __shared__ int32_t Tb[EREG ? 1 : NP * TN];
   __shared__ double Cr[CMAX];
@@ -3048,8 +3056,14 @@ static bool sigma_dgemm_n(int n, const Item* items, const Work* work, int nwork,
 #define MBEFCI_CASE(N) \
   case N: sigma_dgemm_t<N, TN>(items, work, nwork, warena, V, ntot, G, st, slot, s); return true;
     MBEFCI_CASE(2) MBEFCI_CASE(3) MBEFCI_CASE(4) MBEFCI_CASE(5) MBEFCI_CASE(6) MBEFCI_CASE(7)
-    MBEFCI_CASE(8) MBEFCI_CASE(9) MBEFCI_CASE(10) MBEFCI_CASE(11) MBEFCI_CASE(12)
+    MBEFCI_CASE(10) MBEFCI_CASE(11) MBEFCI_CASE(12)
 #undef MBEFCI_CASE
+    case 8:  // three-wave workgroups: up to 64 columns
+      if constexpr (TN <= 64) { sigma_dgemm_t<8, TN>(items, work, nwork, warena, V, ntot, G, st, slot, s); return true; }
+      return false;
+    case 9:
+      if constexpr (TN <= 64) { sigma_dgemm_t<9, TN>(items, work, nwork, warena, V, ntot, G, st, slot, s); return true; }
+      return false;
     case 13:
       if constexpr (TN <= 64) { sigma_dgemm_t<13, TN>(items, work, nwork, warena, V, ntot, G, st, slot, s); return true; }
       return false;
@@ -3087,8 +3101,9 @@ bool launch_sigma_dgemm(int n, int tn, const Item* items, const Work* work, int 
     case 32: return sigma_dgemm_n<32>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
     case 64: return sigma_dgemm_n<64>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
     case 128:
-      // n >= 13 needs more LDS than one CU holds at 128 columns
-      if (n >= 13) return sigma_dgemm_n<64>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
+      // not compiled for n >= 13 (more LDS than one CU holds) nor for the
+      // three-wave workgroups of n = 8, 9: the work units must not be built
+      // for it (the caller maps such a schedule to 64 columns)
       return sigma_dgemm_n<128>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
     default: return false;
   }

@@ -489,9 +489,23 @@ const SymTab& sym_tab(mbefci_ctx* c, int n, int na, int nb, const int* osym, int
   return c->symtabs[key] = T;
 }
 
+void load_tune_cache(mbefci_ctx* c);
+// Tile widths compiled for active size n: 32 and 64 columns; 128 up to 12
+// orbitals except the three-wave workgroups of 8 and 9; flattened tiles of
+// 32 or 64 determinants up to 9 orbitals.
+bool tile_supported(int n, int tn) {
+  if (tn == 32 || tn == 64) return n >= 2 && n <= 14;
+  if (tn == 128) return n >= 2 && n <= 12 && n != 8 && n != 9;
+  if (tn == -32 || tn == -64) return n >= 2 && n <= 9;
+  return false;
+}
+// The schedule of active size n: a forced tile width (opts.tile; 128 becomes
+// 64 where it is not compiled), else the tuned one (a schedule read from the
+// cache file applies to every plan), else the default.
 int tile_for(mbefci_ctx* c, int n) {
   if (c->opts.tile == 32 || c->opts.tile == 64 || c->opts.tile == 128)
-    return (n >= 13 && c->opts.tile == 128) ? 64 : c->opts.tile;
+    return tile_supported(n, c->opts.tile) ? c->opts.tile : 64;
+  load_tune_cache(c);
   auto it = c->tuned.find(n);
   if (it != c->tuned.end()) return it->second.first;
   return n >= 10 ? 32 : 64;  // measured defaults when nothing is tuned
@@ -511,8 +525,7 @@ void load_tune_cache(mbefci_ctx* c) {
   int n, tn, tpw;
   char line[128];
   while (std::fgets(line, sizeof(line), f))
-    if (std::sscanf(line, "%d %d %d", &n, &tn, &tpw) == 3 && n >= 2 && n <= 14 &&
-        (tn == 32 || tn == 64 || tn == 128 || ((tn == -32 || tn == -64) && n <= 9)) &&
+    if (std::sscanf(line, "%d %d %d", &n, &tn, &tpw) == 3 && tile_supported(n, tn) &&
         tpw >= 1 && tpw <= 256)
       c->tuned[n] = {tn, tpw};
   std::fclose(f);
@@ -1012,8 +1025,7 @@ void autotune(mbefci_ctx* c, Plan& P) {
     float best = 1e30f;
     std::pair<int, int> pick{g.tn, g.tiles_per_wg};
     for (int tn : {32, 64, 128, -32, -64}) {
-      if (tn == 128 && g.n >= 13) continue;
-      if (tn < 0 && g.n > 9) continue;
+      if (!tile_supported(g.n, tn)) continue;
       for (int tpw : {4, 8, 16, 32}) {
         g.tn = tn;
         g.tiles_per_wg = tpw;

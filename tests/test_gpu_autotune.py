@@ -74,3 +74,41 @@ def test_flat_tiles_bitwise(tmp_path, tile):
     c.close()
     assert e0 == e1
     assert f"sigma_dgemm_flat<n=9,tile={-tile}>" in names
+
+
+SCHEDULES = [(tn, w) for tn in (32, 64, 128, -32, -64) for w in (1, 3, 16)]
+
+
+@pytest.mark.parametrize("n,na,nb", [(10, 5, 5), (9, 3, 4), (12, 6, 5)])
+def test_every_schedule_sigma_bitwise(tmp_path, n, na, nb):
+    """sigma = H c of one CASCI under every schedule the tuner can pick (tiles
+    of one alpha string x 32, 64 or 128 beta strings, flattened tiles of 32
+    or 64 determinants up to 9 orbitals; 1, 3 or 16 tiles per workgroup),
+    forced through the cache file: the same vector bit for bit, since the
+    contraction's MFMA chains and the gather's order do not depend on the
+    schedule."""
+    from paper_1910_03527_amd import Context, num_strings
+    h, g = W.synthetic(n, 700 + n)
+    nd = num_strings(n, na) * num_strings(n, nb)
+    rng = np.random.default_rng(n)
+    cv = rng.standard_normal(nd)
+    cv /= np.linalg.norm(cv)
+    hd, gd, cd = _dev(h), _dev(g), _dev(cv)
+    ref = None
+    for tn, w in SCHEDULES:
+        if (tn == 128 and (n > 12 or n in (8, 9))) or (tn < 0 and n > 9):
+            continue  # not compiled for this size (a cache entry for it is ignored)
+        cache = tmp_path / f"s{tn}_{w}.txt"
+        cache.write_text(f"{n} {tn} {w}\n")
+        c = Context(0, tile=0, tune_cache=str(cache), conv_tol=1e-3)
+        try:
+            got = c.sigma(hd, gd, na, nb, cd, 0.0).cpu().numpy()
+            c.casci([hd], [gd], na, nb)  # a solve of the same shape, for its kernel names
+            names = [k["name"] for k in c.time_kernels(reps=1)]
+        finally:
+            c.close()
+        kind = "sigma_dgemm_flat<" if tn < 0 else "sigma_dgemm<"
+        assert any(x.startswith(kind + f"n={n},tile={abs(tn)}>") for x in names), (names, tn)
+        if ref is None:
+            ref = got
+        assert np.array_equal(got, ref), (tn, w, float(np.max(np.abs(got - ref))))
