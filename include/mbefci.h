@@ -93,8 +93,9 @@ typedef struct {
                             pspace = 0: unit-vector guesses and the diagonal
                             correction only.  CASCIs of at most 112
                             determinants are always solved from their
-                            whole-space block.  Ignored with precond = 1
-                            (default 112)                                     */
+                            whole-space block.  With precond = 1 the P-space
+                            gives the guess only and every iteration takes
+                            the Olsen correction (default 112)               */
   int32_t screen_batch;  /* most CASCIs per solve batch of mbefci_mbe_screened
                             (an order with more tuples, or more than 2^25
                             determinants, is solved in several batches);

@@ -689,9 +689,9 @@ void build_sym_work(Plan& P, int64_t& gtot) {
 
 // items must have n, na, nb filled; computes every derived field, work lists
 // and allocates the arenas.
-// The P-space machinery also solves every CASCI of at most kMaxPspace
-// determinants exactly, so it runs whenever the diagonal correction is used.
-bool use_pspace(const mbefci_ctx* c) { return c->opts.precond == 0; }
+// The P-space machinery gives every solve its guess (and solves every CASCI
+// of at most kMaxPspace determinants exactly) under both corrections; its
+// correction on the P block is used with the diagonal correction only.
 
 void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
   const int mmax = c->opts.max_space;
@@ -817,7 +817,7 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
   P.V = arena<double>(c, "V", (size_t)(mmax + 1) * P.ntot, &grown);
   P.S = arena<double>(c, "S", (size_t)mmax * P.ntot, &grown);
   P.diag = arena<double>(c, "diag", P.ntot, &grown);
-  if (use_pspace(c)) {
+  {
     P.pidx = arena<int32_t>(c, "pidx", (size_t)P.nitem * kMaxPspace, &grown);
     P.pQ = arena<double>(c, "pQ", (size_t)P.nitem * kMaxPspace * kMaxPspace, &grown);
     P.pT = arena<double>(c, "pT", (size_t)P.nitem * 2 * kMaxPspace, &grown);
@@ -984,7 +984,7 @@ void step_a(mbefci_ctx* c, Plan& P, const View& v) {
   launch_dav_iteration(P.d_items, v.ibase, v.nitem, P.d_chunks + v.chunk_lo, v.nchunk, P.V, P.S,
                        P.diag, P.ntot, P.st, P.part, c->opts.conv_tol, c->opts.max_iter,
                        c->opts.max_space, olsen ? P.R : nullptr, olsen ? P.X : nullptr,
-                       P.pidx ? &ps : nullptr, c->stream);
+                       (P.pidx && !olsen) ? &ps : nullptr, c->stream);
 }
 void step_b(mbefci_ctx* c, Plan& P, const View& v) { add_vector(c, P, v, -1); }
 
