@@ -537,6 +537,16 @@ def main():
                                  "ncasci": int(sc["ntuples"]), "max_order": cp.max_order,
                                  "sigma_calls": sc["sigma_calls"], "e_total": rc["e_total"]}
                 if name == "synthetic40":
+                    # the RDM backward of the same expansion (dE/dh, dE/d(pq|rs),
+                    # M = 40), timed after a forward: median of three
+                    bt = []
+                    for _ in range(3):
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        cctx.mbe_backward([1.0] * (1 + cp.max_order))
+                        torch.cuda.synchronize()
+                        bt.append((time.perf_counter() - t0) * 1e3)
+                    configs[name]["ms_backward"] = round(sorted(bt)[1], 3)
                     kc = cctx.time_kernels(2)
                     configs[name]["kernels"] = _kernel_rows(kc, name)
                     configs[name]["roofline"] = _roofline(kc, name)

@@ -2643,62 +2643,128 @@ __device__ inline double wave_sum64(double v) {
   return v;
 }
 
+// Orbitals on which a CASCI's full-space RDMs can be non-zero: its active
+// orbitals and the occupied orbitals of the reference determinant (frozen
+// when not active); every other orbital is deleted.  A single-determinant
+// CASCI counts only the occupied ones (its active orbitals are frozen or
+// deleted alike).  One thread per item.
+__global__ void k_grad_masks(const Item* __restrict__ items, int nitem,
+                             const int32_t* __restrict__ act, uint64_t occmask,
+                             uint64_t* __restrict__ live) {
+  const int it = blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= nitem) return;
+  const Item& I = items[it];
+  uint64_t m = occmask;
+  if (I.ndet > 1)
+    for (int t = 0; t < I.n; ++t) m |= (uint64_t)1 << act[it * kMaxActive + t];
+  live[it] = m;
+}
+
+// Inverted index: list[v * nitem + k], k < count[v], the items whose live
+// mask holds orbital v, in ascending order (one wave per orbital compacts
+// the items with a ballot, so the order is fixed).
+__global__ void __launch_bounds__(64) k_grad_index(const uint64_t* __restrict__ live, int nitem,
+                                                   int32_t* __restrict__ list,
+                                                   int32_t* __restrict__ count) {
+  const int v = blockIdx.x, lane = threadIdx.x;
+  int base = 0;
+  for (int it0 = 0; it0 < nitem; it0 += 64) {
+    const int it = it0 + lane;
+    const bool has = it < nitem && ((live[it] >> v) & 1);
+    const uint64_t b = __ballot(has);
+    if (has) list[(int64_t)v * nitem + base + __popcll(b & ((1ull << lane) - 1))] = it;
+    base += __popcll(b);
+  }
+  if (lane == 0) count[v] = base;
+}
+
+// The items an element with orbitals in mask e can draw on: the inverted
+// list of its orbital with the fewest items (ties: the lower orbital); an
+// item of that list contributes only if its live mask holds all of e.
+__device__ inline int grad_pivot(uint64_t e, const int32_t* __restrict__ count) {
+  int best = -1, nb = 0;
+  for (uint64_t m = e; m; m &= m - 1) {
+    const int v = __builtin_ctzll(m);
+    const int nv = count[v];
+    if (best < 0 || nv < nb) best = v, nb = nv;
+  }
+  return best;
+}
+
 // dE/dh_pq = sum_it w_it gamma_full(p, q).  One wave per element: lane l
-// sums the items l, l + 64, ..., then the lanes' sums meet in wave_sum64
-// (a fixed order, so the result is bitwise reproducible).
+// sums the candidate items l, l + 64, ... of the pivot's inverted list (in
+// ascending item order), then the lanes' sums meet in wave_sum64 (a fixed
+// order, so the result is bitwise reproducible).
 __global__ void __launch_bounds__(64) k_grad_h(const Item* __restrict__ items, int nitem,
                                                const int32_t* __restrict__ act, uint64_t occmask,
                                                int M, const double* __restrict__ w,
                                                const double* __restrict__ rdmp,
-                                               const int64_t* __restrict__ roff, double* out) {
+                                               const int64_t* __restrict__ roff,
+                                               const uint64_t* __restrict__ live,
+                                               const int32_t* __restrict__ list,
+                                               const int32_t* __restrict__ count, double* out) {
   const int x = blockIdx.x;
   const int p = x / M, q = x % M;
   const int lane = threadIdx.x;
+  const uint64_t e = ((uint64_t)1 << p) | ((uint64_t)1 << q);
+  const int v = grad_pivot(e, count);
+  const int nv = count[v];
+  const int32_t* __restrict__ cand = list + (int64_t)v * nitem;
   double acc = 0.0;
-  for (int it = lane; it < nitem; it += 64) {
+  for (int k = lane; k < nv; k += 64) {
+    const int it = cand[k];
+    if (e & ~live[it]) continue;
     const double wt = w[it];
     if (wt == 0.0) continue;
     const Item& I = items[it];
     const bool single = I.ndet == 1;
     const int32_t* a = act + it * kMaxActive;
     const int cp = orb_class(a, I.n, single, occmask, p), cq = orb_class(a, I.n, single, occmask, q);
-    double v = 0.0;
-    if (cp == -1 && cq == -1 && p == q) v = 2.0;
-    else if (cp >= 0 && cq >= 0) v = act_gamma(rdmp + roff[it], I.kpad, I.npair, cp, cq);
-    acc += wt * v;
+    double val = 0.0;
+    if (cp == -1 && cq == -1 && p == q) val = 2.0;
+    else if (cp >= 0 && cq >= 0) val = act_gamma(rdmp + roff[it], I.kpad, I.npair, cp, cq);
+    acc += wt * val;
   }
   acc = wave_sum64(acc);
   if (lane == 0) out[x] = acc;
 }
 
 // dE/d(pq|rs) = sum_it w_it 1/2 Sym8(Gamma_full)_pqrs, one wave per element
-// as in k_grad_h (four elements per 256-thread block).
+// as in k_grad_h (four elements per 256-thread block).  An element with an
+// orbital outside every CASCI's live set, or with more expansion orbitals
+// than any tuple holds, finds an empty or non-matching candidate list.
 __global__ void __launch_bounds__(256) k_grad_g(const Item* __restrict__ items, int nitem,
                                                 const int32_t* __restrict__ act, uint64_t occmask,
                                                 int M, const double* __restrict__ w,
                                                 const double* __restrict__ rdmp,
-                                                const int64_t* __restrict__ roff, double* out) {
+                                                const int64_t* __restrict__ roff,
+                                                const uint64_t* __restrict__ live,
+                                                const int32_t* __restrict__ list,
+                                                const int32_t* __restrict__ count, double* out) {
   const int64_t x = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t M2 = (int64_t)M * M;
   if (x >= M2 * M2) return;  // whole waves
   const int p = (int)(x / (M2 * M)), q = (int)((x / M2) % M), r = (int)((x / M) % M),
             s = (int)(x % M);
+  const uint64_t e = ((uint64_t)1 << p) | ((uint64_t)1 << q) | ((uint64_t)1 << r) |
+                     ((uint64_t)1 << s);
+  const int v = __builtin_amdgcn_readfirstlane(grad_pivot(e, count));
+  const int nv = count[v];
+  const int32_t* __restrict__ cand = list + (int64_t)v * nitem;
   double acc = 0.0;
-  for (int it = lane; it < nitem; it += 64) {
+  for (int k = lane; k < nv; k += 64) {
+    const int it = cand[k];
+    if (e & ~live[it]) continue;
     const double wt = w[it];
     if (wt == 0.0) continue;
     const Item& I = items[it];
     const bool single = I.ndet == 1;
     const int32_t* a = act + it * kMaxActive;
     const int cp = orb_class(a, I.n, single, occmask, p);
-    if (cp == -2) continue;
     const int cq = orb_class(a, I.n, single, occmask, q);
-    if (cq == -2) continue;
     const int cr = orb_class(a, I.n, single, occmask, r);
-    if (cr == -2) continue;
     const int cs = orb_class(a, I.n, single, occmask, s);
-    if (cs == -2) continue;
     acc += wt * 0.5 * sym_gamma2(p, q, r, s, cp, cq, cr, cs, rdmp + roff[it], I.kpad, I.npair);
   }
   acc = wave_sum64(acc);
@@ -3349,13 +3415,16 @@ void launch_mbe_weights(const BucketDev* buckets, int nbucket, int nitem, int ne
                      nexp, max_order, g, w);
 }
 void launch_grad(const Item* items, int nitem, const int32_t* act, uint64_t occmask, int M,
-                 const double* w, const double* rdmp, const int64_t* roff, double* dh, double* dg,
-                 hipStream_t s) {
+                 const double* w, const double* rdmp, const int64_t* roff, uint64_t* live,
+                 int32_t* list, int32_t* count, double* dh, double* dg, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_masks, dim3(nblk(nitem, 64)), dim3(64), 0, s, items, nitem, act,
+                     occmask, live);
+  hipLaunchKernelGGL(k_grad_index, dim3(M), dim3(64), 0, s, live, nitem, list, count);
   hipLaunchKernelGGL(k_grad_h, dim3(M * M), dim3(64), 0, s, items, nitem, act, occmask, M, w, rdmp,
-                     roff, dh);
+                     roff, live, list, count, dh);
   const int64_t M4 = (int64_t)M * M * M * M;
   hipLaunchKernelGGL(k_grad_g, dim3(nblk(M4, 4)), dim3(256), 0, s, items, nitem, act, occmask, M,
-                     w, rdmp, roff, dg);
+                     w, rdmp, roff, live, list, count, dg);
 }
 void launch_casci_rdm_out(const Item* items, int it, int n, const double* rdmp,
                           const int64_t* roff, double* rdm1, double* rdm2, hipStream_t s) {

@@ -152,9 +152,11 @@ void launch_rdm_reduce(const Item* items, int nitem, const int32_t* wlo, const i
                        hipStream_t s);
 void launch_mbe_weights(const BucketDev* buckets, int nbucket, int nitem, int nexp, int max_order,
                         const double* g, double* w, hipStream_t s);
+// dE/dh and dE/d(pq|rs) from the weighted RDMs; live [nitem], list
+// [M * nitem] and count [M] are workspace for the per-orbital item lists
 void launch_grad(const Item* items, int nitem, const int32_t* act, uint64_t occmask, int M,
-                 const double* w, const double* rdmp, const int64_t* roff, double* dh, double* dg,
-                 hipStream_t s);
+                 const double* w, const double* rdmp, const int64_t* roff, uint64_t* live,
+                 int32_t* list, int32_t* count, double* dh, double* dg, hipStream_t s);
 void launch_casci_rdm_out(const Item* items, int it, int n, const double* rdmp,
                           const int64_t* roff, double* rdm1, double* rdm2, hipStream_t s);
 

@@ -2312,8 +2312,11 @@ int mbefci_mbe_backward(mbefci_ctx* c, const double* grad_out, double* d_h1, dou
                        P.max_order, d_g, d_w, c->stream);
     uint64_t occmask = 0;
     for (int i = 0; i < P.sp.nO; ++i) occmask |= (uint64_t)1 << P.sp.O[i];
-    launch_grad(P.d_items, P.nitem, P.act, occmask, P.norb, d_w, R.rdmp, R.roff, d_h1, d_eri,
-                c->stream);
+    uint64_t* d_live = arena<uint64_t>(c, "grad_live", P.nitem);
+    int32_t* d_list = arena<int32_t>(c, "grad_list", (size_t)P.norb * P.nitem);
+    int32_t* d_count = arena<int32_t>(c, "grad_count", P.norb);
+    launch_grad(P.d_items, P.nitem, P.act, occmask, P.norb, d_w, R.rdmp, R.roff, d_live, d_list,
+                d_count, d_h1, d_eri, c->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
     sc.done();
