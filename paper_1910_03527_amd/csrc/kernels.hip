@@ -972,25 +972,81 @@ __global__ void __launch_bounds__(256) k_sigma_sym_dgemm(
   }
   const int blk = wk.begin / NA;
   const int kb0 = blk * TN;
+  // Classes of up to 32 pairs: this thread builds the D+ slots (class pair
+  // sub + NSUB k, column col) of every tile of the unit; their beta
+  // pair-table entries depend on the column only, so they are loaded once
+  // per unit, and the alpha entries are wave-uniform per pair row (scalar
+  // loads).  Larger classes build D+ element by element (registers for the
+  // slots would cost them occupancy).
+  constexpr bool SLOTS = NPC <= 32;
+  constexpr int NSUB = 256 / TN;
+  constexpr int NPER = SLOTS ? (NPC + NSUB - 1) / NSUB : 1;
+  const int col = t % TN;
+  const int sub = TN >= 64 ? __builtin_amdgcn_readfirstlane(t / TN) : t / TN;
+  const int kb = kb0 + col;
+  const bool live = kb < NB;
+  const int kbc = live ? kb : NB - 1;
+  int32_t eb[NPER];
+  int32_t ea[NPER];
+  double ga[NPER], gb[NPER];
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  auto load_tile = [&](int ka) {
+    const int32_t* __restrict__ pa = pA + (int64_t)ka * Y.npair;
+    const double* __restrict__ crow = csrcB + (int64_t)ka * NBa;
+#pragma unroll
+    for (int k = 0; k < NPER; ++k) {
+      if constexpr (TN >= 64) {
+        const int i = sub + NSUB * k;
+        ea[k] = (i < nps) ? ldc(pa + i) : 0;
+      } else {
+        const int i0 = 2 * wave_u + NSUB * k;
+        const int32_t e0 = i0 < nps ? ldc(pa + i0) : 0;
+        const int32_t e1 = i0 + 1 < nps ? ldc(pa + i0 + 1) : 0;
+        ea[k] = lane < 32 ? e0 : e1;
+      }
+      ga[k] = ea[k] ? ldg(csrcA + (int64_t)((ea[k] >> 1) - 1) * NB + kbc) : 0.0;
+      gb[k] = eb[k] ? ldg(crow + ((eb[k] >> 1) - 1)) : 0.0;
+    }
+  };
+  if constexpr (SLOTS) {
+#pragma unroll
+    for (int k = 0; k < NPER; ++k) {
+      const int i = sub + NSUB * k;
+      eb[k] = (i < nps && live) ? ldg(pB + (int64_t)i * I.Nb + kbc) : 0;
+    }
+  }
   for (int tile = wk.begin; tile < wk.end; ++tile) {
     const int ka = tile - blk * NA;
     // D+ tile [NPC][TN]: class pair i, column kb0 + col
-    for (int x = t; x < NPC * TN; x += 256) {
-      const int i = x / TN, col = x % TN, kb = kb0 + col;
-      double v = 0.0;
-      if (i < nps && kb < NB) {
-        const int32_t ea = ldg(pA + (int64_t)ka * Y.npair + i);
-        if (ea) {
-          const double cv = ldg(csrcA + (int64_t)((ea >> 1) - 1) * NB + kb);
-          v += (ea & 1) ? -cv : cv;
-        }
-        const int32_t eb = ldg(pB + (int64_t)i * I.Nb + kb);
-        if (eb) {
-          const double cv = ldg(csrcB + (int64_t)ka * NBa + ((eb >> 1) - 1));
-          v += (eb & 1) ? -cv : cv;
+    if constexpr (SLOTS) {
+      load_tile(ka);
+#pragma unroll
+      for (int k = 0; k < NPER; ++k) {
+        const int i = sub + NSUB * k;
+        if (i < NPC) {
+          const double fa = (ea[k] && live) ? ((ea[k] & 1) ? -1.0 : 1.0) : 0.0;
+          const double fb = eb[k] ? ((eb[k] & 1) ? -1.0 : 1.0) : 0.0;
+          Ds[i * LDT + col] = fa * ga[k] + fb * gb[k];
         }
       }
-      Ds[i * LDT + col] = v;
+    } else {
+      for (int x = t; x < NPC * TN; x += 256) {
+        const int i = x / TN, cx = x % TN, kx = kb0 + cx;
+        double v = 0.0;
+        if (i < nps && kx < NB) {
+          const int32_t e1 = ldg(pA + (int64_t)ka * Y.npair + i);
+          if (e1) {
+            const double cv = ldg(csrcA + (int64_t)((e1 >> 1) - 1) * NB + kx);
+            v += (e1 & 1) ? -cv : cv;
+          }
+          const int32_t e2 = ldg(pB + (int64_t)i * I.Nb + kx);
+          if (e2) {
+            const double cv = ldg(csrcB + (int64_t)ka * NBa + ((e2 >> 1) - 1));
+            v += (e2 & 1) ? -cv : cv;
+          }
+        }
+        Ds[i * LDT + cx] = v;
+      }
     }
     __syncthreads();
     double* __restrict__ Grows = G_s + (int64_t)ka * nps * NB;
