@@ -147,7 +147,7 @@ struct DavState {
   int32_t nguess;     // number of guess vectors (slots 0..nguess-1)
   int32_t np;         // P-space size (0: diagonal preconditioner only)
   int32_t onepass;    // this iteration's correction needs one Gram-Schmidt pass
-  int32_t pad_;
+  int32_t olsen;      // 1: the corrections have switched to the Olsen form
   double theta;       // lowest Ritz value (active-space energy without ecore)
   double rnorm;       // residual norm of the last Ritz vector
   double tnorm2;      // squared norm of the correction vector

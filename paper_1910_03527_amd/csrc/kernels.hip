@@ -1279,6 +1279,7 @@ __global__ void k_dav_guess(const Item* __restrict__ items, int ibase,
     S.nguess = g + (dense ? 1 : 0);
     S.np = 0;
     S.onepass = 0;
+    S.olsen = 0;
     S.iters = 0;
     S.status = 0;
     S.rnorm = 0.0;
@@ -1526,7 +1527,7 @@ __global__ void __launch_bounds__(256) k_dav_residual(const Item* __restrict__ i
   const Work wk = work[blockIdx.x];
   const Item& I = items[wk.item];
   const DavState& S = st[wk.item];
-  if (S.conv) return;
+  if (S.conv || S.olsen) return;
   const int m = S.m;
   const double th = S.theta;
   double y[kMaxSpace];
@@ -1576,11 +1577,11 @@ __global__ void __launch_bounds__(256) k_dav_residual_olsen(
     const Item* __restrict__ items, const Work* __restrict__ work, const double* __restrict__ V,
     const double* __restrict__ Sv, const double* __restrict__ diag, int64_t ntot,
     const DavState* __restrict__ st, double* __restrict__ Rb, double* __restrict__ Xb,
-    double* part) {
+    double* part, int all) {
   const Work wk = work[blockIdx.x];
   const Item& I = items[wk.item];
   const DavState& S = st[wk.item];
-  if (S.conv) return;
+  if (S.conv || !(all || S.olsen)) return;
   const int m = S.m;
   const double th = S.theta;
   double y[kMaxSpace];
@@ -1610,13 +1611,13 @@ __global__ void __launch_bounds__(256) k_dav_residual_olsen(
 
 __global__ void k_dav_reduce1_olsen(const Item* __restrict__ items,
                                     const double* __restrict__ part, DavState* st, int ibase,
-                                    int nitem, double tol, int max_iter) {
+                                    int nitem, double tol, int max_iter, int all) {
   int it = blockIdx.x * blockDim.x + threadIdx.x;
   if (it >= nitem) return;
   it += ibase;
   const Item& I = items[it];
   DavState& S = st[it];
-  if (S.conv) return;
+  if (S.conv || !(all || S.olsen)) return;
   double rr = 0.0, a = 0.0, b = 0.0;
   for (int c = 0; c < I.nchunk; ++c) {
     const double* p = part + (int64_t)(I.chunk0 + c) * kPart;
@@ -1638,11 +1639,11 @@ __global__ void k_dav_reduce1_olsen(const Item* __restrict__ items,
 __global__ void __launch_bounds__(256) k_dav_precond_olsen(
     const Item* __restrict__ items, const Work* __restrict__ work, double* V,
     const double* __restrict__ diag, int64_t ntot, const DavState* __restrict__ st,
-    const double* __restrict__ Rb, const double* __restrict__ Xb, double* part) {
+    const double* __restrict__ Rb, const double* __restrict__ Xb, double* part, int all) {
   const Work wk = work[blockIdx.x];
   const Item& I = items[wk.item];
   const DavState& S = st[wk.item];
-  if (S.conv) return;
+  if (S.conv || !(all || S.olsen)) return;
   const int m = S.m;
   const double th = S.theta, eps = S.eps;
   double acc[kMaxSpace];
@@ -1664,13 +1665,13 @@ __global__ void __launch_bounds__(256) k_dav_precond_olsen(
 
 // first Gram-Schmidt coefficients from the partial dots
 __global__ void k_dav_reduce_coef(const Item* __restrict__ items, const double* __restrict__ part,
-                                  DavState* st, int ibase, int nitem) {
+                                  DavState* st, int ibase, int nitem, int all) {
   int it = blockIdx.x * blockDim.x + threadIdx.x;
   if (it >= nitem) return;
   it += ibase;
   const Item& I = items[it];
   DavState& S = st[it];
-  if (S.conv) return;
+  if (S.conv || !(all || S.olsen)) return;
   double cf[kMaxSpace];
   for (int i = 0; i < kMaxSpace; ++i) cf[i] = 0.0;
   for (int c = 0; c < I.nchunk; ++c) {
@@ -1681,16 +1682,18 @@ __global__ void k_dav_reduce_coef(const Item* __restrict__ items, const double* 
   S.onepass = 0;
 }
 
-// Convergence test and first Gram-Schmidt coefficients.
+// Convergence test and first Gram-Schmidt coefficients.  An unconverged
+// item whose residual fell below olsen_below takes the Olsen correction from
+// the next iteration on (0: never).
 __global__ void k_dav_reduce1(const Item* __restrict__ items, const double* __restrict__ part,
                               const double* __restrict__ pdots, DavState* st, int ibase,
-                              int nitem, double tol, int max_iter) {
+                              int nitem, double tol, int max_iter, double olsen_below) {
   int it = blockIdx.x * blockDim.x + threadIdx.x;
   if (it >= nitem) return;
   it += ibase;
   const Item& I = items[it];
   DavState& S = st[it];
-  if (S.conv) return;
+  if (S.conv || S.olsen) return;
   double rr = 0.0, tt = 0.0;
   double cf[kMaxSpace];
   for (int i = 0; i < kMaxSpace; ++i) cf[i] = 0.0;
@@ -1718,6 +1721,8 @@ __global__ void k_dav_reduce1(const Item* __restrict__ items, const double* __re
   } else if (S.iters >= max_iter) {
     S.conv = 1;
     S.status = 1;
+  } else if (S.rnorm < olsen_below) {
+    S.olsen = 1;
   }
 }
 
@@ -2143,6 +2148,7 @@ __global__ void __launch_bounds__(256) k_pspace_guess(const Item* __restrict__ i
       V[I.off] = 1.0;
       S.m = 1; S.nguess = 1; S.np = 0; S.iters = 0; S.status = 0; S.rnorm = 0.0; S.conv = 1;
       S.onepass = 0;
+      S.olsen = 0;
       S.theta = diag[I.off];
     }
     return;
@@ -2160,6 +2166,7 @@ __global__ void __launch_bounds__(256) k_pspace_guess(const Item* __restrict__ i
   if (t == 0) {
     S.m = 0; S.nguess = g + 1; S.np = 0; S.iters = 0; S.status = 0; S.rnorm = 0.0; S.conv = 0;
     S.onepass = 0;
+    S.olsen = 0;
     S.theta = 0.0;
   }
 }
@@ -2422,6 +2429,7 @@ __global__ void __launch_bounds__(NT) k_pspace_eigen(
     S.nguess = 1 + (dense ? 1 : 0);
     S.np = EXACT ? 0 : n;  // an exact guess needs no P-space correction
     S.onepass = 0;
+    S.olsen = 0;
     S.iters = 0;
     S.status = 0;
     S.rnorm = 0.0;
@@ -2446,7 +2454,7 @@ __global__ void __launch_bounds__(256) k_pspace_correct(const Item* __restrict__
   const int it = ibase + blockIdx.x;
   const Item& I = items[it];
   const DavState& S = st[it];
-  if (S.conv || S.np == 0) return;
+  if (S.conv || S.np == 0 || S.olsen) return;
   const int np = S.np, m = S.m, t = threadIdx.x;
   const double th = S.theta;
   __shared__ double r[PM], z[PM], dd[PM], ee[PM], piv[PM];
@@ -3354,29 +3362,36 @@ void launch_pspace_setup(const Item* items, int ibase, int nitem, const PspaceLi
 void launch_dav_iteration(const Item* items, int ibase, int nitem, const Work* chunks, int nchunk,
                           double* V, double* Sv, const double* diag, int64_t ntot, DavState* st,
                           double* part, double tol, int max_iter, int mmax, double* Rb,
-                          double* Xb, const PspaceArgs* ps, hipStream_t s) {
+                          double* Xb, const PspaceArgs* ps, bool olsen_all, double olsen_below,
+                          hipStream_t s) {
   if (nchunk <= 0) return;
   const int nb = nblk(nitem, 64);
   hipLaunchKernelGGL(k_dav_collapse, dim3(nchunk), dim3(256), 0, s, items, chunks, V, Sv, ntot, st,
                      mmax);
   hipLaunchKernelGGL(k_dav_collapse_state, dim3(nb), dim3(64), 0, s, items, st, ibase, nitem,
                      mmax);
-  if (Rb && Xb) {
+  // Olsen-corrected items first (all of them with olsen_all, else those that
+  // switched in an earlier iteration), then the diagonal / P-space path for
+  // the others, whose test may switch an item for the next iteration
+  if (olsen_all || olsen_below > 0.0) {
+    const int all = olsen_all ? 1 : 0;
     hipLaunchKernelGGL(k_dav_residual_olsen, dim3(nchunk), dim3(256), 0, s, items, chunks, V, Sv,
-                       diag, ntot, st, Rb, Xb, part);
+                       diag, ntot, st, Rb, Xb, part, all);
     hipLaunchKernelGGL(k_dav_reduce1_olsen, dim3(nb), dim3(64), 0, s, items, part, st, ibase,
-                       nitem, tol, max_iter);
+                       nitem, tol, max_iter, all);
     hipLaunchKernelGGL(k_dav_precond_olsen, dim3(nchunk), dim3(256), 0, s, items, chunks, V, diag,
-                       ntot, st, Rb, Xb, part);
-    hipLaunchKernelGGL(k_dav_reduce_coef, dim3(nb), dim3(64), 0, s, items, part, st, ibase, nitem);
-  } else {
+                       ntot, st, Rb, Xb, part, all);
+    hipLaunchKernelGGL(k_dav_reduce_coef, dim3(nb), dim3(64), 0, s, items, part, st, ibase, nitem,
+                       all);
+  }
+  if (!olsen_all) {
     hipLaunchKernelGGL(k_dav_residual, dim3(nchunk), dim3(256), 0, s, items, chunks, V, Sv, diag,
                        ntot, st, part);
     if (ps)
       hipLaunchKernelGGL(k_pspace_correct, dim3(nitem), dim3(256), 0, s, items, ibase, ps->pidx,
                          ps->pQ, ps->pT, V, Sv, ntot, st, ps->pdots);
     hipLaunchKernelGGL(k_dav_reduce1, dim3(nb), dim3(64), 0, s, items, part,
-                       ps ? ps->pdots : nullptr, st, ibase, nitem, tol, max_iter);
+                       ps ? ps->pdots : nullptr, st, ibase, nitem, tol, max_iter, olsen_below);
   }
   hipLaunchKernelGGL(k_dav_orth, dim3(nchunk), dim3(256), 0, s, items, chunks, V, ntot, st, part);
   hipLaunchKernelGGL(k_dav_reduce2, dim3(nb), dim3(64), 0, s, items, part, st, ibase, nitem);

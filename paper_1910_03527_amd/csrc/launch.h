@@ -120,10 +120,16 @@ void launch_pspace_setup(const Item* items, int ibase, int nitem, const PspaceLi
                          const ItemHam* hams, const double* diag, int32_t* pidx, double* pQ,
                          double* pT, double* V, int64_t ntot, DavState* st, int pmax, int nunit,
                          const PspaceSelect& sel, hipStream_t s);
+// One Davidson iteration after a sigma sweep: restart, correction, Gram-Schmidt.
+// olsen_all: every item takes the Olsen correction (Rb, Xb: residual and Ritz
+// vector buffers); otherwise the diagonal correction (with the P-space block
+// when ps is set), and items whose residual fell below olsen_below (> 0)
+// switch to the Olsen correction for the rest of the solve.
 void launch_dav_iteration(const Item* items, int ibase, int nitem, const Work* chunks, int nchunk,
                           double* V, double* Sv, const double* diag, int64_t ntot, DavState* st,
                           double* part, double tol, int max_iter, int mmax, double* Rb,
-                          double* Xb, const PspaceArgs* ps, hipStream_t s);
+                          double* Xb, const PspaceArgs* ps, bool olsen_all, double olsen_below,
+                          hipStream_t s);
 void launch_item_energy(const Item* items, const ItemHam* hams, const DavState* st, int nitem,
                         double* f, hipStream_t s);
 void launch_mbe_combine(const MbeSpaces* sp, const BucketDev* buckets, int nbucket,

@@ -850,10 +850,10 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
     upload(c, P.psel_slot, P.psel_slots);
     upload(c, P.psel_work, P.psel_works);
   }
-  if (c->opts.precond == 1) {
-    P.R = arena<double>(c, "resid", P.ntot, &grown);
-    P.X = arena<double>(c, "ritz", P.ntot, &grown);
-  }
+  // residual and Ritz vectors of the Olsen correction (every solve may switch
+  // to it near convergence)
+  P.R = arena<double>(c, "resid", P.ntot, &grown);
+  P.X = arena<double>(c, "ritz", P.ntot, &grown);
   P.G = arena<double>(c, "G", std::max<int64_t>(P.gtot, 1), &grown);
   P.W = arena<double>(c, "W", std::max<int64_t>(P.wtot, 1), &grown);
   P.part = arena<double>(c, "part", (size_t)std::max(P.nchunk, 1) * kPartStride, &grown);
@@ -978,13 +978,19 @@ void add_vector(mbefci_ctx* c, Plan& P, const View& v, int slot) {
 // sits between them: step_a forms the residual of the current Ritz vector,
 // decides convergence and builds the next basis vector; step_b applies sigma
 // to it and updates the subspace matrix and Ritz pair.
+constexpr double kOlsenSwitch = 1e-7;
 void step_a(mbefci_ctx* c, Plan& P, const View& v) {
   const bool olsen = c->opts.precond == 1;
   const PspaceArgs ps{P.pidx, P.pQ, P.pT, P.pdots};
+  // with the diagonal / P-space correction a CASCI switches to the Olsen
+  // correction once its residual is below kOlsenSwitch: that correction is
+  // exact on the P block, so near convergence most of the new direction lies
+  // along the Ritz vector and cancels in the Gram-Schmidt step
+  const double below = (!olsen && c->opts.conv_tol < kOlsenSwitch) ? kOlsenSwitch : 0.0;
   launch_dav_iteration(P.d_items, v.ibase, v.nitem, P.d_chunks + v.chunk_lo, v.nchunk, P.V, P.S,
                        P.diag, P.ntot, P.st, P.part, c->opts.conv_tol, c->opts.max_iter,
-                       c->opts.max_space, olsen ? P.R : nullptr, olsen ? P.X : nullptr,
-                       (P.pidx && !olsen) ? &ps : nullptr, c->stream);
+                       c->opts.max_space, P.R, P.X, (P.pidx && !olsen) ? &ps : nullptr, olsen,
+                       below, c->stream);
 }
 void step_b(mbefci_ctx* c, Plan& P, const View& v) { add_vector(c, P, v, -1); }
 

@@ -96,6 +96,9 @@ def test_olsen_casci_batch(tol):
         try:
             es.append(c.casci([_dev(h) for h, _ in probs], [_dev(g) for _, g in probs], 5, 5))
             assert c.last_stats["first_failed"] == -1
+            # below residual 1e-7 the P-space path switches to the Olsen
+            # correction (it took 50 iterations to 1e-9 without the switch)
+            assert c.last_stats["max_iters"] <= 35, (opts, c.last_stats["max_iters"])
         finally:
             c.close()
     assert max(abs(a - b) for a, b in zip(*es)) < 1e-10
