@@ -81,9 +81,12 @@ typedef struct {
                             pair array) stays below this many MiB, so that it is
                             re-read from the on-die cache and its memory is bounded;
                             0 = one pass (default 0) */
-  int32_t precond;       /* Davidson correction: 0 = diagonal (theta - H_II)^-1 r,
-                            1 = Olsen-corrected, orthogonal to the Ritz vector
-                            (default 0)                                          */
+  int32_t precond;       /* Davidson correction: 0 = diagonal (theta - H_II)^-1 r
+                            (with the P-space block below), where, when
+                            conv_tol < 1e-7, a CASCI whose residual norm has
+                            fallen below 1e-7 takes the Olsen form for the
+                            rest of its solve; 1 = Olsen-corrected, orthogonal
+                            to the Ritz vector, every iteration (default 0) */
   int32_t pspace;        /* largest P-space, 0..112: a CASCI of ndet > 112
                             determinants uses the P = min(pspace, ndet / 64)
                             determinants of lowest diagonal energy, whose block
