@@ -2742,42 +2742,132 @@ __global__ void __launch_bounds__(64) k_grad_index(const uint64_t* __restrict__ 
   if (lane == 0) count[v] = base;
 }
 
-// The items an element with orbitals in mask e can draw on: the inverted
-// list of its orbital with the fewest items (ties: the lower orbital); an
-// item of that list contributes only if its live mask holds all of e.
-__device__ inline int grad_pivot(uint64_t e, const int32_t* __restrict__ count) {
-  int best = -1, nb = 0;
-  for (uint64_t m = e; m; m &= m - 1) {
-    const int v = __builtin_ctzll(m);
-    const int nv = count[v];
-    if (best < 0 || nv < nb) best = v, nb = nv;
+// Inverted lists of orbital pairs u < v (pair number v (v - 1) / 2 + u):
+// the items whose live mask holds both, in ascending order, stored one after
+// another (pair p at poff[p], pcount[p] entries).  An element with two or
+// more distinct orbitals draws on the shortest of its pairs' lists when that
+// is shorter than its orbitals' lists: the items that hold two given
+// expansion orbitals are far fewer than those that hold one.
+__host__ __device__ inline int orb_pair_id(int u, int v) { return v * (v - 1) / 2 + u; }
+
+// pcount of pair (blockIdx.x, blockIdx.y) when x < y; one wave per pair.
+__global__ void __launch_bounds__(64) k_grad_pair_count(const uint64_t* __restrict__ live,
+                                                        int nitem, int32_t* __restrict__ pcount) {
+  const int u = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
+  if (u >= v) return;
+  const uint64_t m = ((uint64_t)1 << u) | ((uint64_t)1 << v);
+  int n = 0;
+  for (int it0 = 0; it0 < nitem; it0 += 64) {
+    const int it = it0 + lane;
+    n += __popcll(__ballot(it < nitem && (live[it] & m) == m));
   }
-  return best;
+  if (lane == 0) pcount[orb_pair_id(u, v)] = n;
 }
 
-// dE/dh_pq = sum_it w_it gamma_full(p, q).  One wave per element: lane l
-// sums the candidate items l, l + 64, ... of the pivot's inverted list (in
-// ascending item order), then the lanes' sums meet in wave_sum64 (a fixed
-// order, so the result is bitwise reproducible).
+// poff[p] = pcount[0] + ... + pcount[p - 1] for p <= npair: one wave, lane
+// l sums a contiguous chunk, the chunk sums are scanned across the lanes.
+__global__ void __launch_bounds__(64) k_grad_pair_scan(const int32_t* __restrict__ pcount,
+                                                       int npair, int64_t* __restrict__ poff) {
+  const int lane = threadIdx.x;
+  const int per = (npair + 63) / 64;
+  const int lo = min(lane * per, npair), hi = min(lo + per, npair);
+  int64_t sum = 0;
+  for (int i = lo; i < hi; ++i) sum += pcount[i];
+  int64_t incl = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  int64_t run = incl - sum;
+  for (int i = lo; i < hi; ++i) {
+    poff[i] = run;
+    run += pcount[i];
+  }
+  if (lane == 63) poff[npair] = incl;
+}
+
+// The list of pair (blockIdx.x, blockIdx.y), x < y, compacted with a ballot
+// in ascending item order; one wave per pair.
+__global__ void __launch_bounds__(64) k_grad_pair_fill(const uint64_t* __restrict__ live,
+                                                       int nitem, const int64_t* __restrict__ poff,
+                                                       int32_t* __restrict__ plist) {
+  const int u = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
+  if (u >= v) return;
+  const uint64_t m = ((uint64_t)1 << u) | ((uint64_t)1 << v);
+  int32_t* __restrict__ out = plist + poff[orb_pair_id(u, v)];
+  int base = 0;
+  for (int it0 = 0; it0 < nitem; it0 += 64) {
+    const int it = it0 + lane;
+    const bool has = it < nitem && (live[it] & m) == m;
+    const uint64_t b = __ballot(has);
+    if (has) out[base + __popcll(b & ((1ull << lane) - 1))] = it;
+    base += __popcll(b);
+  }
+}
+
+struct GradLists {
+  const uint64_t* live;
+  const int32_t* list;    // [M][nitem] per-orbital lists
+  const int32_t* count;   // [M]
+  const int32_t* plist;   // pair lists, concatenated
+  const int64_t* poff;    // [npair + 1]
+  const int32_t* pcount;  // [npair]
+};
+
+// The candidate items of an element with orbitals in mask e: the shortest of
+// the inverted lists of its orbitals (ties: the lower orbital) and of its
+// orbital pairs (ties: a single orbital, then the earlier pair in
+// (lower, higher) order); an item of that list contributes only if its live
+// mask holds all of e.  Wave-uniform.
+__device__ inline const int32_t* grad_candidates(uint64_t e, int nitem, const GradLists& L,
+                                                 int* ncand) {
+  int o[4], d = 0;
+  for (uint64_t m = e; m; m &= m - 1) o[d++] = __builtin_ctzll(m);
+  int best = o[0], nb = L.count[o[0]];
+  for (int i = 1; i < d; ++i)
+    if (L.count[o[i]] < nb) best = o[i], nb = L.count[o[i]];
+  const int32_t* cand = L.list + (int64_t)best * nitem;
+  for (int i = 0; i < d; ++i)
+    for (int j = i + 1; j < d; ++j) {
+      const int pid = orb_pair_id(o[i], o[j]);
+      const int np = L.pcount[pid];
+      if (np < nb) nb = np, cand = L.plist + L.poff[pid];
+    }
+  *ncand = nb;
+  return cand;
+}
+
+// Row and column of entry x of a lower triangle numbered row by row
+// (x = i (i + 1) / 2 + j, j <= i).
+__device__ inline void tri_index(int64_t x, int* i, int* j) {
+  int a = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+  while ((int64_t)a * (a + 1) / 2 > x) --a;
+  while ((int64_t)(a + 1) * (a + 2) / 2 <= x) ++a;
+  *i = a;
+  *j = (int)(x - (int64_t)a * (a + 1) / 2);
+}
+
+// dE/dh_pq = sum_it w_it gamma_full(p, q), for p >= q, written to (p, q)
+// and (q, p).  One wave per element: lane l sums the candidate items l,
+// l + 64, ... (in ascending item order), then the lanes' sums meet in
+// wave_sum64 (a fixed order, so the result is bitwise reproducible).
 __global__ void __launch_bounds__(64) k_grad_h(const Item* __restrict__ items, int nitem,
                                                const int32_t* __restrict__ act, uint64_t occmask,
                                                int M, const double* __restrict__ w,
                                                const double* __restrict__ rdmp,
-                                               const int64_t* __restrict__ roff,
-                                               const uint64_t* __restrict__ live,
-                                               const int32_t* __restrict__ list,
-                                               const int32_t* __restrict__ count, double* out) {
-  const int x = blockIdx.x;
-  const int p = x / M, q = x % M;
+                                               const int64_t* __restrict__ roff, GradLists L,
+                                               double* out) {
+  int p, q;
+  tri_index(blockIdx.x, &p, &q);
   const int lane = threadIdx.x;
   const uint64_t e = ((uint64_t)1 << p) | ((uint64_t)1 << q);
-  const int v = grad_pivot(e, count);
-  const int nv = count[v];
-  const int32_t* __restrict__ cand = list + (int64_t)v * nitem;
+  int nv;
+  const int32_t* __restrict__ cand = grad_candidates(e, nitem, L, &nv);
   double acc = 0.0;
   for (int k = lane; k < nv; k += 64) {
     const int it = cand[k];
-    if (e & ~live[it]) continue;
+    if (e & ~L.live[it]) continue;
     const double wt = w[it];
     if (wt == 0.0) continue;
     const Item& I = items[it];
@@ -2790,36 +2880,40 @@ __global__ void __launch_bounds__(64) k_grad_h(const Item* __restrict__ items, i
     acc += wt * val;
   }
   acc = wave_sum64(acc);
-  if (lane == 0) out[x] = acc;
+  if (lane == 0) {
+    out[p * M + q] = acc;
+    out[q * M + p] = acc;
+  }
 }
 
-// dE/d(pq|rs) = sum_it w_it 1/2 Sym8(Gamma_full)_pqrs, one wave per element
-// as in k_grad_h (four elements per 256-thread block).  An element with an
+// dE/d(pq|rs) = sum_it w_it 1/2 Sym8(Gamma_full)_pqrs.  The value has the
+// 8-fold symmetry of the integrals, so it is formed once per orbit (p >= q,
+// r >= s, pair pq >= pair rs) and written to all eight positions; one wave
+// per orbit as in k_grad_h (four per 256-thread block).  An element with an
 // orbital outside every CASCI's live set, or with more expansion orbitals
 // than any tuple holds, finds an empty or non-matching candidate list.
 __global__ void __launch_bounds__(256) k_grad_g(const Item* __restrict__ items, int nitem,
                                                 const int32_t* __restrict__ act, uint64_t occmask,
                                                 int M, const double* __restrict__ w,
                                                 const double* __restrict__ rdmp,
-                                                const int64_t* __restrict__ roff,
-                                                const uint64_t* __restrict__ live,
-                                                const int32_t* __restrict__ list,
-                                                const int32_t* __restrict__ count, double* out) {
+                                                const int64_t* __restrict__ roff, GradLists L,
+                                                double* out) {
   const int64_t x = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t M2 = (int64_t)M * M;
-  if (x >= M2 * M2) return;  // whole waves
-  const int p = (int)(x / (M2 * M)), q = (int)((x / M2) % M), r = (int)((x / M) % M),
-            s = (int)(x % M);
+  const int64_t np = (int64_t)M * (M + 1) / 2;
+  if (x >= np * (np + 1) / 2) return;  // whole waves
+  int P, Q, p, q, r, s;
+  tri_index(x, &P, &Q);
+  tri_index(P, &p, &q);
+  tri_index(Q, &r, &s);
   const uint64_t e = ((uint64_t)1 << p) | ((uint64_t)1 << q) | ((uint64_t)1 << r) |
                      ((uint64_t)1 << s);
-  const int v = __builtin_amdgcn_readfirstlane(grad_pivot(e, count));
-  const int nv = count[v];
-  const int32_t* __restrict__ cand = list + (int64_t)v * nitem;
+  int nv;
+  const int32_t* __restrict__ cand = grad_candidates(e, nitem, L, &nv);
   double acc = 0.0;
   for (int k = lane; k < nv; k += 64) {
     const int it = cand[k];
-    if (e & ~live[it]) continue;
+    if (e & ~L.live[it]) continue;
     const double wt = w[it];
     if (wt == 0.0) continue;
     const Item& I = items[it];
@@ -2832,7 +2926,17 @@ __global__ void __launch_bounds__(256) k_grad_g(const Item* __restrict__ items, 
     acc += wt * 0.5 * sym_gamma2(p, q, r, s, cp, cq, cr, cs, rdmp + roff[it], I.kpad, I.npair);
   }
   acc = wave_sum64(acc);
-  if (lane == 0) out[x] = acc;
+  if (lane < 8) {
+    // lane l writes the permutation (bit 0: swap p q, bit 1: swap r s, bit 2: swap the pairs)
+    int a = p, b = q, c = r, d = s;
+    if (lane & 1) a = q, b = p;
+    if (lane & 2) c = s, d = r;
+    if (lane & 4) {
+      const int t0 = a, t1 = b;
+      a = c, b = d, c = t0, d = t1;
+    }
+    out[(((int64_t)a * M + b) * M + c) * M + d] = acc;
+  }
 }
 
 // RDMs of one whole-space CASCI: rdm1 = gamma, rdm2 = Sym8(Gamma).
@@ -3485,17 +3589,26 @@ void launch_mbe_weights(const BucketDev* buckets, int nbucket, int nitem, int ne
   hipLaunchKernelGGL(k_mbe_weights, dim3(nblk(nitem, 64)), dim3(64), 0, s, buckets, nbucket, nitem,
                      nexp, max_order, g, w);
 }
-void launch_grad(const Item* items, int nitem, const int32_t* act, uint64_t occmask, int M,
-                 const double* w, const double* rdmp, const int64_t* roff, uint64_t* live,
-                 int32_t* list, int32_t* count, double* dh, double* dg, hipStream_t s) {
+void launch_grad_index(const Item* items, int nitem, const int32_t* act, uint64_t occmask, int M,
+                       uint64_t* live, int32_t* list, int32_t* count, int32_t* pcount,
+                       int64_t* poff, hipStream_t s) {
   hipLaunchKernelGGL(k_grad_masks, dim3(nblk(nitem, 64)), dim3(64), 0, s, items, nitem, act,
                      occmask, live);
   hipLaunchKernelGGL(k_grad_index, dim3(M), dim3(64), 0, s, live, nitem, list, count);
-  hipLaunchKernelGGL(k_grad_h, dim3(M * M), dim3(64), 0, s, items, nitem, act, occmask, M, w, rdmp,
-                     roff, live, list, count, dh);
-  const int64_t M4 = (int64_t)M * M * M * M;
-  hipLaunchKernelGGL(k_grad_g, dim3(nblk(M4, 4)), dim3(256), 0, s, items, nitem, act, occmask, M,
-                     w, rdmp, roff, live, list, count, dg);
+  hipLaunchKernelGGL(k_grad_pair_count, dim3(M, M), dim3(64), 0, s, live, nitem, pcount);
+  hipLaunchKernelGGL(k_grad_pair_scan, dim3(1), dim3(64), 0, s, pcount, M * (M - 1) / 2, poff);
+}
+void launch_grad(const Item* items, int nitem, const int32_t* act, uint64_t occmask, int M,
+                 const double* w, const double* rdmp, const int64_t* roff, const uint64_t* live,
+                 const int32_t* list, const int32_t* count, const int32_t* pcount,
+                 const int64_t* poff, int32_t* plist, double* dh, double* dg, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_pair_fill, dim3(M, M), dim3(64), 0, s, live, nitem, poff, plist);
+  const GradLists L{live, list, count, plist, poff, pcount};
+  const int64_t np = (int64_t)M * (M + 1) / 2;  // p >= q
+  hipLaunchKernelGGL(k_grad_h, dim3((int)np), dim3(64), 0, s, items, nitem, act, occmask, M, w,
+                     rdmp, roff, L, dh);
+  hipLaunchKernelGGL(k_grad_g, dim3(nblk(np * (np + 1) / 2, 4)), dim3(256), 0, s, items, nitem,
+                     act, occmask, M, w, rdmp, roff, L, dg);
 }
 void launch_casci_rdm_out(const Item* items, int it, int n, const double* rdmp,
                           const int64_t* roff, double* rdm1, double* rdm2, hipStream_t s) {

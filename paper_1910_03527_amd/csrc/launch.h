@@ -158,11 +158,19 @@ void launch_rdm_reduce(const Item* items, int nitem, const int32_t* wlo, const i
                        hipStream_t s);
 void launch_mbe_weights(const BucketDev* buckets, int nbucket, int nitem, int nexp, int max_order,
                         const double* g, double* w, hipStream_t s);
-// dE/dh and dE/d(pq|rs) from the weighted RDMs; live [nitem], list
-// [M * nitem] and count [M] are workspace for the per-orbital item lists
+// dE/dh and dE/d(pq|rs) from the weighted RDMs, in two launches around a
+// host read of poff[M (M - 1) / 2] (the length of the pair lists).
+// launch_grad_index fills the workspace: live [nitem] masks, per-orbital
+// item lists list [M * nitem] and count [M], pair counts pcount
+// [M (M - 1) / 2] and offsets poff [M (M - 1) / 2 + 1]; launch_grad fills
+// the pair lists plist [poff[M (M - 1) / 2]] and sums the gradients.
+void launch_grad_index(const Item* items, int nitem, const int32_t* act, uint64_t occmask, int M,
+                       uint64_t* live, int32_t* list, int32_t* count, int32_t* pcount,
+                       int64_t* poff, hipStream_t s);
 void launch_grad(const Item* items, int nitem, const int32_t* act, uint64_t occmask, int M,
-                 const double* w, const double* rdmp, const int64_t* roff, uint64_t* live,
-                 int32_t* list, int32_t* count, double* dh, double* dg, hipStream_t s);
+                 const double* w, const double* rdmp, const int64_t* roff, const uint64_t* live,
+                 const int32_t* list, const int32_t* count, const int32_t* pcount,
+                 const int64_t* poff, int32_t* plist, double* dh, double* dg, hipStream_t s);
 void launch_casci_rdm_out(const Item* items, int it, int n, const double* rdmp,
                           const int64_t* roff, double* rdm1, double* rdm2, hipStream_t s);
 

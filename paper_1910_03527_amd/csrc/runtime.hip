@@ -2318,11 +2318,22 @@ int mbefci_mbe_backward(mbefci_ctx* c, const double* grad_out, double* d_h1, dou
                        P.max_order, d_g, d_w, c->stream);
     uint64_t occmask = 0;
     for (int i = 0; i < P.sp.nO; ++i) occmask |= (uint64_t)1 << P.sp.O[i];
+    const int M = P.norb, npair = M * (M - 1) / 2;
     uint64_t* d_live = arena<uint64_t>(c, "grad_live", P.nitem);
-    int32_t* d_list = arena<int32_t>(c, "grad_list", (size_t)P.norb * P.nitem);
-    int32_t* d_count = arena<int32_t>(c, "grad_count", P.norb);
-    launch_grad(P.d_items, P.nitem, P.act, occmask, P.norb, d_w, R.rdmp, R.roff, d_live, d_list,
-                d_count, d_h1, d_eri, c->stream);
+    int32_t* d_list = arena<int32_t>(c, "grad_list", (size_t)M * P.nitem);
+    int32_t* d_count = arena<int32_t>(c, "grad_count", M);
+    int32_t* d_pcount = arena<int32_t>(c, "grad_pcount", std::max(npair, 1));
+    int64_t* d_poff = arena<int64_t>(c, "grad_poff", npair + 1);
+    launch_grad_index(P.d_items, P.nitem, P.act, occmask, M, d_live, d_list, d_count, d_pcount,
+                      d_poff, c->stream);
+    HIPCHK(hipGetLastError());
+    int64_t nplist = 0;
+    HIPCHK(hipMemcpyAsync(&nplist, d_poff + npair, sizeof(int64_t), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    int32_t* d_plist = arena<int32_t>(c, "grad_plist", (size_t)std::max<int64_t>(nplist, 1));
+    launch_grad(P.d_items, P.nitem, P.act, occmask, M, d_w, R.rdmp, R.roff, d_live, d_list,
+                d_count, d_pcount, d_poff, d_plist, d_h1, d_eri, c->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
     sc.done();
