@@ -2184,7 +2184,6 @@ __global__ void __launch_bounds__(NT) k_pspace_eigen(
   static_assert(EXACT || NT / 4 >= PMAX, "four threads per column when forming Q");
   constexpr int PM = kMaxPspace;  // stride of the per-item arrays in global memory
   __shared__ double A[PMAX * (PMAX + 1) / 2];
-  __shared__ double Q[EXACT ? 1 : PMAX * PMAX];
   __shared__ uint64_t sa[PMAX], sb[PMAX];
   __shared__ double vv[PMAX], pw[PMAX], dd[PMAX], ee[PMAX], beta[PMAX], zz[PMAX], piv[PMAX];
   __shared__ double lo_hi[2];
@@ -2199,6 +2198,9 @@ __global__ void __launch_bounds__(NT) k_pspace_eigen(
   // the list holds only this class (checked again: a mismatch would overrun LDS)
   if (nd == 1 || n == 0 || n > PMAX || (nd == n) != EXACT) return;
   const ItemHam& H = hams[I.ham];
+  // Q is accumulated in place in the item's output rows (L2-resident):
+  // in LDS it would hold the CU to one workgroup
+  double* __restrict__ Q = pQ + (int64_t)it * PM * PM;
   for (int k = t; k < n; k += NT) {
     const int e = idx[k];  // an address of this item: 0 <= e < ndet
     uint64_t ma, mb;
@@ -2286,7 +2288,7 @@ __global__ void __launch_bounds__(NT) k_pspace_eigen(
   // reflectors below.
   // ---- Q = H_0 H_1 ... H_{n-3}, accumulated backwards from the identity
   if constexpr (!EXACT) {
-  for (int x = t; x < n * n; x += NT) Q[x] = (x / n == x % n) ? 1.0 : 0.0;
+  for (int x = t; x < n * n; x += NT) Q[(x / n) * PM + (x % n)] = (x / n == x % n) ? 1.0 : 0.0;
   __syncthreads();
   for (int k = n - 3; k >= 0; --k) {
     const int m = n - k - 1;
@@ -2299,7 +2301,7 @@ __global__ void __launch_bounds__(NT) k_pspace_eigen(
       double acc = 0.0;
       if (col < n) {
 #pragma unroll 4
-        for (int i = part; i < m; i += 4) acc += A[L(k + 1 + i, k)] * Q[(k + 1 + i) * n + col];
+        for (int i = part; i < m; i += 4) acc += A[L(k + 1 + i, k)] * Q[(k + 1 + i) * PM + col];
       }
       acc += __shfl_xor(acc, 1, 64);
       acc += __shfl_xor(acc, 2, 64);
@@ -2312,7 +2314,7 @@ __global__ void __launch_bounds__(NT) k_pspace_eigen(
       const int di = NT / m, dj = NT % m;
       int i = t / m, j = t % m;
       while (i < m) {
-        Q[(k + 1 + i) * n + (k + 1 + j)] -= A[L(k + 1 + i, k)] * pw[j];
+        Q[(k + 1 + i) * PM + (k + 1 + j)] -= A[L(k + 1 + i, k)] * pw[j];
         i += di;
         j += dj;
         if (j >= m) {
@@ -2371,10 +2373,8 @@ __global__ void __launch_bounds__(NT) k_pspace_eigen(
     }
   }
   __syncthreads();
-  // ---- outputs: Q (row = P position), T, the guess vectors
+  // ---- outputs: T and the guess vectors (Q is in place)
   if constexpr (!EXACT) {
-    double* __restrict__ Qo = pQ + (int64_t)it * PM * PM;
-    for (int x = t; x < n * n; x += NT) Qo[(x / n) * PM + (x % n)] = Q[x];
     double* __restrict__ To = pT + (int64_t)it * 2 * PM;
     for (int i = t; i < n; i += NT) {
       To[i] = dd[i];
@@ -2383,7 +2383,7 @@ __global__ void __launch_bounds__(NT) k_pspace_eigen(
     // u = Q z (row k: P position k)
     if (t < n) {
       double u = 0.0;
-      for (int j = 0; j < n; ++j) u += Q[t * n + j] * zz[j];
+      for (int j = 0; j < n; ++j) u += Q[t * PM + j] * zz[j];
       vv[t] = u;
     }
   } else if (t < 64) {  // EXACT
