@@ -111,6 +111,11 @@ def test_hubbard12_gradient_matches_oracle(ctx, hub12_grad):
     dh_o, dg_o, _, _ = ordm.mbe_gradient(p, gvec[0], gvec[1:], workers=min(16, os.cpu_count() or 1))
     assert np.max(np.abs(dh - dh_o)) < 1e-8
     assert np.max(np.abs(dg - dg_o)) < 1e-8
+    # each orbit of the integrals' 8-fold symmetry gets one value (and dh one
+    # per p >= q), so the gradients are exactly symmetric
+    assert np.array_equal(dh, dh.T)
+    for perm in ((1, 0, 2, 3), (0, 1, 3, 2), (2, 3, 0, 1)):
+        assert np.array_equal(dg, dg.transpose(perm)), perm
 
 
 def test_hubbard12_gradient_finite_differences(ctx, hub12_grad):
