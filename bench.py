@@ -294,6 +294,13 @@ def main():
     ap.add_argument("--kernel-replay", action="store_true",
                     help="profiling mode: a forward that stops after the guess sigma sweeps, then "
                          "only the sigma-sweep replays (every sigma launch does the same work)")
+    ap.add_argument("--steps-only", action="store_true",
+                    help="profiling mode: the warm-up and the timed steps only (no forward-only "
+                         "loop, per-launch leg, kernel re-timing or other workloads); with "
+                         "--steps 0 it runs the warm-up alone, so two profiles subtract to K steps")
+    ap.add_argument("--conv-tol", type=float, default=None,
+                    help="Davidson residual tolerance of the main workload (default: the "
+                         "library's 1e-6)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library drives one device per context and has "
@@ -320,7 +327,8 @@ def main():
     h1 = torch.as_tensor(prob.h1, dtype=torch.float64, device=dev)
     eri = torch.as_tensor(prob.eri, dtype=torch.float64, device=dev)
     ctx = Context(0, tile=args.tile, sigma_pass_mb=args.sigma_pass_mb,
-                  tune_cache=args.tune_cache)
+                  tune_cache=args.tune_cache,
+                  **({} if args.conv_tol is None else {"conv_tol": args.conv_tol}))
     if args.tune_only:
         ctx.mbe_forward(h1, eri, prob.occ, prob.ref, prob.exp, prob.max_order, prob.e_const)
         print(json.dumps({"mode": "tune-only", "ms_tune": ctx.last_stats["ms_tune"],
@@ -357,7 +365,12 @@ def main():
     for _ in range(args.steps):
         res = step()
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+    if args.steps_only:
+        print(json.dumps({"mode": "steps-only", "workload": args.workload, "steps": args.steps,
+                          "warmup": args.warmup, "ms_per_step": ms,
+                          "conv_tol": ctx.opts["conv_tol"]}), flush=True)
+        return
     t0 = time.perf_counter()
     for _ in range(args.steps):
         forward()
