@@ -84,6 +84,32 @@ def test_largest_orbital_count(ctx):
     assert np.max(np.abs(np.array(r["increments"]) - np.array(o["inc"]))) < 1e-9
 
 
+def test_largest_orbital_count_backward():
+    """The backward at M = 64 with orbital 63 in the expansion space (the top
+    bit of the 64-bit orbital masks, 2,016 orbital pairs) against the
+    oracle's gradient; the gradients are exactly symmetric.  The RDMs are
+    first order in the CI vector's error, hence the tight residual."""
+    from oracle import rdm as ordm
+    from paper_1910_03527_amd import Context
+    _log("M = 64 backward")
+    h1, g = W.synthetic(64, 5)
+    p = W.Problem("s64b", h1, g, 0.0, list(range(10)), [8, 9, 10, 11], [5, 6, 12, 63], 2)
+    gvec = [0.7, 1.0, -0.4]
+    c = Context(0, conv_tol=1e-10)
+    try:
+        c.mbe_forward(_dev(p.h1), _dev(p.eri), p.occ, p.ref, p.exp, p.max_order, p.e_const)
+        dh, dg = c.mbe_backward(gvec)
+        dh, dg = dh.cpu().numpy(), dg.cpu().numpy()
+    finally:
+        c.close()
+    dh_o, dg_o, _, _ = ordm.mbe_gradient(p, gvec[0], gvec[1:], workers=min(16, os.cpu_count() or 1))
+    assert np.max(np.abs(dh - dh_o)) < 1e-8
+    assert np.max(np.abs(dg - dg_o)) < 1e-8
+    assert np.max(np.abs(dg_o[63])) > 1e-6  # orbital 63 does enter
+    assert np.array_equal(dh, dh.T)
+    assert np.array_equal(dg, dg.transpose(2, 3, 0, 1))
+
+
 @pytest.mark.parametrize("n,na,nb", [(4, 2, 0), (5, 0, 3), (6, 1, 4), (7, 7, 2)])
 def test_unbalanced_spin_sectors(ctx, n, na, nb):
     _log("casci", n, na, nb)
