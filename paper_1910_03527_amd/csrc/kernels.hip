@@ -803,13 +803,15 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm_flat(const Item* __restrict
 // sigma_I = sum_{links (x,y,J,s) of Ia} s G_xy[J, Ib] + sum_{links of Ib} s G_xy[Ia, J]
 // One wave per 64-determinant segment of one alpha row (segments are
 // row-aligned), so the alpha string and its links are wave-uniform (scalar
-// loads) and the alpha-part reads of G are coalesced rows.
+// loads) and the alpha-part reads of G are coalesced rows.  Work units run
+// in reverse order: the contraction wrote G in unit order, so the part it
+// wrote last, still in the last-level cache, is read first.
 __global__ void __launch_bounds__(256) k_sigma_gather(const Item* __restrict__ items,
                                                       const Work* __restrict__ work,
                                                       const double* __restrict__ Garena,
                                                       double* __restrict__ Sarena, int64_t ntot,
                                                       const DavState* __restrict__ st, int slot) {
-  const Work wk = work[blockIdx.x];
+  const Work wk = work[gridDim.x - 1 - blockIdx.x];
   const Item& I = items[wk.item];
   const DavState& S = st[wk.item];
   if (!item_active(S, slot)) return;
