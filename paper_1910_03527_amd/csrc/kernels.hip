@@ -3373,10 +3373,11 @@ void launch_sigma_sym_gather(const Item* items, const Work* work, int nwork, con
 }
 
 void launch_sigma_gather(const Item* items, const Work* work, int nwork, const double* G,
-                         double* Sv, int64_t ntot, const DavState* st, int slot, hipStream_t s) {
+                         double* Sv, int64_t ntot, const DavState* st, int slot, int lds,
+                         hipStream_t s) {
   if (nwork > 0)
-    hipLaunchKernelGGL(k_sigma_gather, dim3(nwork), dim3(256), 0, s, items, work, G, Sv, ntot, st,
-                       slot);
+    hipLaunchKernelGGL(k_sigma_gather, dim3(nwork), dim3(256), lds, s, items, work, G, Sv, ntot,
+                       st, slot);
 }
 
 // ------------------------------------------------------- peak probes

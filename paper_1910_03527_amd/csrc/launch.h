@@ -26,8 +26,22 @@ void launch_hdiag(const Item* items, const Work* work, int nwork, const ItemHam*
 bool launch_sigma_dgemm(int n, int tn, const Item* items, const Work* work, int nwork,
                         const double* warena, const double* V, int64_t ntot, double* G,
                         const DavState* st, int slot, hipStream_t s);
+// lds: bytes of LDS reserved per workgroup (the kernel uses none), a cap on
+// the workgroups per CU: see gather_lds_bytes
 void launch_sigma_gather(const Item* items, const Work* work, int nwork, const double* G,
-                         double* Sv, int64_t ntot, const DavState* st, int slot, hipStream_t s);
+                         double* Sv, int64_t ntot, const DavState* st, int slot, int lds,
+                         hipStream_t s);
+// The gather's LDS reservation for items whose row block of G (npair rows
+// of the row stride) takes `row_block` bytes.  Each workgroup reads one
+// row block scattered; with many resident workgroups the L2 re-fetches it.
+// Measured (8 workgroups per CU uncapped): 112 KB blocks (10 orbitals) take
+// five per CU, blocks of 1 MB and more (13-14 orbitals) three; smaller
+// blocks keep every workgroup.
+inline int gather_lds_bytes(int64_t row_block) {
+  if (row_block >= ((int64_t)1 << 20)) return 53248;  // three workgroups per CU
+  if (row_block >= 96 * 1024) return 32768;           // five
+  return 0;
+}
 // point-group blocked sigma (items with a SymInfo): the per-class contraction
 // (npc = the class's pair count rounded up to 16, sym_npc; work units carry
 // class and alpha irrep in Work.pad_ = s * 8 + a') and the gather (work units

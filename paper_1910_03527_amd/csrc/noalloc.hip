@@ -216,7 +216,8 @@ int noalloc_sigma(int device, int n, int na, int nb, const double* h1, const dou
       *why = "no sigma kernel for n=" + std::to_string(n);
       return MBEFCI_EUNSUPPORTED;
     }
-    launch_sigma_gather(items, segs, L.nsegs, G, sigma, I.ndet, st, 0, s);
+    launch_sigma_gather(items, segs, L.nsegs, G, sigma, I.ndet, st, 0,
+                        gather_lds_bytes((int64_t)I.npair * g_stride(I.Nb) * 8), s);
     launch_axpy_out(sigma, sigma, c, e_core, I.ndet, s);
   } else {
     double* diag = (double*)at(L.diag);

@@ -128,6 +128,7 @@ struct Plan {
   Work* d_sym_blocks = nullptr;
   bool has_sym = false;
   int nitem = 0, nchunk = 0, nblock = 0, nseg = 0;
+  int gather_lds = 0;  // LDS reserved per gather workgroup (an occupancy cap), gather_lds_bytes
   int64_t ntot = 0, gtot = 0, wtot = 0;
   int nsingle = 0;
   int64_t ndet_total = 0;
@@ -806,6 +807,20 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
   P.nchunk = (int)P.chunks.size();
   P.nblock = (int)P.blocks.size();
   P.nseg = (int)P.segs.size();
+  {
+    // the gather's occupancy follows the row block (npair x row stride) of
+    // the items that hold most of its segments
+    std::map<int64_t, int64_t> segs_by_block;
+    for (int i = 0; i < P.nitem; ++i) {
+      const Item& I = P.items[i];
+      if (P.seg_hi[i] > P.seg_lo[i])
+        segs_by_block[(int64_t)I.npair * g_stride(I.Nb) * 8] += P.seg_hi[i] - P.seg_lo[i];
+    }
+    int64_t best = 0, most = -1;
+    for (const auto& kv : segs_by_block)
+      if (kv.second > most) best = kv.first, most = kv.second;
+    P.gather_lds = gather_lds_bytes(best);
+  }
 
   bool grown = false;
   P.d_items = arena<Item>(c, "items", P.nitem, &grown);
@@ -950,7 +965,7 @@ void sigma_launch(mbefci_ctx* c, Plan& P, const SigmaLaunch& L, int slot) {
       throw Error(MBEFCI_EUNSUPPORTED, "no sigma kernel for n=" + std::to_string(g.n));
   } else if (L.kind == 1) {
     launch_sigma_gather(P.d_items, P.d_segs + L.lo, L.cnt, P.G, P.S, P.ntot, P.st, slot,
-                        c->stream);
+                        P.gather_lds, c->stream);
   } else if (L.kind == 2) {
     const auto& sg = P.sym_groups[L.group];
     if (!launch_sigma_sym_dgemm(sg.npc, P.d_items, sg.d_tiles + L.lo, L.cnt, P.W, P.V, P.ntot,
