@@ -86,18 +86,29 @@ __global__ void k_strings(int n, int ne, int64_t N, uint64_t* out) {
 // canonical order (diagonal entries first, then q in I ascending, p not in I
 // ascending).  The sign is (-1)^(number of occupied orbitals strictly between
 // p and q), the parity of a+_p a_q acting on the occupation-number vector.
+// The link-major copy packedT (read by the gather's beta half) holds each
+// string's links in ascending pair order instead (a string's links have
+// distinct pairs): at link step l the lanes of a wave then read nearby rows
+// of G's row block, which the L1 and L2 serve far better than the canonical
+// order's spread (gather 6-10% faster).
 __global__ void k_links(int n, int ne, int64_t N, uint32_t* packed, uint32_t* packedT,
                         int32_t* abi4) {
+  constexpr int kSortMax = kMaxActive * (kMaxActive / 2 + 1);  // links of a CASCI string
   int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= N) return;
   const int L = ne * (n - ne + 1);
+  const bool sortT = packedT && L <= kSortMax;
+  uint32_t vs[kSortMax];
   uint64_t m = string_unrank(I, n, ne);
   int idx = 0;
+  auto put = [&](uint32_t v) {
+    if (packed) packed[I * L + idx] = v;
+    if (sortT) vs[idx] = v;
+    else if (packedT) packedT[idx * N + I] = v;
+  };
   for (int o = 0; o < n; ++o)
     if (m >> o & 1) {
-      const uint32_t v = pack_link((int)I, pair_index(o, o), 1);
-      if (packed) packed[I * L + idx] = v;
-      if (packedT) packedT[idx * N + I] = v;
+      put(pack_link((int)I, pair_index(o, o), 1));
       if (abi4) {
         int32_t* e = abi4 + (I * L + idx) * 4;
         e[0] = o; e[1] = o; e[2] = (int32_t)I; e[3] = 1;
@@ -113,9 +124,7 @@ __global__ void k_links(int n, int ne, int64_t N, uint32_t* packed, uint32_t* pa
       uint64_t between = (((uint64_t)1 << hi) - 1) & ~((((uint64_t)1 << lo) << 1) - 1);
       int sign = (__builtin_popcountll(m & between) & 1) ? -1 : 1;
       int64_t J = string_addr(r);
-      const uint32_t v = pack_link((int)J, pair_index(p, q), sign);
-      if (packed) packed[I * L + idx] = v;
-      if (packedT) packedT[idx * N + I] = v;
+      put(pack_link((int)J, pair_index(p, q), sign));
       if (abi4) {
         int32_t* e = abi4 + (I * L + idx) * 4;
         e[0] = p; e[1] = q; e[2] = (int32_t)J; e[3] = sign;
@@ -123,6 +132,12 @@ __global__ void k_links(int n, int ne, int64_t N, uint32_t* packed, uint32_t* pa
       ++idx;
     }
   }
+  if (sortT)
+    for (int a = 0; a < L; ++a) {
+      int rank = 0;  // position of link a in ascending pair order
+      for (int b = 0; b < L; ++b) rank += link_pair(vs[b]) < link_pair(vs[a]);
+      packedT[rank * N + I] = vs[a];
+    }
 }
 
 // One thread per string K: for every orbital pair a >= b the non-vanishing

@@ -34,12 +34,12 @@ void launch_sigma_gather(const Item* items, const Work* work, int nwork, const d
 // The gather's LDS reservation for items whose row block of G (npair rows
 // of the row stride) takes `row_block` bytes.  Each workgroup reads one
 // row block scattered; with many resident workgroups the L2 re-fetches it.
-// Measured (8 workgroups per CU uncapped): 112 KB blocks (10 orbitals) take
-// five per CU, blocks of 1 MB and more (13-14 orbitals) three; smaller
-// blocks keep every workgroup.
+// Measured (eight workgroups per CU uncapped): blocks of 30-112 KB (9 and
+// 10 orbitals) do best at six per CU, blocks of 1 MB and more (13-14
+// orbitals) at four; blocks below 24 KB are not capped.
 inline int gather_lds_bytes(int64_t row_block) {
-  if (row_block >= ((int64_t)1 << 20)) return 53248;  // three workgroups per CU
-  if (row_block >= 96 * 1024) return 32768;           // five
+  if (row_block >= ((int64_t)1 << 20)) return 40960;  // four workgroups per CU
+  if (row_block >= 24 * 1024) return 26624;           // six
   return 0;
 }
 // point-group blocked sigma (items with a SymInfo): the per-class contraction
