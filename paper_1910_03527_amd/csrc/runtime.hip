@@ -458,9 +458,16 @@ const SymTab& sym_tab(mbefci_ctx* c, int n, int na, int nb, const int* osym, int
   std::vector<int32_t> pA, pB;
   T.La = make_tables(A, na, lA, pA, false);
   T.Lb = make_tables(B, nb, lB, pB, true);
+  // link-major beta copy for the gather, each string's links in ascending
+  // pair position (class-major): a wave's lanes then read nearby rows of G
   std::vector<uint32_t> lBT(lB.size());
-  for (int64_t k = 0; k < T.Nb; ++k)
-    for (int l = 0; l < T.Lb; ++l) lBT[(int64_t)l * T.Nb + k] = lB[k * T.Lb + l];
+  std::vector<uint32_t> row(T.Lb);
+  for (int64_t k = 0; k < T.Nb; ++k) {
+    std::copy(lB.begin() + k * T.Lb, lB.begin() + (k + 1) * T.Lb, row.begin());
+    std::stable_sort(row.begin(), row.end(),
+                     [](uint32_t x, uint32_t y) { return link_pair(x) < link_pair(y); });
+    for (int l = 0; l < T.Lb; ++l) lBT[(int64_t)l * T.Nb + k] = row[l];
+  }
   // one device block: strings, links, pair tables, SymInfo (256-byte aligned parts)
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t o_sa = 0, o_sb = o_sa + al(8 * T.Na), o_la = o_sb + al(8 * T.Nb),
