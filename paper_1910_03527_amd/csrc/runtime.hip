@@ -14,9 +14,12 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <exception>
+#include <iterator>
 #include <map>
 #include <memory>
 #include <stdexcept>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -1449,6 +1452,59 @@ RdmOut rdm_pass(mbefci_ctx* c, Plan& P) {
 }  // namespace
 
 // =================================================================== C ABI
+namespace {
+// Host threads for n independent items: one per 16,384 items, at most 16
+// (the host share of one GPU) and at most the hardware's count.
+int host_threads(int64_t n) {
+  const int hw = std::max(1u, std::thread::hardware_concurrency());
+  return (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)16, (int64_t)hw, n / 16384}));
+}
+// f(t, lo, hi) on nth contiguous chunks of [0, n), chunk 0 on this thread;
+// an exception of any chunk is rethrown here after every thread has ended.
+template <class F>
+void run_chunks(int64_t n, int nth, F f) {
+  std::vector<std::thread> pool;
+  std::vector<std::exception_ptr> err(nth);
+  const int64_t per = (n + nth - 1) / nth;
+  auto body = [&f, &err](int t, int64_t lo, int64_t hi) {
+    try {
+      f(t, lo, hi);
+    } catch (...) {
+      err[t] = std::current_exception();
+    }
+  };
+  for (int t = 1; t < nth; ++t) {
+    const int64_t lo = std::min(n, t * per), hi = std::min(n, lo + per);
+    pool.emplace_back(body, t, lo, hi);
+  }
+  body(0, 0, std::min(n, per));
+  for (auto& th : pool) th.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+}
+// The sorted union of sorted, duplicate-free lists: pairwise merges, each
+// round's merges on threads of their own.
+std::vector<uint64_t> merge_unique(std::vector<std::vector<uint64_t>>& lists) {
+  if (lists.empty()) return {};
+  while (lists.size() > 1) {
+    const int64_t half = (int64_t)(lists.size() / 2);
+    std::vector<std::vector<uint64_t>> out(half + lists.size() % 2);
+    run_chunks(half, (int)std::max<int64_t>(1, half), [&](int, int64_t lo, int64_t hi) {
+      for (int64_t i = lo; i < hi; ++i) {
+        const auto& a = lists[2 * i];
+        const auto& b = lists[2 * i + 1];
+        std::vector<uint64_t>& m = out[i];
+        m.reserve(a.size() + b.size());
+        std::set_union(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(m));
+      }
+    });
+    if (lists.size() % 2) out[half].swap(lists.back());
+    lists.swap(out);
+  }
+  return std::move(lists[0]);
+}
+}  // namespace
+
 extern "C" {
 
 void mbefci_default_opts(mbefci_opts* o) {
@@ -2161,7 +2217,7 @@ int mbefci_mbe_screened(mbefci_ctx* c, const mbefci_problem* pb, const mbefci_sc
     for (;;) {
       const bool run = k <= K && !level.empty();
       if (!run && !first) break;
-      std::sort(level.begin(), level.end());
+      if (!std::is_sorted(level.begin(), level.end())) std::sort(level.begin(), level.end());
       level.erase(std::unique(level.begin(), level.end()), level.end());
       // the order's tuples are solved in chunks of bounded size (items and
       // determinants), so that an order of any width fits the device; their
@@ -2255,26 +2311,41 @@ int mbefci_mbe_screened(mbefci_ctx* c, const mbefci_problem* pb, const mbefci_sc
       // second computed one (the parent P != Q).  Candidates come from the
       // significant tuples; each keeps its place if at least two of its
       // order-k sub-tuples were computed.  `level` is sorted.
-      std::vector<uint64_t> next;
-      for (int64_t i = 0; i < n; ++i) {
-        if (!(std::fabs(inc[i]) > threshold(level[i]))) continue;
-        for (int p : xs) {
-          if (level[i] >> p & 1) continue;
-          const uint64_t child = level[i] | ((uint64_t)1 << p);
-          if (!structural(child)) next.push_back(child);
+      // Host threads (at most 16) take contiguous chunks of the parents, then
+      // of the candidates; the result, sorted and unique, does not depend on
+      // their number.
+      const int nth = host_threads(n);
+      std::vector<std::vector<uint64_t>> part(nth);
+      run_chunks(n, nth, [&](int t, int64_t lo, int64_t hi) {
+        std::vector<uint64_t>& out = part[t];
+        for (int64_t i = lo; i < hi; ++i) {
+          if (!(std::fabs(inc[i]) > threshold(level[i]))) continue;
+          for (int p : xs) {
+            if (level[i] >> p & 1) continue;
+            const uint64_t child = level[i] | ((uint64_t)1 << p);
+            if (!structural(child)) out.push_back(child);
+          }
         }
-      }
-      std::sort(next.begin(), next.end());
-      next.erase(std::unique(next.begin(), next.end()), next.end());
+        std::sort(out.begin(), out.end());
+        out.erase(std::unique(out.begin(), out.end()), out.end());
+      });
+      std::vector<uint64_t> next = merge_unique(part);
+      std::vector<char> keep(next.size());
+      run_chunks((int64_t)next.size(), host_threads((int64_t)next.size()),
+                 [&](int, int64_t lo, int64_t hi) {
+                   for (int64_t i = lo; i < hi; ++i) {
+                     const uint64_t child = next[i];
+                     int computed = 0;
+                     for (uint64_t x = child; x && computed < 2; x &= x - 1) {
+                       const uint64_t sub = child & ~(x & (~x + 1));
+                       if (std::binary_search(level.begin(), level.end(), sub)) ++computed;
+                     }
+                     keep[i] = computed >= 2;
+                   }
+                 });
       size_t kept = 0;
-      for (uint64_t child : next) {
-        int computed = 0;
-        for (uint64_t x = child; x && computed < 2; x &= x - 1) {
-          const uint64_t sub = child & ~(x & (~x + 1));
-          if (std::binary_search(level.begin(), level.end(), sub)) ++computed;
-        }
-        if (computed >= 2) next[kept++] = child;
-      }
+      for (size_t i = 0; i < next.size(); ++i)
+        if (keep[i]) next[kept++] = next[i];
       next.resize(kept);
       level.swap(next);
       ++k;
