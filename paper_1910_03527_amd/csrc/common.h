@@ -33,6 +33,13 @@ __host__ __device__ inline int pair_index(int p, int q) {
   int a = p > q ? p : q, b = p > q ? q : p;
   return a * (a + 1) / 2 + b;
 }
+// index of the off-diagonal pair a > b among the n (n - 1) / 2 such pairs
+__host__ __device__ inline int offdiag_index(int a, int b) { return a * (a - 1) / 2 + b; }
+// Active spaces of up to kFoldMax orbitals: the sigma contraction sums the
+// diagonal pairs' part of sigma itself and G holds only the off-diagonal pair
+// rows; larger ones keep every pair row in G (their contraction kernels have
+// no register room for the epilogue).
+constexpr int kFoldMax = 10;
 
 // Load through the global address space (pointers read from device structs
 // are generic; this keeps the loads off the flat path).

@@ -86,11 +86,15 @@ __global__ void k_strings(int n, int ne, int64_t N, uint64_t* out) {
 // canonical order (diagonal entries first, then q in I ascending, p not in I
 // ascending).  The sign is (-1)^(number of occupied orbitals strictly between
 // p and q), the parity of a+_p a_q acting on the occupation-number vector.
-// The link-major copy packedT (read by the gather's beta half) holds each
-// string's links in ascending pair order instead (a string's links have
-// distinct pairs): at link step l the lanes of a wave then read nearby rows
-// of G's row block, which the L1 and L2 serve far better than the canonical
-// order's spread (gather 6-10% faster).
+// abi4 lists (p, q, J, s).  The packed tables are the sigma gather's.  Up
+// to kFoldMax orbitals an off-diagonal entry carries G's row
+// offdiag_index(max(p, q), min(p, q)) (the diagonal entries, first in packed,
+// carry pair_index(o, o) and the gather skips them) and the link-major copy
+// packedT holds only the L - ne off-diagonal links; above, entries carry
+// pair_index and packedT holds all L links.  packedT orders each string's
+// links by ascending pair field (a string's links have distinct pairs): at
+// link step l the lanes of a wave then read nearby rows of G's row block,
+// which the L1 and L2 serve far better than the canonical order's spread.
 __global__ void k_links(int n, int ne, int64_t N, uint32_t* packed, uint32_t* packedT,
                         int32_t* abi4) {
   constexpr int kSortMax = kMaxActive * (kMaxActive / 2 + 1);  // links of a CASCI string
@@ -98,13 +102,15 @@ __global__ void k_links(int n, int ne, int64_t N, uint32_t* packed, uint32_t* pa
   if (I >= N) return;
   const int L = ne * (n - ne + 1);
   const bool sortT = packedT && L <= kSortMax;
+  const bool fold = n <= kFoldMax;  // the gather's layout of G (see k_sigma_gather)
+  const int nd = fold ? ne : 0;     // leading diagonal links left out of packedT
   uint32_t vs[kSortMax];
   uint64_t m = string_unrank(I, n, ne);
   int idx = 0;
   auto put = [&](uint32_t v) {
     if (packed) packed[I * L + idx] = v;
     if (sortT) vs[idx] = v;
-    else if (packedT) packedT[idx * N + I] = v;
+    else if (packedT && idx >= nd) packedT[(idx - nd) * N + I] = v;
   };
   for (int o = 0; o < n; ++o)
     if (m >> o & 1) {
@@ -124,7 +130,7 @@ __global__ void k_links(int n, int ne, int64_t N, uint32_t* packed, uint32_t* pa
       uint64_t between = (((uint64_t)1 << hi) - 1) & ~((((uint64_t)1 << lo) << 1) - 1);
       int sign = (__builtin_popcountll(m & between) & 1) ? -1 : 1;
       int64_t J = string_addr(r);
-      put(pack_link((int)J, pair_index(p, q), sign));
+      put(pack_link((int)J, fold ? offdiag_index(hi, lo) : pair_index(hi, lo), sign));
       if (abi4) {
         int32_t* e = abi4 + (I * L + idx) * 4;
         e[0] = p; e[1] = q; e[2] = (int32_t)J; e[3] = sign;
@@ -132,10 +138,10 @@ __global__ void k_links(int n, int ne, int64_t N, uint32_t* packed, uint32_t* pa
       ++idx;
     }
   }
-  if (sortT)
-    for (int a = 0; a < L; ++a) {
-      int rank = 0;  // position of link a in ascending pair order
-      for (int b = 0; b < L; ++b) rank += link_pair(vs[b]) < link_pair(vs[a]);
+  if (sortT)  // links nd..L-1 in ascending pair field (distinct within a string)
+    for (int a = nd; a < L; ++a) {
+      int rank = 0;
+      for (int b = nd; b < L; ++b) rank += link_pair(vs[b]) < link_pair(vs[a]);
       packedT[rank * N + I] = vs[a];
     }
 }
@@ -397,6 +403,24 @@ constexpr int64_t binom_c(int n, int k) {
   return r;
 }
 
+// Up to kFoldMax orbitals the diagonal pairs kk need no row of G: E_kk only counts occupations, so
+// their part of sigma, sum_k n_k(I) G_kk[I] with n_k(I) = n_k(Ia) + n_k(Ib),
+// is summed in the contraction's epilogue and written to sigma, and the
+// gather adds the off-diagonal links to it.  The contraction's output rows
+// are the off-diagonal pairs a > b first (row offdiag_index(a, b), the row of
+// G, which the gather's link tables carry), then padding, then the n
+// diagonal pairs in the last n rows of the last 16-row block (row
+// nrows - n + k: pair kk).  That block's wave, which sums the diagonal part,
+// has few or no G rows to store, so the waves stay balanced.
+// pair_index of output row r (nrows rows, n orbitals; -1: padding)
+__device__ inline int out_row_pair(int r, int n, int nrows) {
+  if (r >= nrows - n) return pair_index(r - (nrows - n), r - (nrows - n));
+  if (r >= n * (n - 1) / 2) return -1;
+  int a = 1;
+  while ((a + 1) * a / 2 <= r) ++a;
+  return pair_index(a, r - a * (a - 1) / 2);
+}
+
 // With 32-column tiles of up to 10 orbitals the pair-table entries stay in
 // registers and the kernel is compiled for four waves per SIMD (128 registers
 // per lane, accumulators included), which those shapes reach without
@@ -417,6 +441,277 @@ constexpr bool dgemm_reg_entries(int nact, int tn, int nt) {
 
 template <int NACT, int TN, int NT = dgemm_threads(NACT)>
 __global__ void __launch_bounds__(NT, dgemm_reg_entries(NACT, TN, NT) ? 4 : 1) k_sigma_dgemm(
+    const Item* __restrict__ items, const Work* __restrict__ work,
+    const double* __restrict__ warena, const double* __restrict__ V, int64_t ntot,
+    double* __restrict__ Garena, double* __restrict__ Sarena, const DavState* __restrict__ st,
+    int slot) {
+  constexpr int NP = NACT * (NACT + 1) / 2;
+  constexpr int KPAD = (NP + 15) / 16 * 16;
+  constexpr int KS = (NP + 3) / 4;       // MFMA k-steps (4 pair rows per step)
+  constexpr int KR = KS * 4;             // D+ rows held in LDS (zero beyond NP)
+  constexpr int NRB = KPAD / 16;         // 16-row blocks of G
+  constexpr int NW = NT / 64;            // waves per workgroup
+  constexpr int NCB = TN / 16;           // 16-column blocks per tile
+  constexpr int NCG = (NW >= 16 && NCB % 2 == 0) ? 2 : 1;  // column groups of waves
+  constexpr int NRG = NW / NCG;          // row groups of waves
+  constexpr int NCBW = NCB / NCG;        // column blocks per wave
+  constexpr int RBW = (NRB + NRG - 1) / NRG;  // row blocks per wave
+  constexpr int NSUB = NT / TN;          // row groups of the D+ build
+  constexpr int NPER = (NP + NSUB - 1) / NSUB;
+  constexpr int LDT = TN + 1;            // padded LDS row (doubles)
+  constexpr int CMAX = (int)binom_c(NACT, NACT / 2);  // largest string count for NACT
+  constexpr int CPT = (CMAX + NT - 1) / NT;           // c-row doubles per thread
+  constexpr int TPT = (NP * TN + NT - 1) / NT;        // beta-table entries per thread
+  constexpr bool EREG = dgemm_reg_entries(NACT, TN, NT);  // the launch-bounds rule
+  constexpr int NO = NP - NACT;          // off-diagonal pairs: the rows of G
+  static_assert(NACT <= kFoldMax, "larger active spaces take k_sigma_dgemm_pairrows");
+  __shared__ double Ds[KR * LDT];
+  __shared__ int32_t Tb[EREG ? 1 : NP * TN];
+  __shared__ double Cr[CMAX];
+  __shared__ uint32_t occB[TN];          // occupations of the work unit's beta strings
+
+  const Work wk = work[blockIdx.x];
+  const Item& I = items[wk.item];
+  const DavState& S = st[wk.item];
+  if (!item_active(S, slot)) return;
+  const int vs = vec_slot(S, slot);
+  const double* __restrict__ c = V + (int64_t)vs * ntot + I.off;
+  double* __restrict__ G = Garena + I.goff;
+  const int Na = I.Na, Nb = I.Nb;
+  const int32_t* __restrict__ pA = I.pairA;
+  const int32_t* __restrict__ pB = I.pairB;
+
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int col = t % TN;
+  const int sub = (TN >= 64) ? __builtin_amdgcn_readfirstlane(t / TN) : t / TN;
+
+  const int blk = wk.begin / Na;          // every work unit stays inside one beta block
+  const int Kb0 = blk * TN;
+  const int Kb = Kb0 + col;
+  const double keep = Kb < Nb ? 1.0 : 0.0;  // ragged end of the row: zero columns
+  const int Kbc = Kb < Nb ? Kb : Nb - 1;
+  const double* __restrict__ ca = c + Kbc;  // alpha source of D+: ca[Ja * Nb]
+  for (int x = t; x < TN; x += NT) occB[x] = Kb0 + x < Nb ? (uint32_t)ldg(I.strB + Kb0 + x) : 0u;
+
+  // Row blocks rb = wrot + NRG r and column blocks cg NCBW .. of this wave.
+  // When the 16-row blocks of G do not come in multiples of NRG some waves
+  // have one block fewer; rotating the assignment by workgroup spreads those
+  // idle slots over the SIMDs.
+  const int cg = NCG == 1 ? 0 : wave / NRG;
+  const int wrot = ((NCG == 1 ? wave : wave % NRG) + (int)blockIdx.x) % NRG;
+  // W rows of this wave's row blocks, as MFMA A operands: lane l holds
+  // W[rb*16 + l%16][ks*4 + l/16] (B operand: lane l holds D+[ks*4 + l/16][l%16])
+  double wreg[RBW][KS];
+  const double* __restrict__ W = warena + I.woff;
+#pragma unroll
+  for (int r = 0; r < RBW; ++r) {
+    const int rb = wrot + NRG * r;
+    const int wr = rb < NRB ? out_row_pair(rb * 16 + (lane & 15), NACT, KPAD) : -1;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+      wreg[r][ks] = wr >= 0 ? ldg(W + wr * KPAD + ks * 4 + (lane >> 4)) : 0.0;
+  }
+  // This thread's beta pair-table entries: slot i is pair sub + NSUB i of
+  // column col (x = t + NT i has x / TN = sub + NSUB i and x % TN = col),
+  // the slots it writes in every tile's D+.  Then the zero padding rows of D+.
+  static_assert(TPT == NPER, "one pair-table entry per D+ slot of a thread");
+  // With EREG the entries stay in registers, packed: the Cr position jb of
+  // slot i in byte i % 4 of jbp[i / 4], its sign and non-zero flag in bit i
+  // of sgb and nzb (at most 10 orbitals: jb < 256).
+  constexpr int NJP = (NPER + 3) / 4;
+  uint32_t jbp[NJP], sgb = 0, nzb = 0;
+#pragma unroll
+  for (int q = 0; q < NJP; ++q) jbp[q] = 0;
+#pragma unroll
+  for (int i = 0; i < NPER; ++i) {
+    const int ab = sub + NSUB * i;
+    const int32_t e = ab < NP ? ldg(pB + ab * Nb + Kbc) : 0;
+    if constexpr (EREG) {
+      jbp[i / 4] |= (uint32_t)(e ? (e >> 1) - 1 : 0) << (8 * (i % 4));
+      sgb |= (uint32_t)(e & 1) << i;
+      nzb |= (uint32_t)(e != 0) << i;
+    } else if (ab < NP) {
+      Tb[t + NT * i] = e;
+    }
+  }
+  for (int x = NP * LDT + t; x < KR * LDT; x += NT) Ds[x] = 0.0;
+
+  // Software pipeline over the tiles of the work unit: the alpha pair-table
+  // entries of tile i+1 are loaded while tile i builds D+, and the c row and
+  // alpha-half values of tile i+1 while tile i runs its MFMAs.
+  int32_t ea[NPER];   // alpha pair-table entries (only while their values are loaded)
+  uint32_t sga = 0, nza = 0;  // their signs and non-zero flags, bit i
+  double ga[NPER];    // c values they address (alpha half of D+)
+  double cr[CPT];     // this thread's share of the c row Ka
+  // The alpha entries are wave-uniform per row (scalar loads): with TN = 32
+  // a wave covers the two rows 2*wave and 2*wave+1 of each row group.
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  auto load_entries = [&](int ka, int32_t (&e)[NPER]) {
+    const int32_t* __restrict__ pa = pA + ka * NP;
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) {
+      if constexpr (TN >= 64) {
+        const int ab = sub + NSUB * i;
+        e[i] = ab < NP ? ldc(pa + ab) : 0;
+      } else {
+        static_assert(TN == 32, "tile width 32, 64 or 128");
+        const int ab0 = 2 * wave_u + NSUB * i;
+        const int32_t e0 = ab0 < NP ? ldc(pa + ab0) : 0;
+        const int32_t e1 = ab0 + 1 < NP ? ldc(pa + ab0 + 1) : 0;
+        e[i] = lane < 32 ? e0 : e1;
+      }
+    }
+  };
+  auto load_values = [&](int ka) {
+    if constexpr (EREG) {
+      sga = 0;
+      nza = 0;
+    }
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) {
+      ga[i] = ea[i] ? ldg(ca + ((ea[i] >> 1) - 1) * Nb) : 0.0;
+      if constexpr (EREG) {
+        sga |= (uint32_t)(ea[i] & 1) << i;
+        nza |= (uint32_t)(ea[i] != 0) << i;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const int x = t + NT * j;
+      cr[j] = x < Nb ? ldg(c + ka * Nb + x) : 0.0;
+    }
+  };
+  load_entries(wk.begin - blk * Na, ea);
+  load_values(wk.begin - blk * Na);
+
+  for (int tile = wk.begin; tile < wk.end; ++tile) {
+    const int Ka = tile - blk * Na;              // uniform
+    const bool more = tile + 1 < wk.end;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j)
+      if (t + NT * j < Nb) Cr[t + NT * j] = cr[j];
+    // the next tile's alpha entries: for the register-entry kernels after the
+    // D+ build (their registers are short), else ahead of it
+    int32_t en[EREG ? 1 : NPER];
+    if constexpr (!EREG) {
+      if (more) {
+        load_entries(Ka + 1, en);
+      } else {
+#pragma unroll
+        for (int i = 0; i < NPER; ++i) en[i] = 0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) {
+      const int ab = sub + NSUB * i;
+      if (ab < NP) {
+        int jb;
+        double fb;
+        if constexpr (EREG) {
+          jb = (jbp[i / 4] >> (8 * (i % 4))) & 0xFF;
+          fb = (nzb >> i & 1) ? ((sgb >> i & 1) ? -keep : keep) : 0.0;
+        } else {
+          const int32_t e = Tb[t + NT * i];
+          jb = e ? (e >> 1) - 1 : 0;
+          fb = e ? ((e & 1) ? -keep : keep) : 0.0;
+        }
+        double fa;
+        if constexpr (EREG) fa = (nza >> i & 1) ? ((sga >> i & 1) ? -keep : keep) : 0.0;
+        else fa = ea[i] ? ((ea[i] & 1) ? -keep : keep) : 0.0;
+        Ds[ab * LDT + col] = fa * ga[i] + fb * Cr[jb];
+      }
+    }
+    __syncthreads();
+    if (more) {
+      if constexpr (EREG) {
+        load_entries(Ka + 1, ea);
+      } else {
+#pragma unroll
+        for (int i = 0; i < NPER; ++i) ea[i] = en[i];
+      }
+      load_values(Ka + 1);
+    }
+#pragma unroll
+    for (int r = 0; r < RBW; ++r) {
+      const int rb = wrot + NRG * r;
+      if (rb >= NRB) continue;
+      double4_t acc[NCBW];
+#pragma unroll
+      for (int cb2 = 0; cb2 < NCBW; ++cb2) acc[cb2] = (double4_t){0.0, 0.0, 0.0, 0.0};
+      // B operands double-buffered in registers: the LDS reads of k-step
+      // ks+1 are issued before the MFMAs of k-step ks
+      double bq[2][NCBW];
+      const double* bbase = Ds + (lane >> 4) * LDT + cg * NCBW * 16 + (lane & 15);
+#pragma unroll
+      for (int cb2 = 0; cb2 < NCBW; ++cb2) bq[0][cb2] = bbase[cb2 * 16];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        if (ks + 1 < KS) {
+#pragma unroll
+          for (int cb2 = 0; cb2 < NCBW; ++cb2)
+            bq[(ks + 1) & 1][cb2] = bbase[(ks + 1) * 4 * LDT + cb2 * 16];
+        }
+#pragma unroll
+        for (int cb2 = 0; cb2 < NCBW; ++cb2)
+          acc[cb2] = __builtin_amdgcn_mfma_f64_16x16x4f64(wreg[r][ks], bq[ks & 1][cb2], acc[cb2],
+                                                          0, 0, 0);
+      }
+      // instruction order for the scheduler: the first B reads, then per
+      // k-step the next step's B reads (0x100: LDS read) ahead of this
+      // step's MFMAs (0x008)
+      __builtin_amdgcn_sched_group_barrier(0x100, NCBW, 0);
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        if (ks + 1 < KS) __builtin_amdgcn_sched_group_barrier(0x100, NCBW, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, NCBW, 0);
+      }
+      const int Gs = g_stride(Nb);  // row stride of G
+      double* __restrict__ Grow = G + (int64_t)Ka * NO * Gs;
+#pragma unroll
+      for (int cb2 = 0; cb2 < NCBW; ++cb2) {
+        const int cl = (cg * NCBW + cb2) * 16 + (lane & 15);  // column in the tile
+        const int Kc = Kb0 + cl;
+        // gfx950 FP64 16x16x4 output layout: register v of lane l is row
+        // l/16 + 4v, column l%16 of the 16x16 block
+        if (rb == NRB - 1) {
+          // the last block's rows 16 - NACT + k: the diagonal pairs, summed
+          // into sigma with weights n_k(Ka) + n_k(Kb), lanes l/16 in a fixed order
+          const uint32_t sa = (uint32_t)ldc(I.strA + Ka), sb = occB[cl];
+          double pd = 0.0;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int k = (lane >> 4) + 4 * v - (16 - NACT);
+            if (k >= 0) pd += (double)(((sa >> k) & 1) + ((sb >> k) & 1)) * acc[cb2][v];
+          }
+          pd += __shfl_xor(pd, 16, 64);
+          pd += __shfl_xor(pd, 32, 64);
+          if ((lane >> 4) == 0 && Kc < Nb)
+            Sarena[(int64_t)vs * ntot + I.off + (int64_t)Ka * Nb + Kc] = pd;
+        }
+        if (Kc < Gs) {  // the row's padding too (zero: D+ is zero there), whole lines
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = rb * 16 + (lane >> 4) + 4 * v;
+            if (row < NO) Grow[row * Gs + Kc] = acc[cb2][v];
+          }
+        }
+      }
+    }
+    // No barrier here: the next tile's Cr stores follow this tile's second
+    // barrier (every D+ read of Cr is done), and its D+ stores follow the
+    // next first barrier (every MFMA read of Ds is done).
+  }
+}
+
+// The contraction for active spaces of more than kFoldMax orbitals: G holds
+// every pair row, [Ka][pair_index][Kb], diagonal pairs included, and the
+// gather adds all links.  Their workgroups (512 and 1024 threads) have no
+// register room for the diagonal epilogue of k_sigma_dgemm (measured: 3
+// instead of 4 waves per SIMD at 11-12 orbitals, spills at 14), so they keep
+// this layout.  Same tiles, D+ build and MFMA order as k_sigma_dgemm.
+template <int NACT, int TN, int NT = dgemm_threads(NACT)>
+__global__ void __launch_bounds__(NT, dgemm_reg_entries(NACT, TN, NT) ? 4 : 1) k_sigma_dgemm_pairrows(
     const Item* __restrict__ items, const Work* __restrict__ work,
     const double* __restrict__ warena, const double* __restrict__ V, int64_t ntot,
     double* __restrict__ Garena, const DavState* __restrict__ st, int slot) {
@@ -642,6 +937,7 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm_flat(const Item* __restrict
                                                           const double* __restrict__ V,
                                                           int64_t ntot,
                                                           double* __restrict__ Garena,
+                                                          double* __restrict__ Sarena,
                                                           const DavState* __restrict__ st,
                                                           int slot) {
   static_assert(NACT <= 9, "flattened tiles stage the whole beta pair table");
@@ -658,6 +954,8 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm_flat(const Item* __restrict
   constexpr int CMAX = (int)binom_c(NACT, NACT / 2);
   constexpr int CRMAX = TN + 2 * CMAX;                 // c rows a tile can touch
   constexpr int CPT = (CRMAX + 255) / 256;
+  constexpr int NO = NP - NACT;  // off-diagonal pairs: the rows of G
+  static_assert(NACT <= kFoldMax, "flattened tiles sum the diagonal part themselves");
   __shared__ double Ds[KR * LDT];
   __shared__ int32_t Tb[NP * CMAX];  // beta pair table [pair][Kb]
   __shared__ double Cr[CRMAX];       // c rows Ka_lo .. Ka_hi of the tile
@@ -683,10 +981,10 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm_flat(const Item* __restrict
 #pragma unroll
   for (int r = 0; r < RBW; ++r) {
     const int rb = wrot + 4 * r;
+    const int wr = rb < NRB ? out_row_pair(rb * 16 + (lane & 15), NACT, KPAD) : -1;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
-      wreg[r][ks] = (rb < NRB) ? ldg(W + (rb * 16 + (lane & 15)) * KPAD + ks * 4 + (lane >> 4))
-                               : 0.0;
+      wreg[r][ks] = wr >= 0 ? ldg(W + wr * KPAD + ks * 4 + (lane >> 4)) : 0.0;
   }
   for (int x = t; x < NP * Nb; x += 256) Tb[x] = ldg(pB + x);
   for (int x = NP * LDT + t; x < KR * LDT; x += 256) Ds[x] = 0.0;
@@ -798,13 +1096,26 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm_flat(const Item* __restrict
 #pragma unroll
       for (int cb2 = 0; cb2 < NCB; ++cb2) {
         const int Kc = tile * TN + cb2 * 16 + (lane & 15);
+        const int Kq = Kc < nd ? Kc : nd - 1;
+        const int kac = Kq / Nb, kbc = Kq - kac * Nb;
+        if (rb == NRB - 1) {  // the diagonal pairs' part of sigma, as in k_sigma_dgemm
+          const uint32_t sa = (uint32_t)ldg(I.strA + kac), sb = (uint32_t)ldg(I.strB + kbc);
+          double pd = 0.0;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int k = (lane >> 4) + 4 * v - (16 - NACT);
+            if (k >= 0) pd += (double)(((sa >> k) & 1) + ((sb >> k) & 1)) * acc[cb2][v];
+          }
+          pd += __shfl_xor(pd, 16, 64);
+          pd += __shfl_xor(pd, 32, 64);
+          if ((lane >> 4) == 0 && Kc < nd) Sarena[(int64_t)vs * ntot + I.off + Kc] = pd;
+        }
         if (Kc < nd) {
-          const int kac = Kc / Nb, kbc = Kc - kac * Nb;
-          double* __restrict__ Grow = G + (int64_t)kac * NP * g_stride(Nb) + kbc;
+          double* __restrict__ Grow = G + (int64_t)kac * NO * g_stride(Nb) + kbc;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int row = rb * 16 + (lane >> 4) + 4 * v;
-            if (row < NP) Grow[row * g_stride(Nb)] = acc[cb2][v];
+            if (row < NO) Grow[row * g_stride(Nb)] = acc[cb2][v];
           }
         }
       }
@@ -815,7 +1126,11 @@ __global__ void __launch_bounds__(256) k_sigma_dgemm_flat(const Item* __restrict
   }
 }
 
-// sigma_I = sum_{links (x,y,J,s) of Ia} s G_xy[J, Ib] + sum_{links of Ib} s G_xy[Ia, J]
+// sigma_I = sum_{links (x,y,J,s) of Ia} s G_xy[J, Ib] + sum_{links of Ib} s G_xy[Ia, J].
+// Up to kFoldMax orbitals the contraction wrote the diagonal links' part to
+// sigma beforehand, G holds the off-diagonal rows and this adds the
+// off-diagonal links (their entries carry G's row offdiag_index(x, y));
+// above, it sums every link over G's pair_index rows.
 // One wave per 64-determinant segment of one alpha row (segments are
 // row-aligned), so the alpha string and its links are wave-uniform (scalar
 // loads) and the alpha-part reads of G are coalesced rows.  Work units run
@@ -842,10 +1157,13 @@ __global__ void __launch_bounds__(256) k_sigma_gather(const Item* __restrict__ i
   const int Gs = g_stride(Nb);  // row stride of G
   const int La = I.La, Lb = I.Lb;
   double acc0 = 0.0, acc1 = 0.0;
-  const int np = I.npair;
+  // up to kFoldMax orbitals the contraction summed the diagonal links' part
+  // and G holds the off-diagonal rows; otherwise G holds every pair row
+  const bool fold = I.n <= kFoldMax;
+  const int np = fold ? I.npair - I.n : I.npair;  // rows of G per alpha string
   const uint32_t* __restrict__ la = I.linkA + Ka * La;
   const double* __restrict__ Gcol = G + Kb;  // G[(Ja * npair + pair) * Gs + Kb]
-  int l = 0;
+  int l = fold ? I.na : 0;  // the first na links are the diagonal ones
   for (; l + 3 < La; l += 4) {
     const uint32_t e0 = ldc(la + l), e1 = ldc(la + l + 1), e2 = ldc(la + l + 2), e3 = ldc(la + l + 3);
     const double g0 = ldg(Gcol + (int64_t)(link_addr(e0) * np + link_pair(e0)) * Gs);
@@ -859,10 +1177,11 @@ __global__ void __launch_bounds__(256) k_sigma_gather(const Item* __restrict__ i
     const uint32_t e0 = ldc(la + l);
     acc0 += link_sign(e0) * ldg(Gcol + (int64_t)(link_addr(e0) * np + link_pair(e0)) * Gs);
   }
+  const int Lo = fold ? Lb - I.nb : Lb;  // the links held in linkBT
   const uint32_t* __restrict__ lb = I.linkBT + Kb;               // link l of Kb: lb[l * Nb]
   const double* __restrict__ Grow = G + (int64_t)Ka * np * Gs;  // G[(Ka * npair + pair) * Gs + Jb]
   l = 0;
-  for (; l + 3 < Lb; l += 4) {
+  for (; l + 3 < Lo; l += 4) {
     const uint32_t e0 = ldg(lb + l * Nb), e1 = ldg(lb + (l + 1) * Nb), e2 = ldg(lb + (l + 2) * Nb),
                    e3 = ldg(lb + (l + 3) * Nb);
     const double g0 = ldg(Grow + link_pair(e0) * Gs + link_addr(e0));
@@ -872,11 +1191,13 @@ __global__ void __launch_bounds__(256) k_sigma_gather(const Item* __restrict__ i
     acc0 += link_sign(e0) * g0 + link_sign(e2) * g2;
     acc1 += link_sign(e1) * g1 + link_sign(e3) * g3;
   }
-  for (; l < Lb; ++l) {
+  for (; l < Lo; ++l) {
     const uint32_t e0 = ldg(lb + l * Nb);
     acc0 += link_sign(e0) * ldg(Grow + link_pair(e0) * Gs + link_addr(e0));
   }
-  Sarena[(int64_t)vs * ntot + I.off + (int64_t)Ka * Nb + Kb] = acc0 + acc1;
+  double* __restrict__ out = Sarena + (int64_t)vs * ntot + I.off + (int64_t)Ka * Nb + Kb;
+  if (fold) *out += acc0 + acc1;
+  else *out = acc0 + acc1;
 }
 
 // ------------------------------------------------------ input validation
@@ -3293,33 +3614,37 @@ void launch_hdiag(const Item* items, const Work* work, int nwork, const ItemHam*
 
 template <int NACT, int TN>
 static void sigma_dgemm_t(const Item* items, const Work* work, int nwork, const double* warena,
-                          const double* V, int64_t ntot, double* G, const DavState* st, int slot,
-                          hipStream_t s) {
-  hipLaunchKernelGGL((k_sigma_dgemm<NACT, TN>), dim3(nwork), dim3(dgemm_threads(NACT)), 0, s, items,
-                     work, warena, V, ntot, G, st, slot);
+                          const double* V, int64_t ntot, double* G, double* Sv,
+                          const DavState* st, int slot, hipStream_t s) {
+  if constexpr (NACT > kFoldMax)
+    hipLaunchKernelGGL((k_sigma_dgemm_pairrows<NACT, TN>), dim3(nwork), dim3(dgemm_threads(NACT)),
+                       0, s, items, work, warena, V, ntot, G, st, slot);
+  else
+    hipLaunchKernelGGL((k_sigma_dgemm<NACT, TN>), dim3(nwork), dim3(dgemm_threads(NACT)), 0, s,
+                       items, work, warena, V, ntot, G, Sv, st, slot);
 }
 
 template <int TN>
 static bool sigma_dgemm_n(int n, const Item* items, const Work* work, int nwork,
                           const double* warena, const double* V, int64_t ntot, double* G,
-                          const DavState* st, int slot, hipStream_t s) {
+                          double* Sv, const DavState* st, int slot, hipStream_t s) {
   switch (n) {
 #define MBEFCI_CASE(N) \
-  case N: sigma_dgemm_t<N, TN>(items, work, nwork, warena, V, ntot, G, st, slot, s); return true;
+  case N: sigma_dgemm_t<N, TN>(items, work, nwork, warena, V, ntot, G, Sv, st, slot, s); return true;
     MBEFCI_CASE(2) MBEFCI_CASE(3) MBEFCI_CASE(4) MBEFCI_CASE(5) MBEFCI_CASE(6) MBEFCI_CASE(7)
     MBEFCI_CASE(10) MBEFCI_CASE(11) MBEFCI_CASE(12)
 #undef MBEFCI_CASE
     case 8:  // three-wave workgroups: up to 64 columns
-      if constexpr (TN <= 64) { sigma_dgemm_t<8, TN>(items, work, nwork, warena, V, ntot, G, st, slot, s); return true; }
+      if constexpr (TN <= 64) { sigma_dgemm_t<8, TN>(items, work, nwork, warena, V, ntot, G, Sv, st, slot, s); return true; }
       return false;
     case 9:
-      if constexpr (TN <= 64) { sigma_dgemm_t<9, TN>(items, work, nwork, warena, V, ntot, G, st, slot, s); return true; }
+      if constexpr (TN <= 64) { sigma_dgemm_t<9, TN>(items, work, nwork, warena, V, ntot, G, Sv, st, slot, s); return true; }
       return false;
     case 13:
-      if constexpr (TN <= 64) { sigma_dgemm_t<13, TN>(items, work, nwork, warena, V, ntot, G, st, slot, s); return true; }
+      if constexpr (TN <= 64) { sigma_dgemm_t<13, TN>(items, work, nwork, warena, V, ntot, G, Sv, st, slot, s); return true; }
       return false;
     case 14:
-      if constexpr (TN <= 64) { sigma_dgemm_t<14, TN>(items, work, nwork, warena, V, ntot, G, st, slot, s); return true; }
+      if constexpr (TN <= 64) { sigma_dgemm_t<14, TN>(items, work, nwork, warena, V, ntot, G, Sv, st, slot, s); return true; }
       return false;
     default: return false;
   }
@@ -3328,12 +3653,12 @@ static bool sigma_dgemm_n(int n, const Item* items, const Work* work, int nwork,
 template <int TN>
 static bool sigma_dgemm_flat_n(int n, const Item* items, const Work* work, int nwork,
                                const double* warena, const double* V, int64_t ntot, double* G,
-                               const DavState* st, int slot, hipStream_t s) {
+                               double* Sv, const DavState* st, int slot, hipStream_t s) {
   switch (n) {
 #define MBEFCI_CASE(N)                                                                       \
   case N:                                                                                    \
     hipLaunchKernelGGL((k_sigma_dgemm_flat<N, TN>), dim3(nwork), dim3(256), 0, s, items,     \
-                       work, warena, V, ntot, G, st, slot);                                  \
+                       work, warena, V, ntot, G, Sv, st, slot);                              \
     return true;
     MBEFCI_CASE(2) MBEFCI_CASE(3) MBEFCI_CASE(4) MBEFCI_CASE(5) MBEFCI_CASE(6) MBEFCI_CASE(7)
     MBEFCI_CASE(8) MBEFCI_CASE(9)
@@ -3344,18 +3669,18 @@ static bool sigma_dgemm_flat_n(int n, const Item* items, const Work* work, int n
 
 bool launch_sigma_dgemm(int n, int tn, const Item* items, const Work* work, int nwork,
                         const double* warena, const double* V, int64_t ntot, double* G,
-                        const DavState* st, int slot, hipStream_t s) {
+                        double* Sv, const DavState* st, int slot, hipStream_t s) {
   if (nwork <= 0) return true;
   switch (tn) {
-    case -32: return sigma_dgemm_flat_n<32>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
-    case -64: return sigma_dgemm_flat_n<64>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
-    case 32: return sigma_dgemm_n<32>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
-    case 64: return sigma_dgemm_n<64>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
+    case -32: return sigma_dgemm_flat_n<32>(n, items, work, nwork, warena, V, ntot, G, Sv, st, slot, s);
+    case -64: return sigma_dgemm_flat_n<64>(n, items, work, nwork, warena, V, ntot, G, Sv, st, slot, s);
+    case 32: return sigma_dgemm_n<32>(n, items, work, nwork, warena, V, ntot, G, Sv, st, slot, s);
+    case 64: return sigma_dgemm_n<64>(n, items, work, nwork, warena, V, ntot, G, Sv, st, slot, s);
     case 128:
       // not compiled for n >= 13 (more LDS than one CU holds) nor for the
       // three-wave workgroups of n = 8, 9: the work units must not be built
       // for it (the caller maps such a schedule to 64 columns)
-      return sigma_dgemm_n<128>(n, items, work, nwork, warena, V, ntot, G, st, slot, s);
+      return sigma_dgemm_n<128>(n, items, work, nwork, warena, V, ntot, G, Sv, st, slot, s);
     default: return false;
   }
 }

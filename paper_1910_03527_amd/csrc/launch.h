@@ -22,10 +22,13 @@ void launch_casci_setup(int n, const double* const* h1s, const double* const* er
 void launch_hdiag(const Item* items, const Work* work, int nwork, const ItemHam* hams,
                   double* diag, hipStream_t s);
 // tn: 32, 64 or 128 columns of one alpha string per tile; -32 or -64: flattened
-// tiles of that many consecutive determinants (active spaces of at most 9)
+// tiles of that many consecutive determinants (active spaces of at most 9).
+// Up to kFoldMax orbitals it also writes the diagonal pairs' part of sigma to
+// Sv (the slot of the vector it reads from V), to which launch_sigma_gather
+// then adds the off-diagonal links.
 bool launch_sigma_dgemm(int n, int tn, const Item* items, const Work* work, int nwork,
                         const double* warena, const double* V, int64_t ntot, double* G,
-                        const DavState* st, int slot, hipStream_t s);
+                        double* Sv, const DavState* st, int slot, hipStream_t s);
 // lds: bytes of LDS reserved per workgroup (the kernel uses none), a cap on
 // the workgroups per CU: see gather_lds_bytes
 void launch_sigma_gather(const Item* items, const Work* work, int nwork, const double* G,

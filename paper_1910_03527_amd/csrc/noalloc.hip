@@ -212,7 +212,8 @@ int noalloc_sigma(int device, int n, int na, int nb, const double* h1, const dou
   launch_casci_setup(n, hptr, gptr, ecore, items, 1, hams, W, s);
   if (I.ndet > 1) {
     // the caller's vectors stand in for slot 0 of the solver arenas
-    if (!launch_sigma_dgemm(n, kNoallocTile, items, tiles, L.ntiles, W, c, I.ndet, G, st, 0, s)) {
+    if (!launch_sigma_dgemm(n, kNoallocTile, items, tiles, L.ntiles, W, c, I.ndet, G, sigma, st,
+                            0, s)) {
       *why = "no sigma kernel for n=" + std::to_string(n);
       return MBEFCI_EUNSUPPORTED;
     }

@@ -971,7 +971,7 @@ void sigma_launch(mbefci_ctx* c, Plan& P, const SigmaLaunch& L, int slot) {
   if (L.kind == 0) {
     const Group& g = P.groups[L.group];
     if (!launch_sigma_dgemm(g.n, g.tn, P.d_items, g.d_tiles + L.lo, L.cnt, P.W, P.V, P.ntot, P.G,
-                            P.st, slot, c->stream))
+                            P.S, P.st, slot, c->stream))
       throw Error(MBEFCI_EUNSUPPORTED, "no sigma kernel for n=" + std::to_string(g.n));
   } else if (L.kind == 1) {
     launch_sigma_gather(P.d_items, P.d_segs + L.lo, L.cnt, P.G, P.S, P.ntot, P.st, slot,
@@ -1064,10 +1064,12 @@ void autotune(mbefci_ctx* c, Plan& P) {
         Work* d = arena<Work>(c, "tune_tiles", g.tiles.size());
         upload(c, d, g.tiles);
         const int nw = (int)g.tiles.size();
-        launch_sigma_dgemm(g.n, tn, P.d_items, d, nw, P.W, P.V, P.ntot, P.G, P.st, 0, c->stream);
+        launch_sigma_dgemm(g.n, tn, P.d_items, d, nw, P.W, P.V, P.ntot, P.G, P.S, P.st, 0,
+                           c->stream);
         HIPCHK(hipEventRecord(e0, c->stream));
         for (int r = 0; r < 3; ++r)
-          launch_sigma_dgemm(g.n, tn, P.d_items, d, nw, P.W, P.V, P.ntot, P.G, P.st, 0, c->stream);
+          launch_sigma_dgemm(g.n, tn, P.d_items, d, nw, P.W, P.V, P.ntot, P.G, P.S, P.st, 0,
+                           c->stream);
         HIPCHK(hipEventRecord(e1, c->stream));
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -2519,7 +2521,9 @@ int mbefci_time_kernels(mbefci_ctx* c, int32_t reps, mbefci_kernel_time* out, in
           if (g.tiles[w].begin == 0) nd += (double)P.items[g.tiles[w].item].ndet;
         const double np = g.n * (g.n + 1) / 2;
         flops = 2.0 * np * np * nd;
-        bytes = 8.0 * (1.0 + np) * nd;  // c read once, G written once
+        // c read once, G written once (up to kFoldMax orbitals its off-diagonal
+        // rows, and sigma's diagonal part)
+        bytes = 8.0 * (g.n <= kFoldMax ? 2.0 + np - g.n : 1.0 + np) * nd;
         name = (g.tn < 0 ? "sigma_dgemm_flat<n=" : "sigma_dgemm<n=") + std::to_string(g.n) +
                ",tile=" + std::to_string(g.tn < 0 ? -g.tn : g.tn) + ">";
       } else if (L.kind == 1) {
@@ -2527,7 +2531,9 @@ int mbefci_time_kernels(mbefci_ctx* c, int32_t reps, mbefci_kernel_time* out, in
           if (P.segs[w].begin == 0) {
             const Item& I = P.items[P.segs[w].item];
             nd += (double)I.ndet;
-            bytes += 8.0 * (I.npair + 1.0) * I.ndet;  // G read once, sigma written once
+            // G read once, sigma written (up to kFoldMax orbitals: G's
+            // off-diagonal rows, sigma read and written)
+            bytes += 8.0 * (I.n <= kFoldMax ? I.npair - I.n + 2.0 : I.npair + 1.0) * I.ndet;
           }
         name = "sigma_gather";
       } else if (L.kind == 2) {
