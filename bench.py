@@ -42,6 +42,9 @@ def kernel_source_sha(kernel_name):
     here = os.path.dirname(os.path.abspath(__file__))
     csrc = os.path.join(here, "paper_1910_03527_amd", "csrc")
     fn = "k_" + kernel_name.split("<")[0]
+    m = re.match(r"sigma_dgemm<n=(\d+),", kernel_name)
+    if m and int(m.group(1)) > 10:  # the contraction that keeps every pair row of G
+        fn = "k_sigma_dgemm_pairrows"
     with open(os.path.join(csrc, "kernels.hip")) as fh:
         text = fh.read()
     m = re.search(r"\n(template <[^>]*>\n)?__global__ void (__launch_bounds__\((?:[^()]|\([^()]*\))*\) )?" +
