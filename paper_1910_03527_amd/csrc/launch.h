@@ -37,12 +37,13 @@ void launch_sigma_gather(const Item* items, const Work* work, int nwork, const d
 // The gather's LDS reservation for items whose row block of G (npair rows
 // of the row stride) takes `row_block` bytes.  Each workgroup reads one
 // row block scattered; with many resident workgroups the L2 re-fetches it.
-// Measured (eight workgroups per CU uncapped): blocks of 30-112 KB (9 and
-// 10 orbitals) do best at six per CU, blocks of 1 MB and more (13-14
-// orbitals) at four; blocks below 24 KB are not capped.
+// Measured (eight workgroups per CU uncapped): blocks of 112 KB (10
+// orbitals) do best at six per CU, blocks of 1 MB and more (13-14
+// orbitals) at four; blocks below 64 KB (9 orbitals and fewer) are not
+// capped.  (Sized by all npair rows; up to 10 orbitals G holds npair - n.)
 inline int gather_lds_bytes(int64_t row_block) {
   if (row_block >= ((int64_t)1 << 20)) return 40960;  // four workgroups per CU
-  if (row_block >= 24 * 1024) return 26624;           // six
+  if (row_block >= 64 * 1024) return 26624;           // six
   return 0;
 }
 // point-group blocked sigma (items with a SymInfo): the per-class contraction
