@@ -396,7 +396,9 @@ __device__ inline bool item_active(const DavState& st, int slot) {
 // the c row of Ka is staged in LDS.  The alpha half of a D+ entry is
 // wave-uniform: a scalar pair-table load and a coalesced row segment of c.
 // D+ [pair][TN] (B operand) is staged in LDS, the wave's W rows (A operand)
-// sit in registers.  G is stored [Ka][pair][Kb], rows g_stride(Nb) long.
+// sit in registers.  G is stored [Ka][row][Kb], rows g_stride(Nb) long: up to
+// kFoldMax orbitals the off-diagonal pairs (row offdiag_index), above every
+// pair (row pair_index, k_sigma_dgemm_pairrows).
 constexpr int64_t binom_c(int n, int k) {
   int64_t r = 1;
   for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
