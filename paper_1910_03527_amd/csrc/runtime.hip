@@ -611,7 +611,8 @@ int64_t build_passes(mbefci_ctx* c, Plan& P) {
     for (int i = 0; i < P.nitem; ++i) {
       Item& I = P.items[i];
       if (I.ndet <= 1 || I.sym) continue;
-      const int64_t gb = (int64_t)I.npair * I.Na * g_stride(I.Nb);
+      // G rows per alpha string: the off-diagonal pairs up to kFoldMax orbitals
+      const int64_t gb = (int64_t)(I.n <= kFoldMax ? I.npair - I.n : I.npair) * I.Na * g_stride(I.Nb);
       if (gpass > 0 && (((gpass + 15) & ~(int64_t)15) + gb) * 8 > cap) close(i);
       gpass = (gpass + 15) & ~(int64_t)15;  // a 128-byte line
       I.goff = gpass;
@@ -722,6 +723,13 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
   P.seg_hi.assign(P.nitem, 0);
   P.nsingle = 0;
   P.ndet_total = 0;
+  // string tables by (n, electrons): a plan's items share few shapes
+  const StringTab* tab_of[kMaxActive + 1][kMaxActive + 1] = {};
+  auto tab = [&](int n, int ne) -> const StringTab& {
+    const StringTab*& t = tab_of[n][ne];
+    if (!t) t = &string_tab(c, n, ne);
+    return *t;
+  };
   for (int i = 0; i < P.nitem; ++i) {
     Item& I = P.items[i];
     if (I.n > 14) throw Error(MBEFCI_EUNSUPPORTED, "active space of " + std::to_string(I.n) +
@@ -744,8 +752,8 @@ void finalize_plan(mbefci_ctx* c, Plan& P, int nguess_slots) {
       if (I.ndet < 1)
         throw Error(MBEFCI_EINVAL, "no determinant of the requested irrep in a CASCI space");
     } else {
-      const StringTab& ta = string_tab(c, I.n, I.na);
-      const StringTab& tb = string_tab(c, I.n, I.nb);
+      const StringTab& ta = tab(I.n, I.na);
+      const StringTab& tb = tab(I.n, I.nb);
       I.Na = (int32_t)ta.N;
       I.Nb = (int32_t)tb.N;
       I.La = ta.L;
