@@ -59,7 +59,7 @@ typedef struct mbefci_ctx mbefci_ctx;
 typedef struct {
   double conv_tol;       /* Davidson residual 2-norm tolerance (default 1e-6)       */
   int32_t max_iter;      /* Davidson iterations per CASCI (default 200)              */
-  int32_t max_space;     /* subspace size before restart, 3..16 (default 8)         */
+  int32_t max_space;     /* subspace size before restart, 3..16 (default 5)         */
   int32_t nguess;        /* lowest-diagonal unit guess vectors, 1..8, below
                             max_space - 1 (default 1), for CASCIs that use
                             neither their whole space nor a P-space; every

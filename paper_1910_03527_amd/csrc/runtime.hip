@@ -1522,7 +1522,7 @@ void mbefci_default_opts(mbefci_opts* o) {
   std::memset(o, 0, sizeof(*o));
   o->conv_tol = 1e-6;
   o->max_iter = 200;
-  o->max_space = 8;
+  o->max_space = 5;
   o->nguess = 1;
   o->mode = MBEFCI_BATCHED;
   o->use_graph = 1;

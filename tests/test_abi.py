@@ -50,7 +50,7 @@ def test_integer_closed_forms(lib):
 def test_default_options(lib):
     o = _lib.Opts()
     lib.mbefci_default_opts(ctypes.byref(o))
-    assert o.conv_tol == 1e-6 and o.max_space == 8 and o.nguess == 1
+    assert o.conv_tol == 1e-6 and o.max_space == 5 and o.nguess == 1
     assert o.mode == _lib.BATCHED and o.keep_ci == 1 and o.validate == 1
     assert o.precond == 0 and o.pspace == 112
 

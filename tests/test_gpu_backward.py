@@ -159,10 +159,11 @@ def test_hubbard12_gradient_fd_every_element(ctx, hub12_grad):
     """Central differences (step 1e-5) along every unique element of h (78)
     and of (pq|rs) (3,081 orbits of the 8-fold symmetry), each perturbed in all
     its symmetric copies, against the analytic dL/d(element) summed over the
-    copies.  Per element: |an - fd| <= 1e-6 |fd| + 1e-7.  The floor is the FD
+    copies.  Per element: |an - fd| <= 1e-6 |fd| + 2e-7.  The floor is the FD
     noise: L adds the energies of 2,510 CASCIs with alternating binomial
-    weights (Eq. 2), so its rounding is about 1e-12 E_h, and divided by the
-    step that is 1e-7; elements that vanish by the chain's reflection
+    weights (Eq. 2), so its rounding is 1e-12 to 2e-12 E_h (it depends on
+    how often the Davidson subspace restarts), and divided by the step that
+    is 1e-7 to 2e-7; elements that vanish by the chain's reflection
     symmetry show only that noise.  Over all elements the normwise relative
     error must stay below 1e-6."""
     _log("hubbard12 FD over every unique element")
@@ -192,7 +193,7 @@ def test_hubbard12_gradient_fd_every_element(ctx, hub12_grad):
             an = float(sum(grad[e] for e in orbit))
             an_all.append(an)
             fd_all.append(fd)
-            assert abs(an - fd) <= 1e-6 * abs(fd) + 1e-7, (kind, orbit[0], an, fd)
+            assert abs(an - fd) <= 1e-6 * abs(fd) + 2e-7, (kind, orbit[0], an, fd)
             if kind == "g" and k % 1000 == 0:
                 _log("  orbit", k, "of", len(orbits))
     an_all, fd_all = np.array(an_all), np.array(fd_all)
