@@ -512,9 +512,9 @@ def main():
         _progress("lattices done")
 
     # the other workload configurations, each warm, in contexts of their own
-    configs = None
+    side = None
     if not args.no_configs:
-        configs = {}
+        side = {}
         # Davidson residual tolerance per expansion: the order sums weight
         # each CASCI energy by binomial factors (up to 528 in E^(3) of the
         # 34-orbital synthetic expansion), so that expansion needs 3e-7 for
@@ -545,7 +545,7 @@ def main():
                     times.append((time.perf_counter() - t0) * 1e3)
                 mc = sorted(times)[2]
                 sc = dict(cctx.last_stats)
-                configs[name] = {"value": round(sc["ntuples"] / (mc / 1e3), 2),
+                side[name] = {"value": round(sc["ntuples"] / (mc / 1e3), 2),
                                  "unit": "CASCI solves/s", "ms": round(mc, 3),
                                  "conv_tol": cctx.opts["conv_tol"],
                                  "timing": "median of 5 warm runs",
@@ -562,11 +562,11 @@ def main():
                         cctx.mbe_backward([1.0] * (1 + cp.max_order))
                         torch.cuda.synchronize()
                         bt.append((time.perf_counter() - t0) * 1e3)
-                    configs[name]["ms_backward"] = round(sorted(bt)[1], 3)
+                    side[name]["ms_backward"] = round(sorted(bt)[1], 3)
                     kc = cctx.time_kernels(2)
-                    configs[name]["kernels"] = _kernel_rows(kc, name)
-                    configs[name]["roofline"] = _roofline(kc, name)
-                    configs[name]["sigma_build"] = _sigma_build(kc, name, peaks["copy_gbps"])
+                    side[name]["kernels"] = _kernel_rows(kc, name)
+                    side[name]["roofline"] = _roofline(kc, name)
+                    side[name]["sigma_build"] = _sigma_build(kc, name, peaks["copy_gbps"])
                     if args.per_launch_steps > 0:
                         # one CASCI per launch sequence, same kernels and tolerance
                         cctx.set_opts(mode=PER_LAUNCH)
@@ -579,7 +579,7 @@ def main():
                         cctx.set_opts(mode=BATCHED)
                         rb = cctx.mbe_forward(ch, cg, cp.occ, cp.ref, cp.exp, cp.max_order,
                                               cp.e_const, want_increments=True)
-                        configs[name]["per_launch"] = {
+                        side[name]["per_launch"] = {
                             "value": round(sc["ntuples"] / (mpl / 1e3), 2),
                             "ms_per_forward": round(mpl, 1),
                             "batched_speedup_forward": round(mpl / mc, 2),
@@ -604,7 +604,7 @@ def main():
             mc = (time.perf_counter() - t0) * 1e3
             sc = dict(cctx.last_stats)
             kc = cctx.time_kernels(2)
-            configs["cas14x8"] = {
+            side["cas14x8"] = {
                 "value": round(8 / (mc / 1e3), 3), "unit": "CASCI solves/s", "ms": round(mc, 1),
                 "step": "forward + RDMs", "ndet_each": 11778624,
                 "sigma_calls": sc["sigma_calls"], "max_iters": sc["max_iters"],
@@ -637,7 +637,7 @@ def main():
             torch.cuda.synchronize()
             mp = (time.perf_counter() - t0) * 1e3
             from paper_1910_03527_amd import sym_ndet
-            configs["cas14x8_d2h"] = {
+            side["cas14x8_d2h"] = {
                 "value": round(8 / (mb / 1e3), 3), "unit": "CASCI solves/s", "ms": round(mb, 1),
                 "step": "forward, irrep A_g, point-group blocked", "orbsym": osym,
                 "ndet_each": sym_ndet(14, 7, 7, osym, 0), "ndet_unblocked": 11778624,
@@ -682,7 +682,7 @@ def main():
         "peaks_measured": {k2: round(v2, 2) for k2, v2 in peaks.items()},
         "screened": screened,
         "lattice": lattice,
-        "configs": configs,
+        "configs": side,
     }
     if cb is not None:
         tl = list(itertools.chain.from_iterable(
