@@ -910,8 +910,11 @@ __global__ void __launch_bounds__(NT, dgemm_reg_entries(NACT, TN, NT) ? 4 : 1) k
           for (int v = 0; v < 4; ++v) {
             // gfx950 FP64 16x16x4 output layout: register v of lane l is
             // row l/16 + 4v, column l%16 of the 16x16 block
+            // non-temporal: at 11-14 orbitals G (a 1-3 MB row block per
+            // alpha string) streams through the caches without reuse before
+            // the gather, and cached stores only evict c and the tables
             const int row = rb * 16 + (lane >> 4) + 4 * v;
-            if (row < NP) Grow[row * Gs + Kc] = acc[cb2][v];
+            if (row < NP) __builtin_nontemporal_store(acc[cb2][v], &Grow[row * Gs + Kc]);
           }
         }
       }
