@@ -3,6 +3,8 @@
 // One translation unit holds every kernel so that the binomial table lives in
 // a single __constant__ object.  Launchers at the bottom are the only symbols
 // the host runtime calls (declared in launch.h).
+#include <type_traits>
+
 #include "common.h"
 #include "launch.h"
 
@@ -380,6 +382,26 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 
 __device__ inline int vec_slot(const DavState& st, int slot) {
   return slot >= 0 ? slot : st.m - 1;
+}
+// f(std::integral_constant<int, M>{}) with M = m for m = 0..8 (returns
+// true), else nothing (returns false): the Davidson passes loop over the
+// subspace vectors with M known at compile time, so the loop unrolls without
+// a branch per vector and a thread issues all of its loads at once.  Larger
+// subspaces take the passes' generic loops.
+template <class F>
+__device__ inline bool with_space(int m, F&& f) {
+  switch (m) {
+    case 0: f(std::integral_constant<int, 0>{}); return true;
+    case 1: f(std::integral_constant<int, 1>{}); return true;
+    case 2: f(std::integral_constant<int, 2>{}); return true;
+    case 3: f(std::integral_constant<int, 3>{}); return true;
+    case 4: f(std::integral_constant<int, 4>{}); return true;
+    case 5: f(std::integral_constant<int, 5>{}); return true;
+    case 6: f(std::integral_constant<int, 6>{}); return true;
+    case 7: f(std::integral_constant<int, 7>{}); return true;
+    case 8: f(std::integral_constant<int, 8>{}); return true;
+    default: return false;
+  }
 }
 __device__ inline bool item_active(const DavState& st, int slot) {
   if (st.conv) return false;
@@ -1657,11 +1679,21 @@ __global__ void __launch_bounds__(256) k_dav_dots(const Item* __restrict__ items
   const int64_t e0 = (int64_t)(wk.begin - I.chunk0) * kChunk;
   const int64_t e1 = min(e0 + kChunk, I.ndet);
   const double* sj = Sv + (int64_t)j * ntot + I.off;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
-    const double s = sj[e];
+  const bool unrolled = with_space(m, [&](auto mc) {
+    constexpr int M = decltype(mc)::value;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+      const double s = sj[e];
 #pragma unroll
-    for (int i = 0; i < kMaxSpace; ++i)
-      if (i < m) acc[i] += V[(int64_t)i * ntot + I.off + e] * s;
+      for (int i = 0; i < M; ++i) acc[i] += V[(int64_t)i * ntot + I.off + e] * s;
+    }
+  });
+  if (!unrolled) {
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+      const double s = sj[e];
+  #pragma unroll
+      for (int i = 0; i < kMaxSpace; ++i)
+        if (i < m) acc[i] += V[(int64_t)i * ntot + I.off + e] * s;
+    }
   }
   block_reduce_store<kMaxSpace>(acc, part + (int64_t)wk.begin * kPart);
 }
@@ -1814,21 +1846,50 @@ __global__ void __launch_bounds__(256) k_dav_collapse(const Item* __restrict__ i
   const double inv = nz > 0.0 ? 1.0 / nz : 0.0;
   const int64_t e0 = (int64_t)(wk.begin - I.chunk0) * kChunk;
   const int64_t e1 = min(e0 + kChunk, I.ndet);
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
-    double x = 0.0, sx = 0.0, xp = 0.0, sxp = 0.0;
-    for (int i = 0; i < S.m; ++i) {
-      const double v = V[(int64_t)i * ntot + I.off + e];
-      const double s = Sv[(int64_t)i * ntot + I.off + e];
-      x += S.y[i] * v;
-      sx += S.y[i] * s;
-      xp += z[i] * v;
-      sxp += z[i] * s;
+  const bool unrolled = with_space(S.m, [&](auto mc) {
+    constexpr int M = decltype(mc)::value;
+    double y[M > 0 ? M : 1], zz[M > 0 ? M : 1];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      y[i] = S.y[i];
+      zz[i] = z[i];
     }
-    V[I.off + e] = x;
-    Sv[I.off + e] = sx;
-    if (nz > 0.0) {
-      V[ntot + I.off + e] = xp * inv;
-      Sv[ntot + I.off + e] = sxp * inv;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+      double x = 0.0, sx = 0.0, xp = 0.0, sxp = 0.0;
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        const double v = V[(int64_t)i * ntot + I.off + e];
+        const double s = Sv[(int64_t)i * ntot + I.off + e];
+        x += y[i] * v;
+        sx += y[i] * s;
+        xp += zz[i] * v;
+        sxp += zz[i] * s;
+      }
+      V[I.off + e] = x;
+      Sv[I.off + e] = sx;
+      if (nz > 0.0) {
+        V[ntot + I.off + e] = xp * inv;
+        Sv[ntot + I.off + e] = sxp * inv;
+      }
+    }
+  });
+  if (!unrolled) {
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+      double x = 0.0, sx = 0.0, xp = 0.0, sxp = 0.0;
+      for (int i = 0; i < S.m; ++i) {
+        const double v = V[(int64_t)i * ntot + I.off + e];
+        const double s = Sv[(int64_t)i * ntot + I.off + e];
+        x += S.y[i] * v;
+        sx += S.y[i] * s;
+        xp += z[i] * v;
+        sxp += z[i] * s;
+      }
+      V[I.off + e] = x;
+      Sv[I.off + e] = sx;
+      if (nz > 0.0) {
+        V[ntot + I.off + e] = xp * inv;
+        Sv[ntot + I.off + e] = sxp * inv;
+      }
     }
   }
 }
@@ -1884,26 +1945,48 @@ __global__ void __launch_bounds__(256) k_dav_residual(const Item* __restrict__ i
   const int64_t e0 = (int64_t)(wk.begin - I.chunk0) * kChunk;
   const int64_t e1 = min(e0 + kChunk, I.ndet);
   double* t_out = V + (int64_t)m * ntot + I.off;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
-    double r = 0.0;
-    double v[kMaxSpace];
+  const bool unrolled = with_space(m, [&](auto mc) {
+    constexpr int M = decltype(mc)::value;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+      double r = 0.0;
+      double v[M > 0 ? M : 1];
 #pragma unroll
-    for (int i = 0; i < kMaxSpace; ++i) {
-      v[i] = 0.0;
-      if (i < m) {
+      for (int i = 0; i < M; ++i) {
         v[i] = V[(int64_t)i * ntot + I.off + e];
         r += y[i] * (Sv[(int64_t)i * ntot + I.off + e] - th * v[i]);
       }
-    }
-    acc[kMaxSpace] += r * r;
-    double den = th - diag[I.off + e];
-    if (fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
-    const double tv = r / den;
-    t_out[e] = tv;
-    acc[kMaxSpace + 1] += tv * tv;
+      acc[kMaxSpace] += r * r;
+      double den = th - diag[I.off + e];
+      if (fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
+      const double tv = r / den;
+      t_out[e] = tv;
+      acc[kMaxSpace + 1] += tv * tv;
 #pragma unroll
-    for (int i = 0; i < kMaxSpace; ++i)
-      if (i < m) acc[i] += v[i] * tv;
+      for (int i = 0; i < M; ++i) acc[i] += v[i] * tv;
+    }
+  });
+  if (!unrolled) {
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+      double r = 0.0;
+      double v[kMaxSpace];
+  #pragma unroll
+      for (int i = 0; i < kMaxSpace; ++i) {
+        v[i] = 0.0;
+        if (i < m) {
+          v[i] = V[(int64_t)i * ntot + I.off + e];
+          r += y[i] * (Sv[(int64_t)i * ntot + I.off + e] - th * v[i]);
+        }
+      }
+      acc[kMaxSpace] += r * r;
+      double den = th - diag[I.off + e];
+      if (fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
+      const double tv = r / den;
+      t_out[e] = tv;
+      acc[kMaxSpace + 1] += tv * tv;
+  #pragma unroll
+      for (int i = 0; i < kMaxSpace; ++i)
+        if (i < m) acc[i] += v[i] * tv;
+    }
   }
   block_reduce_store<kMaxSpace + 2>(acc, part + (int64_t)wk.begin * kPart);
 }
@@ -2090,12 +2173,23 @@ __global__ void __launch_bounds__(256) k_dav_orth(const Item* __restrict__ items
     const int64_t e0 = (int64_t)(wk.begin - I.chunk0) * kChunk;
     const int64_t e1 = min(e0 + kChunk, I.ndet);
     double* t = V + (int64_t)m * ntot + I.off;
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
-      double tv = t[e];
+    const bool unrolled = with_space(m, [&](auto mc) {
+      constexpr int M = decltype(mc)::value;
+      for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+        double tv = t[e];
 #pragma unroll
-      for (int i = 0; i < kMaxSpace; ++i)
-        if (i < m) tv -= cf[i] * V[(int64_t)i * ntot + I.off + e];
-      t[e] = tv * inv;
+        for (int i = 0; i < M; ++i) tv -= cf[i] * V[(int64_t)i * ntot + I.off + e];
+        t[e] = tv * inv;
+      }
+    });
+    if (!unrolled) {
+      for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+        double tv = t[e];
+  #pragma unroll
+        for (int i = 0; i < kMaxSpace; ++i)
+          if (i < m) tv -= cf[i] * V[(int64_t)i * ntot + I.off + e];
+        t[e] = tv * inv;
+      }
     }
     return;
   }
@@ -2105,22 +2199,40 @@ __global__ void __launch_bounds__(256) k_dav_orth(const Item* __restrict__ items
   const int64_t e0 = (int64_t)(wk.begin - I.chunk0) * kChunk;
   const int64_t e1 = min(e0 + kChunk, I.ndet);
   double* t = V + (int64_t)m * ntot + I.off;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
-    double v[kMaxSpace];
-    double tv = t[e];
+  const bool unrolled = with_space(m, [&](auto mc) {
+    constexpr int M = decltype(mc)::value;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+      double v[M > 0 ? M : 1];
+      double tv = t[e];
 #pragma unroll
-    for (int i = 0; i < kMaxSpace; ++i) {
-      v[i] = 0.0;
-      if (i < m) {
+      for (int i = 0; i < M; ++i) {
         v[i] = V[(int64_t)i * ntot + I.off + e];
         tv -= cf[i] * v[i];
       }
-    }
-    t[e] = tv;
+      t[e] = tv;
 #pragma unroll
-    for (int i = 0; i < kMaxSpace; ++i)
-      if (i < m) acc[i] += v[i] * tv;
-    acc[kMaxSpace] += tv * tv;
+      for (int i = 0; i < M; ++i) acc[i] += v[i] * tv;
+      acc[kMaxSpace] += tv * tv;
+    }
+  });
+  if (!unrolled) {
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+      double v[kMaxSpace];
+      double tv = t[e];
+  #pragma unroll
+      for (int i = 0; i < kMaxSpace; ++i) {
+        v[i] = 0.0;
+        if (i < m) {
+          v[i] = V[(int64_t)i * ntot + I.off + e];
+          tv -= cf[i] * v[i];
+        }
+      }
+      t[e] = tv;
+  #pragma unroll
+      for (int i = 0; i < kMaxSpace; ++i)
+        if (i < m) acc[i] += v[i] * tv;
+      acc[kMaxSpace] += tv * tv;
+    }
   }
   block_reduce_store<kMaxSpace + 1>(acc, part + (int64_t)wk.begin * kPart);
 }
@@ -2167,12 +2279,23 @@ __global__ void __launch_bounds__(256) k_dav_orth2(const Item* __restrict__ item
   const int64_t e0 = (int64_t)(wk.begin - I.chunk0) * kChunk;
   const int64_t e1 = min(e0 + kChunk, I.ndet);
   double* t = V + (int64_t)m * ntot + I.off;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
-    double tv = t[e];
+  const bool unrolled = with_space(m, [&](auto mc) {
+    constexpr int M = decltype(mc)::value;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+      double tv = t[e];
 #pragma unroll
-    for (int i = 0; i < kMaxSpace; ++i)
-      if (i < m) tv -= cf[i] * V[(int64_t)i * ntot + I.off + e];
-    t[e] = tv * inv;
+      for (int i = 0; i < M; ++i) tv -= cf[i] * V[(int64_t)i * ntot + I.off + e];
+      t[e] = tv * inv;
+    }
+  });
+  if (!unrolled) {
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+      double tv = t[e];
+  #pragma unroll
+      for (int i = 0; i < kMaxSpace; ++i)
+        if (i < m) tv -= cf[i] * V[(int64_t)i * ntot + I.off + e];
+      t[e] = tv * inv;
+    }
   }
 }
 __global__ void k_dav_grow(DavState* st, int ibase, int nitem) {
